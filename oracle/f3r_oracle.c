@@ -712,7 +712,7 @@ static void richardson(or_handle* h, int d, const double* vin, double* out) {
   int64_t cn = h->cntr[d];
   int32_t c = h->p.c;
   if (cn == 1) /* the first call: omega_1 = ... = omega_m = 1 */
-    for (int k = 0; k < L->m; k++) om[k] = h->p.omega_init;
+    for (int k = 0; k < L->m; k++) om[k] = RND(q, h->p.omega_init);
   for (int64_t i = 0; i < n; i++) v[i] = RND(p, vin[i]);
   for (int64_t i = 0; i < n; i++) z[i] = 0.0; /* z_0 = 0 */
   for (int k = 0; k < L->m; k++) {
@@ -885,7 +885,10 @@ void or_get_weights(const or_handle* h, int32_t d, double* omega,
 void or_set_weights(or_handle* h, int32_t d, const double* omega,
                     int64_t cntr) {
   if (d < 0 || d >= OR_MAX_LEV) return;
-  for (int k = 0; k < h->p.lev[d].m && k < 64; k++) h->omega[d][k] = omega[k];
+  /* the weights are quantities of the level arithmetic (fp32 for narrow
+     levels, Sec. 4.3) */
+  for (int k = 0; k < h->p.lev[d].m && k < 64; k++)
+    h->omega[d][k] = RND(h->p.lev[d].pacc, omega[k]);
   h->cntr[d] = cntr;
 }
 int64_t or_history(const or_handle* h, double* buf, int64_t cap) {
