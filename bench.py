@@ -1,0 +1,226 @@
+#!/usr/bin/env python3
+"""Benchmark of the F3R hot path on one MI355X.
+
+Workload: the 3D 7-point Poisson system on a 128^3 grid (n = 2,097,152,
+nnz = 14,581,760), x* uniform on [-1, 1] from a seeded SplitMix64 stream,
+b = A x*, tolerance 1e-10 on the fp64 relative residual.  One step is one
+fp16-F3R solve (F100, F8, F4, R2, M; c = 64) from x0 = 0 to the tolerance
+with b already in HBM; set-up (scaling, level copies, M, device format) is
+timed once and reported beside it.  The same GPU also runs fp64
+FGMRES(64)+M, fp32-F3R and fp64-F3R for the comparison the metric names.
+
+Prints one JSON line.  --gpus above 1 is refused: this build runs on one GPU.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import statistics
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "F3R time-to-1e-10 residual vs fp64 FGMRES (s, same GPU); SpMV HBM GB/s"
+HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def algorithmic_bytes(A, idx_bits: int):
+    """Bytes each probed kernel must move per launch (the data structure it
+    reads once and the vectors it reads/writes once), fp16 level storage."""
+    n = A.n
+    nnz = A.nnz
+    rows = np.repeat(np.arange(n), np.diff(A.row_ptr))
+    nl = int(np.count_nonzero(A.col_idx < rows))
+    nu = int(np.count_nonzero(A.col_idx > rows))
+    sv, si = 2, idx_bits // 8
+    off = n / 16.0  # one 4-byte slice offset per 64 rows
+    return {
+        # W sweep: kd (2n), lower entries, input (fp32 basis at k=1, fp16 r
+        # at k=2: 3n on average), t written (2n)
+        "m_lower": 7 * n + (sv + si) * nl + off,
+        # G sweep + update: kd, upper entries, t (2n), z written (2n), z_prev
+        # read at k=2 only (n on average)
+        "m_upper": 7 * n + (sv + si) * nu + off,
+        # r = v - A z: all entries, z (2n), fp32 basis (4n), r written (2n)
+        "r_residual": 8 * n + (sv + si) * nnz + off,
+        # level-2 SpMV + dots: all entries, z (2n), w written (4n), 2.5 fp32
+        # basis vectors on average (10n)
+        "spmv_l2": 16 * n + (sv + si) * nnz + off,
+    }
+
+
+def timed_solves(fn, steps, warmup):
+    import torch
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    out = None
+    times = []
+    t_all = time.perf_counter()
+    for _ in range(steps):
+        t = time.perf_counter()
+        out = fn()
+        torch.cuda.synchronize()
+        times.append(time.perf_counter() - t)
+    torch.cuda.synchronize()
+    total = time.perf_counter() - t_all
+    return out, times, total
+
+
+def cpu_baseline(A, b, outer_iters_gpu, outer_sample):
+    import oracle as O
+    o = O.Oracle(A.row_ptr, A.col_idx, A.val, O.default_params(O.FP16_F3R))
+    p = O.default_params(O.FP16_F3R)
+    p.max_outer = outer_sample
+    o2 = O.Oracle(A.row_ptr, A.col_idx, A.val, p)
+    o.close()
+    t = time.perf_counter()
+    _, info = o2.solve(b, 1e-10)
+    dt = time.perf_counter() - t
+    per_outer = dt / max(info.outer_iters, 1)
+    return {
+        "value": per_outer * outer_iters_gpu,
+        "unit": "s",
+        "cores": 1,
+        "kind": "oracle",
+        "sample": (f"{info.outer_iters} outermost iteration(s) ({info.m_calls} M applications) of the "
+                   f"single-threaded C oracle's fp16-F3R on this workload took {dt:.2f} s; scaled by "
+                   f"the {outer_iters_gpu} outermost iterations the GPU solve needed"),
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--grid", type=int, default=128, help="Poisson grid side (128 = the workload)")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-outer", type=int, default=1)
+    ap.add_argument("--only-f3r", action="store_true", help="time the fp16-F3R solves only (profiling)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU; --gpus {args.gpus} is not supported by this build "
+              "(the solver is single-GPU; see the design notes for how it would shard)",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    import paper_2505_20719_amd as P
+    import workloads as W
+
+    torch.cuda.set_device(0)
+    N = args.grid
+    A = W.poisson3d(N)
+    name = f"poisson3d_{N}"
+    xs, b = W.rhs(A, name)
+    bt = torch.as_tensor(b, device="cuda")
+    log(f"[bench] {name} n={A.n} nnz={A.nnz}")
+
+    t = time.perf_counter()
+    s16 = P.Solver(A.row_ptr, A.col_idx, A.val, P.params_default(P.VARIANT_FP16))
+    torch.cuda.synchronize()
+    setup_s = time.perf_counter() - t
+
+    (x16, info16), times, total = timed_solves(lambda: s16.solve(bt, tol=1e-10), args.steps, args.warmup)
+    assert info16.status == 0, info16.as_dict()
+    mean_s = total / args.steps
+    log(f"[bench] fp16-F3R: {mean_s * 1e3:.2f} ms/solve, outer={info16.outer_iters}, "
+        f"relres={info16.relres_true:.3e}, graphs={info16.graph_launches}")
+    xh = x16.cpu().numpy()
+    err_xstar = float(np.linalg.norm(xh - xs) / np.linalg.norm(xs))
+
+    result_cfg = {
+        "workload": f"{name}: 3D 7-point Poisson {N}^3 (n={A.n}, nnz={A.nnz}), x* ~ U[-1,1] seeded, b = A x*",
+        "tol": 1e-10,
+        "solver": "fp16-F3R (F100, F8, F4, R2, M), c=64, M = two-SpMV truncated SGS inverse",
+        "setup_s": round(setup_s, 4),
+        "f3r_fp16_median_s": round(statistics.median(times), 6),
+        "f3r_fp16_outer_iters": info16.outer_iters,
+        "f3r_fp16_m_calls": info16.m_calls,
+        "relres_true": info16.relres_true,
+        "err_vs_xstar": err_xstar,
+        "device_format": f"SELL-64, {info16.idx_bits}-bit column indices",
+    }
+
+    if not args.only_f3r:
+        (xf, infof), tf, totf = timed_solves(lambda: s16.fgmres_solve(bt, tol=1e-10, m=64),
+                                             max(1, min(args.steps, 3)), 1)
+        assert infof.status == 0, infof.as_dict()
+        fg_s = totf / max(1, min(args.steps, 3))
+        log(f"[bench] fp64 FGMRES(64): {fg_s * 1e3:.2f} ms/solve, iters={infof.outer_iters}")
+        result_cfg.update({"fgmres64_s": round(fg_s, 6), "fgmres64_iters": infof.outer_iters,
+                           "speedup_vs_fgmres64": round(fg_s / mean_s, 3)})
+        for variant, key in ((P.VARIANT_FP32, "fp32"), (P.VARIANT_FP64, "fp64")):
+            s = P.Solver(A.row_ptr, A.col_idx, A.val, P.params_default(variant))
+            (_, iv), tv, totv = timed_solves(lambda: s.solve(bt, tol=1e-10), 2, 1)
+            assert iv.status == 0, iv.as_dict()
+            result_cfg[f"f3r_{key}_s"] = round(totv / 2, 6)
+            result_cfg[f"f3r_{key}_outer_iters"] = iv.outer_iters
+            log(f"[bench] {key}-F3R: {totv / 2 * 1e3:.2f} ms/solve, outer={iv.outer_iters}")
+            s.close()
+        result_cfg["speedup_fp16_vs_fp64_f3r"] = round(result_cfg["f3r_fp64_s"] / mean_s, 3)
+
+    # live per-kernel timing of the hot kernels inside one solve (HIP events
+    # on the solve's stream, direct launches)
+    ab = algorithmic_bytes(A, info16.idx_bits)
+    probes = {"m_lower": P.PROBE_M_LOWER, "m_upper": P.PROBE_M_UPPER,
+              "r_residual": P.PROBE_R_RESIDUAL, "spmv_l2": P.PROBE_SPMV_L2}
+    kern = {}
+    for key, pid in probes.items():
+        ov = P.params_default(P.VARIANT_FP16)
+        ov.probe_kernel = pid
+        _, ip = s16.solve(bt, tol=1e-10, override=ov)
+        avg_ms = ip.probe_ms / max(ip.probe_launches, 1)
+        kern[key] = {"total_ms": ip.probe_ms, "launches": ip.probe_launches, "avg_us": avg_ms * 1e3,
+                     "gbs": ab[key] / (avg_ms * 1e-3) / 1e9}
+        log(f"[bench] probe {key}: {ip.probe_launches} launches, avg {avg_ms * 1e3:.2f} us, "
+            f"{kern[key]['gbs']:.0f} GB/s (algorithmic {ab[key] / 1e6:.1f} MB/launch)")
+    dom = max(kern, key=lambda k: kern[k]["total_ms"])
+    achieved = kern[dom]["gbs"]
+    roofline = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                "bytes_per_launch": int(ab[dom]), "avg_launch_us": round(kern[dom]["avg_us"], 3)}
+    result_cfg["kernels"] = {k: {kk: round(vv, 3) if isinstance(vv, float) else vv for kk, vv in v.items()}
+                             for k, v in kern.items()}
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        log("[bench] CPU oracle sample ...")
+        cpu = cpu_baseline(A, b, info16.outer_iters, args.cpu_outer)
+        log(f"[bench] CPU oracle estimate: {cpu['value']:.1f} s")
+
+    out = {
+        "metric": METRIC,
+        "value": round(mean_s, 6),
+        "unit": "s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(mean_s * 1e3, 4),
+        "higher_is_better": False,
+        "scaling": "strong",
+        "vs_baseline": None,
+        "dtype": "f16/f32/f64",
+        "data": "synthetic",
+        "config": result_cfg,
+        "spmv_gbs": round(achieved, 1),
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,220 @@
+/*
+ * f3r.h -- C ABI of the MI355X (gfx950) F3R solver library, libf3r.so.
+ *
+ * F3R is the nested Krylov solver of "A Nested Krylov Method Using
+ * Half-Precision Arithmetic" (arXiv 2505.20719): in the tuple notation of
+ * Sec. 3, (F_m1, F_m2, F_m3, R_m4, M) with defaults (100, 8, 4, 2) (Sec. 4.2),
+ * three FGMRES levels in fp64, fp32 and fp16-matrix/fp32-vector precision
+ * around a fp16 Richardson level with adaptive weights (Alg. 1, Sec. 4.3)
+ * and a primary preconditioner M (Table 1).  The problem is A x = b with a
+ * square sparse A, x0 = 0, stopping when ||b - A x||_2 / ||b||_2 < tol
+ * (Sec. 1 and Sec. 5).
+ *
+ * Conventions for every entry point:
+ *   - status codes only; nothing is thrown across the ABI;
+ *   - matrices are passed as host CSR (0-based, int32 row pointers and
+ *     column indices, columns sorted and unique within a row, fp64 values);
+ *     f3r_setup copies them, the caller may free its arrays on return;
+ *   - vectors b, x (and the vectors of the f3r_debug_* calls) are DEVICE
+ *     pointers to n doubles on the device that was current at set-up;
+ *   - all work is enqueued on the hipStream_t given at set-up (NULL = the
+ *     default stream); calls return after that stream has drained the work
+ *     they enqueued, because the outermost level checks convergence on the
+ *     host (Sec. 5.2);
+ *   - a handle is not re-entrant: one call at a time per handle.
+ */
+#ifndef F3R_H
+#define F3R_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes ------------------------------------------------------ */
+typedef int32_t f3r_status;
+#define F3R_OK 0
+#define F3R_NOT_CONVERGED 1   /* soft: x holds the best iterate */
+#define F3R_ERR_ARG (-1)      /* bad argument or parameter */
+#define F3R_ERR_MATRIX (-2)   /* not square, unsorted/duplicate columns,
+                                 missing or zero diagonal, non-finite value */
+#define F3R_ERR_RANGE (-3)    /* a scaled value overflows a narrow format */
+#define F3R_ERR_NOMEM (-4)    /* device or pinned host allocation failed */
+#define F3R_ERR_DEVICE (-5)   /* HIP runtime error; code in f3r_info.hip_error */
+#define F3R_ERR_BREAKDOWN (-6) /* non-finite value in the outermost level */
+
+/* ---- precisions and level kinds --------------------------------------- */
+#define F3R_FP64 0
+#define F3R_FP32 1
+#define F3R_FP16 2
+#define F3R_BF16 3
+#define F3R_FGMRES 0
+#define F3R_RICHARDSON 1
+
+/* variants for f3r_params_default (Sec. 5 names) */
+#define F3R_VARIANT_FP16 0     /* fp16-F3R, precisions of Table 1 */
+#define F3R_VARIANT_FP32 1     /* fp32-F3R: every inner level fp32 */
+#define F3R_VARIANT_FP64 2     /* fp64-F3R: every level fp64 */
+#define F3R_VARIANT_FGMRES64 3 /* FGMRES(64)+M, all fp64 (comparison solver) */
+#define F3R_VARIANT_BF16 4     /* fp16-F3R with bfloat16 in place of binary16 */
+
+/* flags */
+#define F3R_USE_X0 1u          /* x holds the initial guess on entry */
+#define F3R_PERSIST_WEIGHTS 2u /* keep omega and c_ntr from the previous solve */
+#define F3R_NO_GRAPH 4u        /* launch kernels one by one, no hipGraph */
+
+/* kernels that f3r_params.probe_kernel can time with HIP events */
+#define F3R_PROBE_NONE 0
+#define F3R_PROBE_M_LOWER 1    /* W sweep of M inside the Richardson level */
+#define F3R_PROBE_M_UPPER 2    /* G sweep of M (with the Richardson update) */
+#define F3R_PROBE_R_RESIDUAL 3 /* Richardson residual SpMV r = v - A z */
+#define F3R_PROBE_SPMV_L2 4    /* SpMV + Gram-Schmidt dots of level 2 */
+#define F3R_PROBE_SPMV_L1 5    /* SpMV + Gram-Schmidt dots of level 1 */
+#define F3R_PROBE_SPMV_L0 6    /* SpMV + Gram-Schmidt dots of level 0 */
+
+#define F3R_MAX_LEVELS 8
+
+typedef struct {
+  int32_t kind;   /* F3R_FGMRES or F3R_RICHARDSON (innermost only) */
+  int32_t m;      /* iterations per invocation (m1..m4 of Sec. 4.2) */
+  int32_t prec_a; /* storage precision of the level's matrix */
+  int32_t prec_v; /* storage precision of the level's vectors; arithmetic is
+                     fp64 when this is fp64 and fp32 otherwise (Table 1) */
+} f3r_level;
+
+typedef struct {
+  int32_t nlev;                  /* number of solver levels (1..8) */
+  f3r_level lev[F3R_MAX_LEVELS]; /* lev[0] is the outermost FGMRES, fp64 */
+  int32_t prec_m;                /* storage precision of M (Table 1) */
+  int32_t m_identity;            /* 1: M = I */
+  int32_t c;                     /* weight-update cycle of Alg. 1; 0 = never */
+  double alpha;                  /* diagonal factor used to build M (Sec. 5.2) */
+  double omega_init;             /* initial Richardson weights (Alg. 1: 1) */
+  int32_t max_outer;             /* outermost iterations allowed in total */
+  uint32_t flags;                /* F3R_USE_X0 | F3R_PERSIST_WEIGHTS | ... */
+  int32_t poison_call;           /* >0: test hook, NaN in that R call's output */
+  int32_t probe_kernel;          /* F3R_PROBE_*: time every launch of that kernel
+                                    with HIP events on the solve's stream; the
+                                    solve then launches without hipGraphs */
+  int32_t reserved[6];
+} f3r_params;
+
+typedef struct {
+  int64_t n;              /* rows = columns */
+  int64_t nnz;            /* stored entries */
+  const int32_t* row_ptr; /* host, n+1 entries, row_ptr[0] = 0 */
+  const int32_t* col_idx; /* host, nnz entries, sorted and unique per row */
+  const double* val;      /* host, nnz entries */
+} f3r_csr;
+
+typedef struct {
+  int32_t status;        /* same as the return value */
+  int32_t outer_iters;   /* outermost iterations done */
+  int32_t restarts;      /* outermost cycles that ended without convergence */
+  int32_t hip_error;     /* hipError_t of the failing call, for F3R_ERR_DEVICE */
+  int64_t m_calls;       /* applications of M */
+  int64_t r_calls;       /* Richardson invocations scheduled */
+  int64_t spmv[F3R_MAX_LEVELS]; /* SpMVs with each level's matrix */
+  int64_t fallbacks;     /* inner outputs replaced by the input (non-finite) */
+  int64_t breakdowns;    /* exact zero subdiagonal met in a level */
+  double relres_est;     /* last Givens estimate |g_{j+1}| / ||b|| */
+  double relres_true;    /* ||b - A x|| / ||b|| at exit, fp64 */
+  double setup_ms;       /* wall time of f3r_setup */
+  double solve_ms;       /* wall time of the solve */
+  int64_t graph_launches; /* F2-call graphs replayed */
+  int32_t idx_bits;      /* 16 or 32: column index width of the device format */
+  int32_t sell_c;        /* rows per slice of the device format */
+  double probe_ms;       /* summed duration of the probed kernel's launches */
+  int64_t probe_launches; /* launches of the probed kernel */
+  int64_t padded_nnz;    /* stored entries of the device format incl. padding */
+} f3r_info;
+
+typedef struct f3r_handle f3r_handle;
+
+/* Parameters of a named variant (Sec. 5): fills every field. */
+void f3r_params_default(f3r_params* p, int32_t variant);
+
+/* Copies A to the device, applies symmetric diagonal scaling
+   Ahat = D^-1/2 A D^-1/2 (Sec. 5), rounds the per-level value copies of
+   Table 1 directly from fp64, builds the two factors of M in fp64 and casts
+   them (Secs. 5 and 5.2), converts everything to the device format and
+   allocates every workspace.  hip_stream: a hipStream_t or NULL.
+   Errors: F3R_ERR_ARG (NULL pointers, bad parameters), F3R_ERR_MATRIX,
+   F3R_ERR_RANGE (a narrow copy of Ahat or M would overflow),
+   F3R_ERR_NOMEM, F3R_ERR_DEVICE.  *out is NULL on error. */
+f3r_status f3r_setup(const f3r_csr* A, const f3r_params* p, void* hip_stream,
+                     f3r_handle** out);
+
+/* Solves A x = b with the nest given at set-up (Sec. 4.2): FGMRES(m1) in
+   fp64 on the original A, calling the inner nest as S F2(S v) on the scaled
+   system; convergence is checked on the host after each outermost iteration
+   from the Givens estimate and confirmed with the fp64 true residual at the
+   end of each cycle; the whole nest restarts after m1 iterations (Sec. 4.2).
+   b, x: device pointers (n doubles); x is overwritten (or read first with
+   F3R_USE_X0).  level_override: NULL, or parameters whose nlev, m, c,
+   omega_init, max_outer and flags replace the set-up ones for this call
+   (precisions must equal the set-up ones).  info may be NULL.
+   Returns F3R_OK, F3R_NOT_CONVERGED (x is the last iterate), or an error. */
+f3r_status f3r_solve(f3r_handle* h, const double* b, double* x, double tol,
+                     const f3r_params* level_override, f3r_info* info);
+
+/* Restarted FGMRES(m) preconditioned by M with every value in fp64: the
+   comparison solver of Sec. 5 ("fp64-FGMRES(64)").  Same conventions as
+   f3r_solve; max_iter counts iterations over all restarts. */
+f3r_status f3r_fgmres_solve(f3r_handle* h, const double* b, double* x,
+                            double tol, int32_t m, int32_t max_iter,
+                            f3r_info* info);
+
+/* Relative residual estimate after every outermost iteration of the last
+   solve (level 0 only).  Copies min(cap, available) values to buf (host),
+   *len = available.  Errors: F3R_ERR_ARG. */
+f3r_status f3r_get_history(const f3r_handle* h, int32_t level, double* buf,
+                           int64_t cap, int64_t* len);
+
+/* Richardson state of Alg. 1 for the Richardson level `level`: the weights
+   omega_1..omega_m (host array of m doubles) and the call counter c_ntr.
+   Errors: F3R_ERR_ARG when `level` is not a Richardson level. */
+f3r_status f3r_get_weights(f3r_handle* h, int32_t level, double* omega,
+                           int64_t* c_ntr);
+f3r_status f3r_set_weights(f3r_handle* h, int32_t level, const double* omega,
+                           int64_t c_ntr);
+
+/* Frees every device and host resource of the handle. NULL is allowed. */
+void f3r_destroy(f3r_handle* h);
+
+/* Static English text of a status code. */
+const char* f3r_status_str(f3r_status s);
+
+/* ---- single steps, for lockstep checks against a reference ------------
+   Every vector is a device array of n doubles holding values representable
+   in the precision named; results are widened exactly to fp64. */
+
+/* y = A_d x: level 0 uses the original A in fp64; level d >= 1 the scaled
+   matrix stored in the level's prec_a, with the level's arithmetic, the
+   result rounded to the level's prec_v (Table 1; mixed inputs use the wider
+   arithmetic, Sec. 4.2). */
+f3r_status f3r_debug_spmv(f3r_handle* h, int32_t level, const double* x,
+                          double* y);
+
+/* y = M r with vectors stored in prec (the two-SpMV application of
+   Sec. 5.2; fp32 arithmetic for narrow prec, fp64 for fp64). prec must be
+   the precision of M or wider. */
+f3r_status f3r_debug_apply_m(f3r_handle* h, int32_t prec, const double* r,
+                             double* y);
+
+/* z = level d (1 <= d < nlev) applied to v on the scaled system, with the
+   handle's Richardson state (which it advances). */
+f3r_status f3r_debug_apply_level(f3r_handle* h, int32_t level, const double* v,
+                                 double* z);
+
+/* Host copies of the set-up results in CSR order: the scaling s (n doubles)
+   and the scaled values rounded to prec (nnz doubles). */
+f3r_status f3r_debug_scaling(f3r_handle* h, double* s_host);
+f3r_status f3r_debug_level_values(f3r_handle* h, int32_t prec,
+                                  double* vals_host);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

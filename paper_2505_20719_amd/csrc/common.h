@@ -1,0 +1,121 @@
+// Device-side helpers shared by every kernel of libf3r: storage types,
+// round-to-nearest-even conversions, the XCD-aware block mapping and the
+// deterministic wave/block reductions.
+//
+// The whole library is compiled with floating-point contraction off, so a
+// product followed by a sum is two separately rounded operations, exactly as
+// an IEEE implementation of the level arithmetic of Table 1 spells it.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace f3r {
+
+typedef _Float16 f16;
+struct bf16 {
+  uint16_t u;
+};
+
+// ---- widening (exact) ------------------------------------------------------
+__device__ __forceinline__ float bf16_to_float(bf16 x) { return __uint_as_float((uint32_t)x.u << 16); }
+
+template <class Q> __device__ __forceinline__ Q widen(double x);
+template <class Q> __device__ __forceinline__ Q widen(float x);
+template <class Q> __device__ __forceinline__ Q widen(f16 x);
+template <class Q> __device__ __forceinline__ Q widen(bf16 x);
+template <> __device__ __forceinline__ double widen<double>(double x) { return x; }
+template <> __device__ __forceinline__ double widen<double>(float x) { return (double)x; }
+template <> __device__ __forceinline__ double widen<double>(f16 x) { return (double)(float)x; }
+template <> __device__ __forceinline__ double widen<double>(bf16 x) { return (double)bf16_to_float(x); }
+template <> __device__ __forceinline__ float widen<float>(double x) { return (float)x; }  // only for fp32-exact values
+template <> __device__ __forceinline__ float widen<float>(float x) { return x; }
+template <> __device__ __forceinline__ float widen<float>(f16 x) { return (float)x; }
+template <> __device__ __forceinline__ float widen<float>(bf16 x) { return bf16_to_float(x); }
+
+// ---- rounding to a storage type (RNE) -------------------------------------
+__device__ __forceinline__ bf16 float_to_bf16(float x) {
+  uint32_t u = __float_as_uint(x);
+  if ((u & 0x7fffffffu) > 0x7f800000u) return bf16{(uint16_t)((u >> 16) | 0x40u)};  // quiet NaN
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return bf16{(uint16_t)(u >> 16)};
+}
+
+// fp64 -> fp32 with round-to-odd: truncate toward zero, then force the last
+// bit to 1 when the truncation was inexact.  Followed by a round-to-nearest-
+// even to a format with at most 22 significand bits it gives the correctly
+// rounded result of the direct conversion (24 >= p + 2 for p = 11 and 8).
+__device__ __forceinline__ float f64_to_f32_odd(double x) {
+  float f = (float)x;  // RNE
+  if (fabs((double)f) > fabs(x)) f = __uint_as_float(__float_as_uint(f) - 1u);  // step toward zero
+  if ((double)f != x && !isnan(x)) f = __uint_as_float(__float_as_uint(f) | 1u);
+  return f;
+}
+
+// An fp32 value that the compiler must materialise as such.  Without it the
+// compiler folds "fp32 product, then convert to fp16" into one mixed
+// multiply-add that rounds the exact product straight to fp16, which is not
+// the fp32-arithmetic-then-store rounding the levels are defined with.
+__device__ __forceinline__ float fp32_value(float x) {
+  asm volatile("" : "+v"(x));
+  return x;
+}
+
+template <class T> __device__ __forceinline__ T round_to(float x);
+template <class T> __device__ __forceinline__ T round_to(double x);
+template <> __device__ __forceinline__ float round_to<float>(float x) { return x; }
+template <> __device__ __forceinline__ f16 round_to<f16>(float x) { return (f16)fp32_value(x); }
+template <> __device__ __forceinline__ bf16 round_to<bf16>(float x) { return float_to_bf16(x); }
+template <> __device__ __forceinline__ double round_to<double>(float x) { return (double)x; }
+template <> __device__ __forceinline__ double round_to<double>(double x) { return x; }
+template <> __device__ __forceinline__ float round_to<float>(double x) { return (float)x; }
+template <> __device__ __forceinline__ f16 round_to<f16>(double x) { return (f16)f64_to_f32_odd(x); }
+template <> __device__ __forceinline__ bf16 round_to<bf16>(double x) { return float_to_bf16(f64_to_f32_odd(x)); }
+
+template <class T> __device__ __forceinline__ bool finite_val(T x);
+template <> __device__ __forceinline__ bool finite_val<double>(double x) { return isfinite(x); }
+template <> __device__ __forceinline__ bool finite_val<float>(float x) { return isfinite(x); }
+template <> __device__ __forceinline__ bool finite_val<f16>(f16 x) { return isfinite((float)x); }
+template <> __device__ __forceinline__ bool finite_val<bf16>(bf16 x) { return isfinite(bf16_to_float(x)); }
+
+// ---- launch geometry -------------------------------------------------------
+// Rows are processed in slices of 64 (one row per lane of a wave64), four
+// slices per 256-thread block.  Blocks are dispatched round-robin over the 8
+// XCDs; logical block b of a kernel is placed on XCD b / per so that every
+// row-parallel kernel touches the same rows on the same XCD and the L2 of
+// that XCD keeps the vectors the previous kernel wrote.
+constexpr int kWave = 64;
+constexpr int kBlock = 256;
+constexpr int kRowsPerBlock = kBlock;
+constexpr int kXcd = 8;
+
+__device__ __forceinline__ int64_t logical_block(int64_t nb) {
+  int64_t per = (nb + kXcd - 1) / kXcd;
+  int64_t b = blockIdx.x;
+  return (b % kXcd) * per + b / kXcd;
+}
+inline int64_t physical_grid(int64_t nb) { return ((nb + kXcd - 1) / kXcd) * kXcd; }
+
+// ---- deterministic reductions ---------------------------------------------
+template <class T> __device__ __forceinline__ T wave_sum(T v) {
+#pragma unroll
+  for (int o = kWave / 2; o > 0; o >>= 1) v = v + __shfl_xor(v, o, kWave);
+  return v;
+}
+
+// Sum of one value per thread over a 256-thread block, fixed order.  The
+// result is valid in thread 0.  `lds` needs kBlock / kWave entries.
+template <class T> __device__ __forceinline__ T block_sum(T v, T* lds) {
+  v = wave_sum(v);
+  int w = threadIdx.x / kWave;
+  if ((threadIdx.x & (kWave - 1)) == 0) lds[w] = v;
+  __syncthreads();
+  T s = 0;
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int i = 0; i < kBlock / kWave; i++) s = s + lds[i];
+  }
+  __syncthreads();
+  return s;
+}
+
+}  // namespace f3r

@@ -1,0 +1,191 @@
+// Host-side declarations of the kernel launchers of libf3r (gfx950).
+// Every launcher enqueues work on `st` and returns the hipError_t of the
+// launch.  Vector arguments are device pointers; "type" tags say how a
+// vector is stored.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace f3r {
+
+enum TypeTag { T64 = 0, T32 = 1, T16 = 2, TB16 = 3 };
+inline size_t type_size(int t) { return t == T64 ? 8 : t == T32 ? 4 : 2; }
+// arithmetic of a level whose vectors are stored in `t` (Table 1 policy)
+inline int q_of(int t) { return t == T64 ? T64 : T32; }
+
+// SELL-64 sparse structure shared by every value array of one matrix:
+// slice s holds rows [64 s, 64 s + 64); entry k of its row r is stored at
+// off[s] + 64 k + (r mod 64) (column-major inside the slice, so a wave
+// reads 64 consecutive elements per k).  Entries are in CSR column order;
+// rows are padded to the slice width with value 0 and the row's own column.
+// idx holds int16 offsets col - row when every offset fits, else int32
+// columns.  kd[r] is the position of the diagonal inside row r.
+struct SellDesc {
+  int64_t n = 0, ns = 0;
+  const uint32_t* off = nullptr;
+  const void* idx = nullptr;
+  int idx16 = 0;
+  const uint16_t* kd = nullptr;
+};
+
+__host__ __device__ inline int64_t n_slices(int64_t n) { return (n + 63) / 64; }
+__host__ __device__ inline int64_t n_blocks(int64_t n) { return (n_slices(n) + 3) / 4; }
+
+// A basis vector held lazily normalised: value_i = raw_i * (*scale) (times
+// s_i when s != nullptr), rounded to the consumer's storage type.
+struct Basis {
+  const void* raw = nullptr;
+  int type = T64;
+  const double* scale = nullptr;
+  const double* s = nullptr;
+  const int* cur = nullptr;  // when set: raw/scale are bases indexed by *cur
+  int64_t stride = 0;        // elements between consecutive basis vectors
+};
+
+// ---- level SpMV + classical Gram-Schmidt dots ----------------------------
+// y = A x (values `av` of type ta, x of type tx, y of type ty, arithmetic
+// q = q_of(ty)); then partial sums of (y, V_l) for l < nv where V_0 = v0 and
+// V_l = vb + (l-1) n.  Partials (type q) at partials[l * nb + block].
+// When fb && *fb, the input x is replaced by the basis `alt`.
+hipError_t spmv_dots(hipStream_t st, const SellDesc& A, const void* av, int ta,
+                     const void* x, int tx, const Basis* alt, const int* fb,
+                     void* y, int ty, const void* v0, const void* vb, int nv,
+                     void* partials, const int* stop);
+
+// dst[l] = round_q(sum_b partials[l nb + b] * (scales ? scales[l] : 1)),
+// one block per l; dst entries are doubles holding q values.
+hipError_t finalize_sums(hipStream_t st, int q, const void* partials, int64_t nb,
+                         int count, const double* scales, double* dst,
+                         const int* stop);
+
+// w_i <- round(w_i - sum_l round(h_l * round(raw_l,i * scale_l))) and partial
+// sums of w_i^2 at partials[b].
+hipError_t axpy_norm(hipStream_t st, int64_t n, void* w, int tw, const void* v0,
+                     const void* vb, int nv, const double* h,
+                     const double* scales, void* partials, const int* stop);
+
+// Layout of the device scalars of one FGMRES level (doubles).
+struct LevelLayout {
+  int m = 0;
+  int64_t H = 0, Hraw = 0, cs = 0, sn = 0, g = 0, y = 0, scale = 0, beta = 0,
+          cbeta = 0, total = 0;
+  void init(int mm) {
+    m = mm;
+    int64_t o = 0;
+    H = o; o += (int64_t)(m + 1) * m;
+    Hraw = o; o += (int64_t)(m + 1) * m;
+    cs = o; o += m;
+    sn = o; o += m;
+    g = o; o += m + 1;
+    y = o; o += m;
+    scale = o; o += m + 1;
+    beta = o; o += 1;
+    cbeta = o; o += 1;
+    total = o;
+  }
+};
+// ints of one FGMRES level
+enum { I_MEFF = 0, I_STOP = 1, I_CUR = 2, I_BAD = 3, I_FALLBACKS = 4, I_BREAKDOWNS = 5, I_FB = 8 };
+inline int level_ints(int m) { return I_FB + m + 8; }
+
+struct ChildInit {  // state of a child FGMRES level reset by its parent
+  double* S = nullptr;
+  int* I = nullptr;
+  int m = 0;
+  int64_t g = 0, scale = 0;
+};
+
+// Givens step j of a level whose arithmetic is q (one block):
+// h_{j+1,j} = sqrt(sum partials); rotations; g; scale_{j+1} = 1/h_{j+1,j};
+// breakdown/stop handling; when solve_y, back-substitution R y = g.
+// host_out (pinned host, outermost only): [0] = |g_{j+1}| / ||b||, [1] flags.
+hipError_t givens(hipStream_t st, int q, const void* partials, int64_t nb,
+                  double* S, int* I, const LevelLayout& L, int j, int solve_y,
+                  double inv_bnorm, double* host_out, const ChildInit* child);
+hipError_t backsolve(hipStream_t st, int q, double* S, int* I, const LevelLayout& L);
+
+// The basis of one FGMRES level: V_0 = v0, V_j = vb + (j-1) n, each held
+// lazily normalised by scales[j].
+struct LevelBasis {
+  const void* v0 = nullptr;
+  const void* vb = nullptr;
+  int type = T64;
+  const double* scales = nullptr;
+};
+
+// Output of a level with vectors stored in tv:
+// u_i = round_tv(sum_{j < meff} round(y_j Z_j,i)).  With s: out_i = s_i u_i
+// in fp64; with accumulate: out_i += u_i; otherwise out_i = u_i (type tv).
+// When `cur` is set the output vector is out + (*cur) n.  fb: per-column
+// flags; a flagged column uses the basis vector V_j instead of Z_j.
+hipError_t combine(hipStream_t st, int64_t n, const void* Z, int tz, int tv,
+                   const double* y, const int* meff, void* out, const double* s,
+                   const int* cur, int accumulate, const LevelBasis* alt,
+                   const int* fb, int* out_fb);
+
+// Entry of an FGMRES level: out = round_to(to, basis value) and partial
+// sums of out^2 (arithmetic q_of(to)); then the level state is reset with
+// beta = ||out||.
+hipError_t entry_cast(hipStream_t st, int64_t n, const Basis& in, void* out, int to,
+                      void* partials, const int* parent_stop);
+hipError_t entry_finalize(hipStream_t st, int q, const void* partials, int64_t nb,
+                          const ChildInit& lev, const ChildInit* child, const int* parent_stop);
+// state of an aliased child for its first call: scale_0 and beta of the
+// level's own V_0, stop flag copied
+hipError_t child_init0(hipStream_t st, double* S, int* I, const LevelLayout& L,
+                       const ChildInit& child);
+
+// outermost: r = b - A x (fp64) into r, partial sums of r^2
+hipError_t residual64(hipStream_t st, const SellDesc& A, const double* a64,
+                      const double* x, const double* b, double* r, void* partials);
+// beta = ||r||; S.scale[0], S.g, I (meff, stop, cur, bad) reset; host_out[0] =
+// beta * inv_bnorm, host_out[2] = beta
+hipError_t residual_finalize(hipStream_t st, const void* partials, int64_t nb,
+                             double* S, int* I, const LevelLayout& L, double inv_bnorm,
+                             double* host_out);
+// partial sums of x_i y_i (fp64), then sum into host_out[slot]
+hipError_t dot64_to_host(hipStream_t st, int64_t n, const double* x, const double* y,
+                         void* partials, double* host_out);
+
+// ---- primary preconditioner M = G W (two SpMVs) and Richardson ------------
+// t = round(u_i + sum_{k < kd} w_k u_c): W = I - L/alpha; `mv` (type tm) are
+// the W values, or the scaled matrix negated when neg = 1.  The input u is
+// a stored vector (`in.raw`, type in.type == tt, scale == nullptr) or a basis.
+// cntr_inc (nullable): the Richardson call counter, advanced by one even when
+// the call is skipped.
+hipError_t m_apply_w(hipStream_t st, const SellDesc& A, const void* mv, int tm, int neg,
+                     const Basis& in, void* t, int tt, const int* stop, int64_t* cntr_inc);
+
+// y = round(gd t_i + sum_{k > kd} g_k t_c): G = (1/alpha)(I - U/alpha).
+// mode 0: out = y; 1: out = round(w y); 2: out = round(zprev + w y) with
+// w = *omega; 3: out = s_i y (fp64 output, s scaling of the comparison solver).
+// fbflag (nullable): set to 1 when an output value is not finite.
+hipError_t m_apply_g(hipStream_t st, const SellDesc& A, const void* mv, int tm, int neg,
+                     double gd, const void* t, int tt, int mode, const double* omega,
+                     const void* zprev, void* out, int tout, const double* s,
+                     int* fbflag, const int* stop, const int* cur = nullptr);
+
+// r = round(u_i - sum_k a_k z_c) with u given by `in` (basis) and z stored.
+hipError_t rich_residual(hipStream_t st, const SellDesc& A, const void* av, int ta,
+                         const Basis& in, const void* z, void* r, int tr, const int* stop);
+// t = A y kept in q; partials [0] = sum r_i t_i, [1] = sum t_i t_i; r given
+// by `rin` (a basis, or a stored vector with scale == nullptr).
+hipError_t rich_tdots(hipStream_t st, const SellDesc& A, const void* av, int ta,
+                      const void* y, int ty, const Basis& rin, void* partials,
+                      const int* stop);
+// omega' = num / den; running mean of Eq. (5) with l = c_ntr / c, where the
+// device counter holds c_ntr + 1 during the call
+hipError_t rich_omega(hipStream_t st, int q, const void* partials, int64_t nb,
+                      double* omega_k, double* wcur, const int64_t* cntr, int c,
+                      const int* stop);
+// z = round(zprev + w y) (zprev may be null), w = *wcur
+hipError_t rich_zupdate(hipStream_t st, int64_t n, const void* zprev, const void* y,
+                        int tr, const double* wcur, void* z, int* fbflag,
+                        const int* stop);
+
+// ---- small utilities -------------------------------------------------------
+hipError_t convert(hipStream_t st, int64_t n, const void* in, int ti, void* out, int to);
+hipError_t fill_nan(hipStream_t st, void* p, int t, int64_t count, int* flag);
+hipError_t set_omega(hipStream_t st, double* omega, int m, double v);
+
+}  // namespace f3r

@@ -1,0 +1,1110 @@
+// Solve-phase kernels of libf3r for gfx950.
+//
+// Every sparse kernel works on the SELL-64 layout described in kernels.h:
+// one row per lane of a wave64, a slice of 64 rows per wave, four slices per
+// 256-thread block.  A lane walks its row in CSR column order with separate
+// multiply and add (no contraction), so a row sum is rounded exactly like
+// the left-to-right sum that defines the level SpMV (Table 1 precisions;
+// fp32 arithmetic when inputs are narrower, Sec. 4.2).  Reductions are
+// deterministic: fixed shuffle pattern inside a wave, fixed order over the
+// waves of a block, one partial per block, and a fixed-order final sum in a
+// separate one-block kernel (a kernel boundary is the cross-XCD sync point).
+#include <type_traits>
+
+#include "common.h"
+#include "kernels.h"
+
+namespace f3r {
+
+template <class T> struct is_dbl : std::is_same<T, double> {};
+template <class A, class B, class C = float> using wider_t =
+    typename std::conditional<is_dbl<A>::value || is_dbl<B>::value || is_dbl<C>::value, double, float>::type;
+
+template <class TI> __device__ __forceinline__ int64_t col_of(TI d, int64_t row);
+template <> __device__ __forceinline__ int64_t col_of<int16_t>(int16_t d, int64_t row) { return row + d; }
+template <> __device__ __forceinline__ int64_t col_of<int32_t>(int32_t d, int64_t) { return d; }
+
+// ---------------------------------------------------------------------------
+// vector loaders (value of entry c as the consumer's arithmetic type Q)
+// ---------------------------------------------------------------------------
+template <class TT, class Q> struct LdVec {
+  const TT* p;
+  __device__ __forceinline__ void init() {}
+  __device__ __forceinline__ Q operator()(int64_t c) const { return widen<Q>(p[c]); }
+};
+
+// round_to<TT>(raw_c * sc) with the product in Q
+template <class TIN, class TT, class Q> struct LdBasis {
+  const TIN* p;
+  const double* scp;
+  const int* cur;
+  int64_t stride;
+  Q sc;
+  __device__ __forceinline__ void init() {
+    int64_t j = cur ? *cur : 0;
+    p += j * stride;
+    sc = (Q)scp[j];
+  }
+  __device__ __forceinline__ Q operator()(int64_t c) const {
+    Q v = widen<Q>(p[c]) * sc;
+    return widen<Q>(round_to<TT>(v));
+  }
+};
+
+// round_to<TT>(s_c * (raw_c * sc)) with fp64 products (outermost -> scaled
+// inner system, P(v) = S F(S v))
+template <class TT, class Q> struct LdSBasis {
+  const double* p;
+  const double* scp;
+  const double* s;
+  const int* cur;
+  int64_t stride;
+  double sc;
+  __device__ __forceinline__ void init() {
+    int64_t j = cur ? *cur : 0;
+    p += j * stride;
+    sc = scp[j];
+  }
+  __device__ __forceinline__ Q operator()(int64_t c) const {
+    double v = s[c] * (p[c] * sc);
+    return widen<Q>(round_to<TT>(v));
+  }
+};
+
+// j-th vector of a level basis (V_0 separate, V_j = vb + (j-1) n), used by
+// the non-finite fallback
+template <class TIN, class Q> struct LdLevelBasis {
+  const TIN* v0;
+  const TIN* vb;
+  const double* scales;
+  int64_t n;
+  __device__ __forceinline__ Q get(int j, int64_t c) const {
+    const TIN* V = j == 0 ? v0 : vb + (int64_t)(j - 1) * n;
+    Q v = widen<Q>(V[c]) * (Q)scales[j];
+    return widen<Q>(round_to<TIN>(v));
+  }
+};
+
+template <class F> static hipError_t with_type(int t, F&& f) {
+  switch (t) {
+    case T64: return f((double*)nullptr);
+    case T32: return f((float*)nullptr);
+    case T16: return f((f16*)nullptr);
+    case TB16: return f((bf16*)nullptr);
+  }
+  return hipErrorInvalidValue;
+}
+template <class F> static hipError_t with_idx(int idx16, F&& f) {
+  return idx16 ? f((int16_t*)nullptr) : f((int32_t*)nullptr);
+}
+#define TYPE_OF(p) typename std::remove_pointer<decltype(p)>::type
+
+static inline dim3 grid_for(int64_t n) { return dim3((unsigned)physical_grid(n_blocks(n))); }
+
+// Storage combinations the library instantiates: a level with vectors in
+// TY uses a matrix TA and preconditioned directions TX no wider than TY.
+template <class TA, class TX, class TY> constexpr bool ok_level() {
+  if (is_dbl<TY>::value) return is_dbl<TA>::value && is_dbl<TX>::value;
+  if (std::is_same<TY, float>::value) return !is_dbl<TA>::value && !is_dbl<TX>::value;
+  return std::is_same<TA, TY>::value && std::is_same<TX, TY>::value;
+}
+
+// ---------------------------------------------------------------------------
+// level SpMV + CGS dots
+// ---------------------------------------------------------------------------
+constexpr int kDotChunk = 64;
+
+template <class TI, class TA, class TX, class TY, class Q, class ALT>
+__global__ __launch_bounds__(kBlock) void k_spmv_dots(SellDesc A, const TA* __restrict__ av,
+                                                      const TX* __restrict__ x, ALT alt,
+                                                      const int* fb, TY* __restrict__ y,
+                                                      const TY* __restrict__ v0,
+                                                      const TY* __restrict__ vb, int nv,
+                                                      Q* __restrict__ part, int64_t nb,
+                                                      const int* stop) {
+  if (stop && *stop) return;
+  __shared__ Q lds[kBlock / kWave][kDotChunk];
+  const int64_t lb = logical_block(nb);
+  if (lb >= nb) return;
+  const int wave = threadIdx.x / kWave, lane = threadIdx.x & (kWave - 1);
+  const int64_t slice = lb * 4 + wave;
+  const int64_t row = slice * kWave + lane;
+  const bool active = row < A.n;
+  const bool use_alt = fb && *fb;
+  Q yv = 0;
+  if (active) {
+    const TI* idx = (const TI*)A.idx;
+    const uint32_t o0 = A.off[slice];
+    const uint32_t w = (A.off[slice + 1] - o0) / kWave;
+    uint32_t e = o0 + lane;
+    Q acc = 0;
+    if (!use_alt) {
+      for (uint32_t k = 0; k < w; k++, e += kWave)
+        acc = acc + widen<Q>(av[e]) * widen<Q>(x[col_of<TI>(idx[e], row)]);
+    } else {
+      alt.init();
+      for (uint32_t k = 0; k < w; k++, e += kWave)
+        acc = acc + widen<Q>(av[e]) * alt(col_of<TI>(idx[e], row));
+    }
+    const TY yr = round_to<TY>(acc);
+    y[row] = yr;
+    yv = widen<Q>(yr);
+  }
+  for (int c0 = 0; c0 < nv; c0 += kDotChunk) {
+    const int cn = nv - c0 < kDotChunk ? nv - c0 : kDotChunk;
+    for (int l = 0; l < cn; l++) {
+      const int ll = c0 + l;
+      const TY* V = ll == 0 ? v0 : vb + (int64_t)(ll - 1) * A.n;
+      Q p = active ? yv * widen<Q>(V[row]) : Q(0);
+      p = wave_sum(p);
+      if (lane == 0) lds[wave][l] = p;
+    }
+    __syncthreads();
+    if ((int)threadIdx.x < cn) {
+      const int t = threadIdx.x;
+      Q s = lds[0][t];
+      s = s + lds[1][t];
+      s = s + lds[2][t];
+      s = s + lds[3][t];
+      part[(int64_t)(c0 + t) * nb + lb] = s;
+    }
+    __syncthreads();
+  }
+}
+
+hipError_t spmv_dots(hipStream_t st, const SellDesc& A, const void* av, int ta, const void* x,
+                     int tx, const Basis* alt, const int* fb, void* y, int ty, const void* v0,
+                     const void* vb, int nv, void* partials, const int* stop) {
+  const int64_t nb = n_blocks(A.n);
+  return with_idx(A.idx16, [&](auto pi) {
+    using TI = TYPE_OF(pi);
+    return with_type(ta, [&](auto pa) {
+      using TA = TYPE_OF(pa);
+      return with_type(tx, [&](auto px) {
+        using TX = TYPE_OF(px);
+        return with_type(ty, [&](auto py) -> hipError_t {
+          using TY = TYPE_OF(py);
+          if constexpr (!ok_level<TA, TX, TY>()) {
+            return hipErrorInvalidValue;
+          } else {
+            using Q = wider_t<TA, TY>;
+            LdBasis<TY, TY, Q> ld{};
+            if (alt) {
+              ld.p = (const TY*)alt->raw;
+              ld.scp = alt->scale;
+              ld.cur = nullptr;
+              ld.stride = 0;
+            }
+            hipLaunchKernelGGL((k_spmv_dots<TI, TA, TX, TY, Q, LdBasis<TY, TY, Q>>), grid_for(A.n),
+                               dim3(kBlock), 0, st, A, (const TA*)av, (const TX*)x, ld,
+                               alt ? fb : nullptr, (TY*)y, (const TY*)v0, (const TY*)vb, nv,
+                               (Q*)partials, nb, stop);
+            return hipGetLastError();
+          }
+        });
+      });
+    });
+  });
+}
+
+// ---------------------------------------------------------------------------
+// one-block finalisation of per-block partial sums
+// ---------------------------------------------------------------------------
+template <class Q>
+__global__ __launch_bounds__(kBlock) void k_finalize(const Q* __restrict__ part, int64_t nb,
+                                                     const double* scales, double* dst,
+                                                     const int* stop) {
+  if (stop && *stop) return;
+  __shared__ Q lds[kBlock / kWave];
+  const int l = blockIdx.x;
+  Q s = 0;
+  for (int64_t i = threadIdx.x; i < nb; i += kBlock) s = s + part[(int64_t)l * nb + i];
+  s = block_sum(s, lds);
+  if (threadIdx.x == 0) {
+    if (scales) s = s * (Q)scales[l];
+    dst[l] = (double)s;
+  }
+}
+
+hipError_t finalize_sums(hipStream_t st, int q, const void* partials, int64_t nb, int count,
+                         const double* scales, double* dst, const int* stop) {
+  if (count <= 0) return hipSuccess;
+  if (q == T64)
+    hipLaunchKernelGGL(k_finalize<double>, dim3(count), dim3(kBlock), 0, st,
+                       (const double*)partials, nb, scales, dst, stop);
+  else
+    hipLaunchKernelGGL(k_finalize<float>, dim3(count), dim3(kBlock), 0, st,
+                       (const float*)partials, nb, scales, dst, stop);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// CGS update w <- w - V h and its squared norm
+// ---------------------------------------------------------------------------
+constexpr int kMaxM = 1024;
+
+template <class TY, class Q>
+__global__ __launch_bounds__(kBlock) void k_axpy_norm(int64_t n, TY* __restrict__ w,
+                                                      const TY* __restrict__ v0,
+                                                      const TY* __restrict__ vb, int nv,
+                                                      const double* h, const double* scales,
+                                                      Q* __restrict__ part, int64_t nb,
+                                                      const int* stop) {
+  if (stop && *stop) return;
+  __shared__ Q hs[kMaxM];
+  __shared__ Q sc[kMaxM];
+  __shared__ Q lds[kBlock / kWave];
+  const int64_t lb = logical_block(nb);
+  if (lb >= nb) return;
+  for (int t = threadIdx.x; t < nv; t += kBlock) {
+    hs[t] = (Q)h[t];
+    sc[t] = (Q)scales[t];
+  }
+  __syncthreads();
+  const int64_t row = lb * kRowsPerBlock + threadIdx.x;
+  Q wv = 0;
+  if (row < n) {
+    Q acc = widen<Q>(w[row]);
+    for (int l = 0; l < nv; l++) {
+      const TY* V = l == 0 ? v0 : vb + (int64_t)(l - 1) * n;
+      const Q v = widen<Q>(round_to<TY>(widen<Q>(V[row]) * sc[l]));
+      acc = acc - hs[l] * v;
+    }
+    const TY wr = round_to<TY>(acc);
+    w[row] = wr;
+    wv = widen<Q>(wr);
+  }
+  const Q s = block_sum(wv * wv, lds);
+  if (threadIdx.x == 0) part[lb] = s;
+}
+
+hipError_t axpy_norm(hipStream_t st, int64_t n, void* w, int tw, const void* v0, const void* vb,
+                     int nv, const double* h, const double* scales, void* partials,
+                     const int* stop) {
+  if (nv > kMaxM) return hipErrorInvalidValue;
+  const int64_t nb = n_blocks(n);
+  return with_type(tw, [&](auto pw) {
+    using TY = TYPE_OF(pw);
+    using Q = wider_t<TY, TY>;
+    hipLaunchKernelGGL((k_axpy_norm<TY, Q>), grid_for(n), dim3(kBlock), 0, st, n, (TY*)w,
+                       (const TY*)v0, (const TY*)vb, nv, h, scales, (Q*)partials, nb, stop);
+    return hipGetLastError();
+  });
+}
+
+// ---------------------------------------------------------------------------
+// Givens rotations, breakdown handling and the small triangular solve
+// ---------------------------------------------------------------------------
+template <class Q> __device__ void back_substitute(double* S, const int* I, const LevelLayout& L) {
+  // R y = g, rows from the last, each sum taken left to right
+  const int meff = I[I_MEFF];
+  const int ld = L.m + 1;
+  const double* H = S + L.H;
+  const double* g = S + L.g;
+  double* y = S + L.y;
+  for (int i = meff - 1; i >= 0; i--) {
+    Q acc = (Q)g[i];
+    for (int k = i + 1; k < meff; k++) acc = acc - (Q)H[i + (int64_t)k * ld] * (Q)y[k];
+    y[i] = (double)(acc / (Q)H[i + (int64_t)i * ld]);
+  }
+}
+
+__device__ void init_child(const ChildInit& c, double scale0, double beta, int stop) {
+  c.S[c.scale] = scale0;
+  c.S[c.g] = beta;
+  for (int i = 1; i <= c.m; i++) c.S[c.g + i] = 0.0;
+  c.I[I_MEFF] = 0;
+  c.I[I_STOP] = stop;
+  c.I[I_BAD] = 0;
+  for (int i = 0; i < c.m; i++) c.I[I_FB + i] = 0;
+}
+
+template <class Q>
+__global__ __launch_bounds__(kBlock) void k_givens(const Q* __restrict__ part, int64_t nb,
+                                                   double* S, int* I, LevelLayout L, int j,
+                                                   int solve_y, double inv_bnorm,
+                                                   double* host_out, ChildInit child) {
+  __shared__ Q lds[kBlock / kWave];
+  if (I[I_STOP]) return;
+  Q s = 0;
+  for (int64_t i = threadIdx.x; i < nb; i += kBlock) s = s + part[i];
+  s = block_sum(s, lds);
+  if (threadIdx.x != 0) return;
+  const int ld = L.m + 1;
+  double* H = S + L.H;
+  double* Hraw = S + L.Hraw;
+  double* g = S + L.g;
+  double* cs = S + L.cs;
+  double* sn = S + L.sn;
+  const Q hn = sqrt(s);
+  for (int i = 0; i <= j; i++) Hraw[i + (int64_t)j * ld] = H[i + (int64_t)j * ld];
+  Hraw[j + 1 + (int64_t)j * ld] = (double)hn;
+  for (int i = 0; i < j; i++) {
+    const Q a0 = (Q)H[i + (int64_t)j * ld], a1 = (Q)H[i + 1 + (int64_t)j * ld];
+    const Q c = (Q)cs[i], sv = (Q)sn[i];
+    H[i + (int64_t)j * ld] = (double)(c * a0 + sv * a1);
+    H[i + 1 + (int64_t)j * ld] = (double)(-sv * a0 + c * a1);
+  }
+  if (I[I_FB + j]) I[I_FALLBACKS] += 1;
+  const Q hjj = (Q)H[j + (int64_t)j * ld];
+  const Q rho = (Q)hypot((double)hjj, (double)hn);
+  int stop = 0;
+  if (!(rho != (Q)0) || !isfinite((double)rho) || !isfinite((double)hn)) {
+    I[I_MEFF] = j;
+    I[I_BREAKDOWNS] += 1;
+    if (!isfinite((double)rho) || !isfinite((double)hn)) I[I_BAD] = 1;
+    stop = 1;
+  } else {
+    const Q c = hjj / rho, sv = hn / rho;
+    cs[j] = (double)c;
+    sn[j] = (double)sv;
+    H[j + (int64_t)j * ld] = (double)rho;
+    H[j + 1 + (int64_t)j * ld] = 0.0;
+    const Q gj = (Q)g[j];
+    g[j + 1] = (double)(-sv * gj);
+    g[j] = (double)(c * gj);
+    I[I_MEFF] = j + 1;
+    if (hn == (Q)0) {
+      I[I_BREAKDOWNS] += 1;
+      stop = 1;
+    } else {
+      const Q inv = (Q)1 / hn;
+      S[L.scale + j + 1] = (double)inv;
+      S[L.cbeta] = (double)(hn * inv);
+    }
+  }
+  I[I_STOP] = stop;
+  I[I_CUR] = j + 1;
+  if (host_out) {
+    host_out[0] = fabs(g[j + 1]) * inv_bnorm;
+    host_out[1] = (double)(stop | (I[I_BAD] << 1));
+  }
+  if (child.S) init_child(child, S[L.scale + j + 1], S[L.cbeta], stop);
+  if (solve_y || stop) back_substitute<Q>(S, I, L);
+}
+
+hipError_t givens(hipStream_t st, int q, const void* partials, int64_t nb, double* S, int* I,
+                  const LevelLayout& L, int j, int solve_y, double inv_bnorm, double* host_out,
+                  const ChildInit* child) {
+  ChildInit c = child ? *child : ChildInit{};
+  if (q == T64)
+    hipLaunchKernelGGL(k_givens<double>, dim3(1), dim3(kBlock), 0, st, (const double*)partials,
+                       nb, S, I, L, j, solve_y, inv_bnorm, host_out, c);
+  else
+    hipLaunchKernelGGL(k_givens<float>, dim3(1), dim3(kBlock), 0, st, (const float*)partials, nb,
+                       S, I, L, j, solve_y, inv_bnorm, host_out, c);
+  return hipGetLastError();
+}
+
+template <class Q> __global__ void k_backsolve(double* S, int* I, LevelLayout L) {
+  if (threadIdx.x == 0) back_substitute<Q>(S, I, L);
+}
+
+hipError_t backsolve(hipStream_t st, int q, double* S, int* I, const LevelLayout& L) {
+  if (q == T64)
+    hipLaunchKernelGGL(k_backsolve<double>, dim3(1), dim3(64), 0, st, S, I, L);
+  else
+    hipLaunchKernelGGL(k_backsolve<float>, dim3(1), dim3(64), 0, st, S, I, L);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// level output: sum_j y_j z_j
+// ---------------------------------------------------------------------------
+template <class TZ, class TV, class Q>
+__global__ __launch_bounds__(kBlock) void k_combine(int64_t n, const TZ* __restrict__ Z,
+                                                    const double* y, const int* meffp,
+                                                    void* out, const double* s, const int* cur,
+                                                    int accumulate, LdLevelBasis<TV, Q> alt,
+                                                    const int* fb, int* out_fb, int64_t nb) {
+  __shared__ Q ys[kMaxM];
+  __shared__ int fbs[kMaxM];
+  const int64_t lb = logical_block(nb);
+  if (lb >= nb) return;
+  const int meff = *meffp;
+  for (int t = threadIdx.x; t < meff; t += kBlock) {
+    ys[t] = (Q)y[t];
+    fbs[t] = fb ? fb[t] : 0;
+  }
+  __syncthreads();
+  const int64_t row = lb * kRowsPerBlock + threadIdx.x;
+  if (row >= n) return;
+  Q acc = 0;
+  for (int j = 0; j < meff; j++) {
+    const Q zv = fbs[j] ? alt.get(j, row) : widen<Q>(Z[(int64_t)j * n + row]);
+    acc = acc + ys[j] * zv;
+  }
+  const int ci = cur ? *cur : 0;
+  const int64_t o = (int64_t)ci * n;
+  bool fin;
+  if (s) {
+    // consumer on the unscaled outermost system: z = s_i u_i in fp64
+    const double v = s[row] * widen<double>(round_to<TV>(acc));
+    double* od = (double*)out + o;
+    const double r = accumulate ? od[row] + v : v;
+    od[row] = r;
+    fin = isfinite(r);
+  } else {
+    TV* ov = (TV*)out + o;
+    const TV r = accumulate ? round_to<TV>(widen<Q>(ov[row]) + acc) : round_to<TV>(acc);
+    ov[row] = r;
+    fin = finite_val(r);
+  }
+  if (out_fb && !fin) atomicOr(out_fb + ci, 1);
+}
+
+hipError_t combine(hipStream_t st, int64_t n, const void* Z, int tz, int tv, const double* y,
+                   const int* meff, void* out, const double* s, const int* cur, int accumulate,
+                   const LevelBasis* alt, const int* fb, int* out_fb) {
+  const int64_t nb = n_blocks(n);
+  return with_type(tz, [&](auto pz) {
+    using TZ = TYPE_OF(pz);
+    return with_type(tv, [&](auto pv) -> hipError_t {
+      using TV = TYPE_OF(pv);
+      using Q = wider_t<TZ, TV>;
+      LdLevelBasis<TV, Q> ld{};
+      if (alt) {
+        if (alt->type != tv) return hipErrorInvalidValue;
+        ld.v0 = (const TV*)alt->v0;
+        ld.vb = (const TV*)alt->vb;
+        ld.scales = alt->scales;
+        ld.n = n;
+      }
+      hipLaunchKernelGGL((k_combine<TZ, TV, Q>), grid_for(n), dim3(kBlock), 0, st, n, (const TZ*)Z,
+                         y, meff, out, s, cur, accumulate, ld, alt ? fb : nullptr, out_fb, nb);
+      return hipGetLastError();
+    });
+  });
+}
+
+// ---------------------------------------------------------------------------
+// level entry (cast + norm) and outermost residual
+// ---------------------------------------------------------------------------
+template <class LD, class TO, class Q>
+__global__ __launch_bounds__(kBlock) void k_entry(int64_t n, LD ld, TO* __restrict__ out,
+                                                  Q* __restrict__ part, int64_t nb,
+                                                  const int* pstop) {
+  if (pstop && *pstop) return;
+  __shared__ Q lds[kBlock / kWave];
+  const int64_t lb = logical_block(nb);
+  if (lb >= nb) return;
+  const int64_t row = lb * kRowsPerBlock + threadIdx.x;
+  Q v = 0;
+  if (row < n) {
+    ld.init();
+    const TO o = round_to<TO>(ld(row));
+    out[row] = o;
+    v = widen<Q>(o);
+  }
+  const Q s = block_sum(v * v, lds);
+  if (threadIdx.x == 0) part[lb] = s;
+}
+
+hipError_t entry_cast(hipStream_t st, int64_t n, const Basis& in, void* out, int to,
+                      void* partials, const int* parent_stop) {
+  const int64_t nb = n_blocks(n);
+  return with_type(to, [&](auto po) -> hipError_t {
+    using TO = TYPE_OF(po);
+    using Q = wider_t<TO, TO>;
+    if (in.s) {
+      if (in.type != T64) return hipErrorInvalidValue;
+      LdSBasis<TO, double> ld{(const double*)in.raw, in.scale, in.s, in.cur, in.stride, 0.0};
+      hipLaunchKernelGGL((k_entry<LdSBasis<TO, double>, TO, Q>), grid_for(n), dim3(kBlock), 0, st,
+                         n, ld, (TO*)out, (Q*)partials, nb, parent_stop);
+      return hipGetLastError();
+    }
+    return with_type(in.type, [&](auto pi) -> hipError_t {
+      using TIN = TYPE_OF(pi);
+      using QQ = wider_t<TIN, TO>;
+      LdBasis<TIN, TO, QQ> ld{(const TIN*)in.raw, in.scale, in.cur, in.stride, (QQ)0};
+      hipLaunchKernelGGL((k_entry<LdBasis<TIN, TO, QQ>, TO, Q>), grid_for(n), dim3(kBlock), 0, st, n,
+                         ld, (TO*)out, (Q*)partials, nb, parent_stop);
+      return hipGetLastError();
+    });
+  });
+}
+
+template <class Q>
+__global__ __launch_bounds__(kBlock) void k_entry_fin(const Q* __restrict__ part, int64_t nb,
+                                                      ChildInit c, ChildInit child,
+                                                      const int* pstop) {
+  __shared__ Q lds[kBlock / kWave];
+  if (pstop && *pstop) {
+    if (threadIdx.x == 0) {
+      init_child(c, 0.0, 0.0, 1);
+      if (child.S) init_child(child, 0.0, 0.0, 1);
+    }
+    return;
+  }
+  Q s = 0;
+  for (int64_t i = threadIdx.x; i < nb; i += kBlock) s = s + part[i];
+  s = block_sum(s, lds);
+  if (threadIdx.x == 0) {
+    const Q beta = sqrt(s);
+    const Q inv = beta > (Q)0 ? (Q)1 / beta : (Q)0;
+    const int stop = beta > (Q)0 && isfinite((double)beta) ? 0 : 1;
+    init_child(c, (double)inv, (double)beta, stop);
+    // an aliased child starts from V_0 of this level: norm beta * (1 / beta)
+    if (child.S) init_child(child, (double)inv, (double)(beta * inv), stop);
+  }
+}
+
+hipError_t entry_finalize(hipStream_t st, int q, const void* partials, int64_t nb,
+                          const ChildInit& lev, const ChildInit* child, const int* parent_stop) {
+  const ChildInit ch = child ? *child : ChildInit{};
+  if (q == T64)
+    hipLaunchKernelGGL(k_entry_fin<double>, dim3(1), dim3(kBlock), 0, st, (const double*)partials,
+                       nb, lev, ch, parent_stop);
+  else
+    hipLaunchKernelGGL(k_entry_fin<float>, dim3(1), dim3(kBlock), 0, st, (const float*)partials,
+                       nb, lev, ch, parent_stop);
+  return hipGetLastError();
+}
+
+__global__ void k_child_init0(double* S, int* I, LevelLayout L, ChildInit child) {
+  if (threadIdx.x == 0) init_child(child, S[L.scale], S[L.g], I[I_STOP]);
+}
+
+hipError_t child_init0(hipStream_t st, double* S, int* I, const LevelLayout& L,
+                       const ChildInit& child) {
+  hipLaunchKernelGGL(k_child_init0, dim3(1), dim3(64), 0, st, S, I, L, child);
+  return hipGetLastError();
+}
+
+template <class TI>
+__global__ __launch_bounds__(kBlock) void k_residual64(SellDesc A, const double* __restrict__ av,
+                                                       const double* __restrict__ x,
+                                                       const double* __restrict__ b,
+                                                       double* __restrict__ r,
+                                                       double* __restrict__ part, int64_t nb) {
+  __shared__ double lds[kBlock / kWave];
+  const int64_t lb = logical_block(nb);
+  if (lb >= nb) return;
+  const int wave = threadIdx.x / kWave, lane = threadIdx.x & (kWave - 1);
+  const int64_t slice = lb * 4 + wave;
+  const int64_t row = slice * kWave + lane;
+  double rv = 0;
+  if (row < A.n) {
+    const TI* idx = (const TI*)A.idx;
+    const uint32_t o0 = A.off[slice];
+    const uint32_t w = (A.off[slice + 1] - o0) / kWave;
+    uint32_t e = o0 + lane;
+    double acc = 0;
+    for (uint32_t k = 0; k < w; k++, e += kWave) acc = acc + av[e] * x[col_of<TI>(idx[e], row)];
+    rv = b[row] - acc;
+    r[row] = rv;
+  }
+  const double s = block_sum(rv * rv, lds);
+  if (threadIdx.x == 0) part[lb] = s;
+}
+
+hipError_t residual64(hipStream_t st, const SellDesc& A, const double* a64, const double* x,
+                      const double* b, double* r, void* partials) {
+  const int64_t nb = n_blocks(A.n);
+  return with_idx(A.idx16, [&](auto pi) {
+    using TI = TYPE_OF(pi);
+    hipLaunchKernelGGL((k_residual64<TI>), grid_for(A.n), dim3(kBlock), 0, st, A, a64, x, b, r,
+                       (double*)partials, nb);
+    return hipGetLastError();
+  });
+}
+
+__global__ __launch_bounds__(kBlock) void k_residual_fin(const double* __restrict__ part, int64_t nb,
+                                                         double* S, int* I, LevelLayout L,
+                                                         double inv_bnorm, double* host_out) {
+  __shared__ double lds[kBlock / kWave];
+  double s = 0;
+  for (int64_t i = threadIdx.x; i < nb; i += kBlock) s = s + part[i];
+  s = block_sum(s, lds);
+  if (threadIdx.x == 0) {
+    const double beta = sqrt(s);
+    S[L.scale] = beta > 0 ? 1.0 / beta : 0.0;
+    S[L.g] = beta;
+    for (int i = 1; i <= L.m; i++) S[L.g + i] = 0.0;
+    I[I_MEFF] = 0;
+    I[I_STOP] = beta > 0 ? 0 : 1;
+    I[I_CUR] = 0;
+    I[I_BAD] = isfinite(beta) ? 0 : 1;
+    for (int i = 0; i < L.m; i++) I[I_FB + i] = 0;
+    host_out[0] = beta * inv_bnorm;
+    host_out[1] = 0.0;
+    host_out[2] = beta;
+  }
+}
+
+hipError_t residual_finalize(hipStream_t st, const void* partials, int64_t nb, double* S, int* I,
+                             const LevelLayout& L, double inv_bnorm, double* host_out) {
+  hipLaunchKernelGGL(k_residual_fin, dim3(1), dim3(kBlock), 0, st, (const double*)partials, nb, S,
+                     I, L, inv_bnorm, host_out);
+  return hipGetLastError();
+}
+
+__global__ __launch_bounds__(kBlock) void k_dot64(int64_t n, const double* __restrict__ x,
+                                                  const double* __restrict__ y,
+                                                  double* __restrict__ part, int64_t nb) {
+  __shared__ double lds[kBlock / kWave];
+  const int64_t lb = logical_block(nb);
+  if (lb >= nb) return;
+  const int64_t row = lb * kRowsPerBlock + threadIdx.x;
+  const double v = row < n ? x[row] * y[row] : 0.0;
+  const double s = block_sum(v, lds);
+  if (threadIdx.x == 0) part[lb] = s;
+}
+
+__global__ __launch_bounds__(kBlock) void k_sum_to(const double* __restrict__ part, int64_t nb,
+                                                   double* out) {
+  __shared__ double lds[kBlock / kWave];
+  double s = 0;
+  for (int64_t i = threadIdx.x; i < nb; i += kBlock) s = s + part[i];
+  s = block_sum(s, lds);
+  if (threadIdx.x == 0) out[0] = s;
+}
+
+hipError_t dot64_to_host(hipStream_t st, int64_t n, const double* x, const double* y,
+                         void* partials, double* host_out) {
+  const int64_t nb = n_blocks(n);
+  hipLaunchKernelGGL(k_dot64, grid_for(n), dim3(kBlock), 0, st, n, x, y, (double*)partials, nb);
+  hipLaunchKernelGGL(k_sum_to, dim3(1), dim3(kBlock), 0, st, (const double*)partials, nb, host_out);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// primary preconditioner: W and G sweeps (Sec. 5.2: two SpMVs)
+// ---------------------------------------------------------------------------
+template <class TI, class TM, class TT, class Q, class LD>
+__global__ __launch_bounds__(kBlock) void k_mw(SellDesc A, const TM* __restrict__ mv, int neg,
+                                               LD ld, TT* __restrict__ t, const int* stop,
+                                               int64_t* cntr, int64_t nb) {
+  if (cntr && blockIdx.x == 0 && threadIdx.x == 0) *cntr += 1;
+  if (stop && *stop) return;
+  const int64_t lb = logical_block(nb);
+  if (lb >= nb) return;
+  const int wave = threadIdx.x / kWave, lane = threadIdx.x & (kWave - 1);
+  const int64_t slice = lb * 4 + wave;
+  const int64_t row = slice * kWave + lane;
+  if (row >= A.n) return;
+  ld.init();
+  const TI* idx = (const TI*)A.idx;
+  const int kd = A.kd[row];
+  uint32_t e = A.off[slice] + lane;
+  Q acc = 0;
+  for (int k = 0; k < kd; k++, e += kWave) {
+    Q m = widen<Q>(mv[e]);
+    if (neg) m = -m;
+    acc = acc + m * ld(col_of<TI>(idx[e], row));
+  }
+  t[row] = round_to<TT>(acc + ld(row));
+}
+
+template <class TT, class Q> struct EpiStore {
+  TT* out;
+  int* fb;
+  __device__ __forceinline__ void init() {}
+  __device__ __forceinline__ void operator()(int64_t r, TT y) const {
+    out[r] = y;
+    if (fb && !finite_val(y)) atomicOr(fb, 1);
+  }
+};
+template <class TT, class Q> struct EpiZ1 {
+  TT* out;
+  const double* wp;
+  int* fb;
+  Q w;
+  __device__ __forceinline__ void init() { w = (Q)(*wp); }
+  __device__ __forceinline__ void operator()(int64_t r, TT y) const {
+    const TT z = round_to<TT>(w * widen<Q>(y));
+    out[r] = z;
+    if (fb && !finite_val(z)) atomicOr(fb, 1);
+  }
+};
+template <class TT, class Q> struct EpiZK {
+  TT* out;
+  const TT* zp;
+  const double* wp;
+  int* fb;
+  Q w;
+  __device__ __forceinline__ void init() { w = (Q)(*wp); }
+  __device__ __forceinline__ void operator()(int64_t r, TT y) const {
+    const TT z = round_to<TT>(widen<Q>(zp[r]) + w * widen<Q>(y));
+    out[r] = z;
+    if (fb && !finite_val(z)) atomicOr(fb, 1);
+  }
+};
+struct EpiS64 {
+  double* out;
+  const double* s;
+  int* fb;
+  const int* cur;
+  int64_t n;
+  __device__ __forceinline__ void init() {
+    if (cur) {
+      out += (int64_t)(*cur) * n;
+      if (fb) fb += *cur;
+    }
+  }
+  __device__ __forceinline__ void operator()(int64_t r, double y) const {
+    const double z = s[r] * y;
+    out[r] = z;
+    if (fb && !isfinite(z)) atomicOr(fb, 1);
+  }
+};
+
+template <class TI, class TM, class TT, class Q, class EPI>
+__global__ __launch_bounds__(kBlock) void k_mg(SellDesc A, const TM* __restrict__ mv, int neg, Q gd,
+                                               const TT* __restrict__ t, EPI epi, const int* stop,
+                                               int64_t nb) {
+  if (stop && *stop) return;
+  const int64_t lb = logical_block(nb);
+  if (lb >= nb) return;
+  const int wave = threadIdx.x / kWave, lane = threadIdx.x & (kWave - 1);
+  const int64_t slice = lb * 4 + wave;
+  const int64_t row = slice * kWave + lane;
+  if (row >= A.n) return;
+  epi.init();
+  const TI* idx = (const TI*)A.idx;
+  const int kd = A.kd[row];
+  const uint32_t o0 = A.off[slice];
+  const int w = (int)((A.off[slice + 1] - o0) / kWave);
+  uint32_t e = o0 + (uint32_t)(kd + 1) * kWave + lane;
+  Q acc = gd * widen<Q>(t[row]);
+  for (int k = kd + 1; k < w; k++, e += kWave) {
+    Q m = widen<Q>(mv[e]);
+    if (neg) m = -m;
+    acc = acc + m * widen<Q>(t[col_of<TI>(idx[e], row)]);
+  }
+  epi(row, round_to<TT>(acc));
+}
+
+template <class TM, class TT> constexpr bool ok_m() {
+  // M stored no wider than the vectors it is applied to
+  if (is_dbl<TT>::value) return true;
+  if (std::is_same<TT, float>::value) return !is_dbl<TM>::value;
+  return std::is_same<TM, TT>::value;
+}
+
+hipError_t m_apply_w(hipStream_t st, const SellDesc& A, const void* mv, int tm, int neg,
+                     const Basis& in, void* t, int tt, const int* stop, int64_t* cntr) {
+  const int64_t nb = n_blocks(A.n);
+  return with_idx(A.idx16, [&](auto pi) {
+    using TI = TYPE_OF(pi);
+    return with_type(tm, [&](auto pm) {
+      using TM = TYPE_OF(pm);
+      return with_type(tt, [&](auto pt) -> hipError_t {
+        using TT = TYPE_OF(pt);
+        if constexpr (!ok_m<TM, TT>()) {
+          return hipErrorInvalidValue;
+        } else {
+          using Q = wider_t<TM, TT>;
+          if (in.s) {
+            if (in.type != T64 || !is_dbl<TT>::value) return hipErrorInvalidValue;
+            LdSBasis<TT, Q> ld{(const double*)in.raw, in.scale, in.s, in.cur, in.stride, 0.0};
+            hipLaunchKernelGGL((k_mw<TI, TM, TT, Q, LdSBasis<TT, Q>>), grid_for(A.n), dim3(kBlock),
+                               0, st, A, (const TM*)mv, neg, ld, (TT*)t, stop, cntr, nb);
+            return hipGetLastError();
+          }
+          if (!in.scale) {
+            if (in.type != tt) return hipErrorInvalidValue;
+            LdVec<TT, Q> ld{(const TT*)in.raw};
+            hipLaunchKernelGGL((k_mw<TI, TM, TT, Q, LdVec<TT, Q>>), grid_for(A.n), dim3(kBlock), 0,
+                               st, A, (const TM*)mv, neg, ld, (TT*)t, stop, cntr, nb);
+            return hipGetLastError();
+          }
+          return with_type(in.type, [&](auto pin) -> hipError_t {
+            using TIN = TYPE_OF(pin);
+            using QQ = wider_t<TIN, Q>;
+            LdBasis<TIN, TT, QQ> ld{(const TIN*)in.raw, in.scale, in.cur, in.stride, (QQ)0};
+            hipLaunchKernelGGL((k_mw<TI, TM, TT, QQ, LdBasis<TIN, TT, QQ>>), grid_for(A.n),
+                               dim3(kBlock), 0, st, A, (const TM*)mv, neg, ld, (TT*)t, stop, cntr, nb);
+            return hipGetLastError();
+          });
+        }
+      });
+    });
+  });
+}
+
+hipError_t m_apply_g(hipStream_t st, const SellDesc& A, const void* mv, int tm, int neg, double gd,
+                     const void* t, int tt, int mode, const double* omega, const void* zprev,
+                     void* out, int tout, const double* s, int* fbflag, const int* stop,
+                     const int* cur) {
+  const int64_t nb = n_blocks(A.n);
+  if (mode != 3 && tout != tt) return hipErrorInvalidValue;
+  return with_idx(A.idx16, [&](auto pi) {
+    using TI = TYPE_OF(pi);
+    return with_type(tm, [&](auto pm) {
+      using TM = TYPE_OF(pm);
+      return with_type(tt, [&](auto pt) -> hipError_t {
+        using TT = TYPE_OF(pt);
+        if constexpr (!ok_m<TM, TT>()) {
+          return hipErrorInvalidValue;
+        } else {
+          using Q = wider_t<TM, TT>;
+          const dim3 g = grid_for(A.n), b(kBlock);
+          if (mode == 0) {
+            EpiStore<TT, Q> ep{(TT*)out, fbflag};
+            hipLaunchKernelGGL((k_mg<TI, TM, TT, Q, EpiStore<TT, Q>>), g, b, 0, st, A,
+                               (const TM*)mv, neg, (Q)gd, (const TT*)t, ep, stop, nb);
+          } else if (mode == 1) {
+            EpiZ1<TT, Q> ep{(TT*)out, omega, fbflag, (Q)0};
+            hipLaunchKernelGGL((k_mg<TI, TM, TT, Q, EpiZ1<TT, Q>>), g, b, 0, st, A, (const TM*)mv,
+                               neg, (Q)gd, (const TT*)t, ep, stop, nb);
+          } else if (mode == 2) {
+            EpiZK<TT, Q> ep{(TT*)out, (const TT*)zprev, omega, fbflag, (Q)0};
+            hipLaunchKernelGGL((k_mg<TI, TM, TT, Q, EpiZK<TT, Q>>), g, b, 0, st, A, (const TM*)mv,
+                               neg, (Q)gd, (const TT*)t, ep, stop, nb);
+          } else {
+            if constexpr (!is_dbl<TT>::value) {
+              return hipErrorInvalidValue;
+            } else {
+              EpiS64 ep{(double*)out, s, fbflag, cur, A.n};
+              hipLaunchKernelGGL((k_mg<TI, TM, TT, Q, EpiS64>), g, b, 0, st, A, (const TM*)mv, neg,
+                                 (Q)gd, (const TT*)t, ep, stop, nb);
+            }
+          }
+          return hipGetLastError();
+        }
+      });
+    });
+  });
+}
+
+// ---------------------------------------------------------------------------
+// Richardson pieces (Alg. 1)
+// ---------------------------------------------------------------------------
+template <class TI, class TA, class TR, class Q, class LD>
+__global__ __launch_bounds__(kBlock) void k_rres(SellDesc A, const TA* __restrict__ av, LD ld,
+                                                 const TR* __restrict__ z, TR* __restrict__ r,
+                                                 const int* stop, int64_t nb) {
+  if (stop && *stop) return;
+  const int64_t lb = logical_block(nb);
+  if (lb >= nb) return;
+  const int wave = threadIdx.x / kWave, lane = threadIdx.x & (kWave - 1);
+  const int64_t slice = lb * 4 + wave;
+  const int64_t row = slice * kWave + lane;
+  if (row >= A.n) return;
+  ld.init();
+  const TI* idx = (const TI*)A.idx;
+  const uint32_t o0 = A.off[slice];
+  const uint32_t w = (A.off[slice + 1] - o0) / kWave;
+  uint32_t e = o0 + lane;
+  Q acc = 0;
+  for (uint32_t k = 0; k < w; k++, e += kWave)
+    acc = acc + widen<Q>(av[e]) * widen<Q>(z[col_of<TI>(idx[e], row)]);
+  r[row] = round_to<TR>(ld(row) - acc);
+}
+
+hipError_t rich_residual(hipStream_t st, const SellDesc& A, const void* av, int ta,
+                         const Basis& in, const void* z, void* r, int tr, const int* stop) {
+  const int64_t nb = n_blocks(A.n);
+  return with_idx(A.idx16, [&](auto pi) {
+    using TI = TYPE_OF(pi);
+    return with_type(ta, [&](auto pa) {
+      using TA = TYPE_OF(pa);
+      return with_type(tr, [&](auto pr) -> hipError_t {
+        using TR = TYPE_OF(pr);
+        if constexpr (!ok_m<TA, TR>()) {
+          return hipErrorInvalidValue;
+        } else {
+          using Q = wider_t<TA, TR>;
+          return with_type(in.type, [&](auto pin) -> hipError_t {
+            using TIN = TYPE_OF(pin);
+            using QQ = wider_t<TIN, Q>;
+            LdBasis<TIN, TR, QQ> ld{(const TIN*)in.raw, in.scale, in.cur, in.stride, (QQ)0};
+            hipLaunchKernelGGL((k_rres<TI, TA, TR, QQ, LdBasis<TIN, TR, QQ>>), grid_for(A.n),
+                               dim3(kBlock), 0, st, A, (const TA*)av, ld, (const TR*)z, (TR*)r, stop,
+                               nb);
+            return hipGetLastError();
+          });
+        }
+      });
+    });
+  });
+}
+
+template <class TI, class TA, class TR, class Q, class LD>
+__global__ __launch_bounds__(kBlock) void k_rtdots(SellDesc A, const TA* __restrict__ av,
+                                                   const TR* __restrict__ y, LD rld,
+                                                   Q* __restrict__ part, int64_t nb,
+                                                   const int* stop) {
+  if (stop && *stop) return;
+  __shared__ Q lds[kBlock / kWave];
+  const int64_t lb = logical_block(nb);
+  if (lb >= nb) return;
+  const int wave = threadIdx.x / kWave, lane = threadIdx.x & (kWave - 1);
+  const int64_t slice = lb * 4 + wave;
+  const int64_t row = slice * kWave + lane;
+  Q p1 = 0, p2 = 0;
+  if (row < A.n) {
+    rld.init();
+    const TI* idx = (const TI*)A.idx;
+    const uint32_t o0 = A.off[slice];
+    const uint32_t w = (A.off[slice + 1] - o0) / kWave;
+    uint32_t e = o0 + lane;
+    Q t = 0;
+    for (uint32_t k = 0; k < w; k++, e += kWave)
+      t = t + widen<Q>(av[e]) * widen<Q>(y[col_of<TI>(idx[e], row)]);
+    const Q rv = rld(row);
+    p1 = rv * t;
+    p2 = t * t;
+  }
+  const Q s1 = block_sum(p1, lds);
+  const Q s2 = block_sum(p2, lds);
+  if (threadIdx.x == 0) {
+    part[lb] = s1;
+    part[nb + lb] = s2;
+  }
+}
+
+hipError_t rich_tdots(hipStream_t st, const SellDesc& A, const void* av, int ta, const void* y,
+                      int ty, const Basis& rin, void* partials, const int* stop) {
+  const int64_t nb = n_blocks(A.n);
+  return with_idx(A.idx16, [&](auto pi) {
+    using TI = TYPE_OF(pi);
+    return with_type(ta, [&](auto pa) {
+      using TA = TYPE_OF(pa);
+      return with_type(ty, [&](auto py) -> hipError_t {
+        using TR = TYPE_OF(py);
+        if constexpr (!ok_m<TA, TR>()) {
+          return hipErrorInvalidValue;
+        } else {
+          using Q = wider_t<TA, TR>;
+          if (!rin.scale) {
+            LdVec<TR, Q> ld{(const TR*)rin.raw};
+            hipLaunchKernelGGL((k_rtdots<TI, TA, TR, Q, LdVec<TR, Q>>), grid_for(A.n), dim3(kBlock),
+                               0, st, A, (const TA*)av, (const TR*)y, ld, (Q*)partials, nb, stop);
+            return hipGetLastError();
+          }
+          return with_type(rin.type, [&](auto pin) -> hipError_t {
+            using TIN = TYPE_OF(pin);
+            if constexpr (!std::is_same<wider_t<TIN, Q>, Q>::value) {
+              return hipErrorInvalidValue;
+            } else {
+              LdBasis<TIN, TR, Q> ld{(const TIN*)rin.raw, rin.scale, rin.cur, rin.stride, (Q)0};
+              hipLaunchKernelGGL((k_rtdots<TI, TA, TR, Q, LdBasis<TIN, TR, Q>>), grid_for(A.n),
+                                 dim3(kBlock), 0, st, A, (const TA*)av, (const TR*)y, ld,
+                                 (Q*)partials, nb, stop);
+              return hipGetLastError();
+            }
+          });
+        }
+      });
+    });
+  });
+}
+
+template <class Q>
+__global__ __launch_bounds__(kBlock) void k_romega(const Q* __restrict__ part, int64_t nb,
+                                                   double* om, double* wcur,
+                                                   const int64_t* cntr, int c, const int* stop) {
+  if (stop && *stop) return;
+  __shared__ Q lds[kBlock / kWave];
+  Q a = 0, b = 0;
+  for (int64_t i = threadIdx.x; i < nb; i += kBlock) {
+    a = a + part[i];
+    b = b + part[nb + i];
+  }
+  const Q num = block_sum(a, lds);
+  const Q den = block_sum(b, lds);
+  if (threadIdx.x == 0) {
+    const int64_t l = (*cntr - 1) / c;  // Eq. (5): l = c_ntr / c
+    const Q wp = num / den;
+    const Q ok = (Q)(*om);
+    if (den > (Q)0 && isfinite((double)wp)) {
+      Q v = (Q)l * ok;
+      v = v + wp;
+      v = v / (Q)(l + 1);
+      *om = (double)v;
+      *wcur = (double)wp;
+    } else {
+      *wcur = (double)ok;
+    }
+  }
+}
+
+hipError_t rich_omega(hipStream_t st, int q, const void* partials, int64_t nb, double* omega_k,
+                      double* wcur, const int64_t* cntr, int c, const int* stop) {
+  if (c <= 0) return hipErrorInvalidValue;
+  if (q == T64)
+    hipLaunchKernelGGL(k_romega<double>, dim3(1), dim3(kBlock), 0, st, (const double*)partials, nb,
+                       omega_k, wcur, cntr, c, stop);
+  else
+    hipLaunchKernelGGL(k_romega<float>, dim3(1), dim3(kBlock), 0, st, (const float*)partials, nb,
+                       omega_k, wcur, cntr, c, stop);
+  return hipGetLastError();
+}
+
+template <class TR, class Q>
+__global__ __launch_bounds__(kBlock) void k_zupd(int64_t n, const TR* __restrict__ zp,
+                                                 const TR* __restrict__ y, const double* wcur,
+                                                 TR* __restrict__ z, int* fb, const int* stop,
+                                                 int64_t nb) {
+  if (stop && *stop) return;
+  const int64_t lb = logical_block(nb);
+  if (lb >= nb) return;
+  const int64_t row = lb * kRowsPerBlock + threadIdx.x;
+  if (row >= n) return;
+  const Q w = (Q)(*wcur);
+  const Q p = w * widen<Q>(y[row]);
+  const TR zz = zp ? round_to<TR>(widen<Q>(zp[row]) + p) : round_to<TR>(p);
+  z[row] = zz;
+  if (fb && !finite_val(zz)) atomicOr(fb, 1);
+}
+
+hipError_t rich_zupdate(hipStream_t st, int64_t n, const void* zprev, const void* y, int tr,
+                        const double* wcur, void* z, int* fbflag, const int* stop) {
+  const int64_t nb = n_blocks(n);
+  return with_type(tr, [&](auto pr) {
+    using TR = TYPE_OF(pr);
+    using Q = wider_t<TR, TR>;
+    hipLaunchKernelGGL((k_zupd<TR, Q>), grid_for(n), dim3(kBlock), 0, st, n, (const TR*)zprev,
+                       (const TR*)y, wcur, (TR*)z, fbflag, stop, nb);
+    return hipGetLastError();
+  });
+}
+
+// ---------------------------------------------------------------------------
+// utilities
+// ---------------------------------------------------------------------------
+template <class TI, class TO>
+__global__ void k_convert(int64_t n, const TI* __restrict__ in, TO* __restrict__ out) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) out[i] = round_to<TO>(widen<double>(in[i]));
+}
+
+hipError_t convert(hipStream_t st, int64_t n, const void* in, int ti, void* out, int to) {
+  return with_type(ti, [&](auto pi) {
+    using TI = TYPE_OF(pi);
+    return with_type(to, [&](auto po) {
+      using TO = TYPE_OF(po);
+      hipLaunchKernelGGL((k_convert<TI, TO>), dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, n,
+                         (const TI*)in, (TO*)out);
+      return hipGetLastError();
+    });
+  });
+}
+
+template <class T> __global__ void k_fill_nan(T* p, int64_t count, int* flag) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < count) p[i] = round_to<T>((double)NAN);
+  if (i == 0 && flag) *flag = 1;
+}
+
+hipError_t fill_nan(hipStream_t st, void* p, int t, int64_t count, int* flag) {
+  return with_type(t, [&](auto pt) {
+    using T = TYPE_OF(pt);
+    hipLaunchKernelGGL((k_fill_nan<T>), dim3((unsigned)((count + 255) / 256)), dim3(256), 0, st,
+                       (T*)p, count, flag);
+    return hipGetLastError();
+  });
+}
+
+__global__ void k_set(double* p, int m, double v) {
+  if ((int)threadIdx.x < m) p[threadIdx.x] = v;
+}
+
+hipError_t set_omega(hipStream_t st, double* omega, int m, double v) {
+  hipLaunchKernelGGL(k_set, dim3(1), dim3(64), 0, st, omega, m, v);
+  return hipGetLastError();
+}
+
+}  // namespace f3r

@@ -1,0 +1,165 @@
+// Set-up kernels: one thread per row of the CSR input.
+#include "common.h"
+#include "kernels.h"
+#include "setup.h"
+
+namespace f3r {
+
+__global__ void k_row_check(int64_t n, const int32_t* __restrict__ rp,
+                            const int32_t* __restrict__ ci, const double* __restrict__ val,
+                            double* __restrict__ s, uint16_t* __restrict__ kd,
+                            int32_t* __restrict__ len, int* flags) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int64_t lo = rp[i], hi = rp[i + 1];
+  int bad = 0;
+  if (hi < lo) {
+    atomicOr(flags, SF_MATRIX);
+    len[i] = 0;
+    kd[i] = 0;
+    s[i] = 0.0;
+    return;
+  }
+  int64_t dpos = -1;
+  double d = 0.0;
+  int64_t far = 0;
+  for (int64_t k = lo; k < hi; k++) {
+    const int64_t c = ci[k];
+    if (c < 0 || c >= n) bad |= SF_MATRIX;
+    if (k > lo && c <= (int64_t)ci[k - 1]) bad |= SF_MATRIX;
+    if (!isfinite(val[k])) bad |= SF_MATRIX;
+    if (c == i) {
+      dpos = k - lo;
+      d = val[k];
+    }
+    const int64_t dd = c - i < 0 ? i - c : c - i;
+    far = dd > far ? dd : far;
+  }
+  if (dpos < 0 || d == 0.0) bad |= SF_MATRIX;
+  if (hi - lo > 65535) bad |= SF_LONGROW;
+  if (far > 32767) bad |= SF_IDX32;
+  if (bad) atomicOr(flags, bad);
+  len[i] = (int32_t)(hi - lo);
+  kd[i] = (uint16_t)(dpos < 0 ? 0 : dpos);
+  s[i] = 1.0 / sqrt(fabs(d));
+}
+
+hipError_t row_check(hipStream_t st, int64_t n, const int32_t* rp, const int32_t* ci,
+                     const double* val, double* s, uint16_t* kd, int32_t* len, int* flags) {
+  hipLaunchKernelGGL(k_row_check, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, n, rp, ci, val,
+                     s, kd, len, flags);
+  return hipGetLastError();
+}
+
+__global__ void k_slice_widths(int64_t n, const int32_t* __restrict__ len, uint32_t* __restrict__ w) {
+  const int64_t sl = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (sl >= n_slices(n)) return;
+  int32_t m = 0;
+  for (int64_t r = sl * 64; r < sl * 64 + 64 && r < n; r++) m = len[r] > m ? len[r] : m;
+  w[sl] = (uint32_t)m;
+}
+
+hipError_t slice_widths(hipStream_t st, int64_t n, const int32_t* len, uint32_t* width) {
+  const int64_t ns = n_slices(n);
+  hipLaunchKernelGGL(k_slice_widths, dim3((unsigned)((ns + 255) / 256)), dim3(256), 0, st, n, len,
+                     width);
+  return hipGetLastError();
+}
+
+template <class T> __device__ __forceinline__ void put(void* p, uint32_t e, double v, int tag,
+                                                       int mask, int* bad) {
+  if (!p) return;
+  const T r = round_to<T>(v);
+  ((T*)p)[e] = r;
+  if ((mask >> tag) & 1)
+    if (!finite_val(r)) *bad |= SF_RANGE;
+}
+
+__global__ void k_to_sell(int64_t n, const int32_t* __restrict__ rp, const int32_t* __restrict__ ci,
+                          const double* __restrict__ val, const double* __restrict__ s,
+                          const uint32_t* __restrict__ off, const int32_t* __restrict__ len,
+                          SellOut o, int* flags) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int64_t sl = i / 64;
+  const int lane = (int)(i % 64);
+  const uint32_t base = off[sl] + lane;
+  const int w = (int)((off[sl + 1] - off[sl]) / 64);
+  const int64_t lo = rp[i];
+  const int L = len[i];
+  const double si = s[i];
+  int bad = 0;
+  for (int k = 0; k < w; k++) {
+    const uint32_t e = base + (uint32_t)k * 64;
+    int64_t c = i;
+    double a = 0.0, ah = 0.0, mvv = 0.0;
+    if (k < L) {
+      c = ci[lo + k];
+      a = val[lo + k];
+      ah = (si * a) * s[c];
+      if (c < i) mvv = -ah / o.alpha;
+      if (c > i) mvv = (-ah / o.alpha) / o.alpha;
+    }
+    if (o.idx16)
+      ((int16_t*)o.idx)[e] = (int16_t)(c - i);
+    else
+      ((int32_t*)o.idx)[e] = (int32_t)c;
+    o.a64[e] = a;
+    put<double>(o.ah[T64], e, ah, T64, o.range_mask, &bad);
+    put<float>(o.ah[T32], e, ah, T32, o.range_mask, &bad);
+    put<f16>(o.ah[T16], e, ah, T16, o.range_mask, &bad);
+    put<bf16>(o.ah[TB16], e, ah, TB16, o.range_mask, &bad);
+    put<double>(o.mv[T64], e, mvv, T64, o.range_mask, &bad);
+    put<float>(o.mv[T32], e, mvv, T32, o.range_mask, &bad);
+    put<f16>(o.mv[T16], e, mvv, T16, o.range_mask, &bad);
+    put<bf16>(o.mv[TB16], e, mvv, TB16, o.range_mask, &bad);
+  }
+  if (bad) atomicOr(flags, bad);
+}
+
+hipError_t to_sell(hipStream_t st, int64_t n, const int32_t* rp, const int32_t* ci,
+                   const double* val, const double* s, const uint32_t* off, const int32_t* len,
+                   const SellOut& o, int* flags) {
+  hipLaunchKernelGGL(k_to_sell, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, n, rp, ci, val, s,
+                     off, len, o, flags);
+  return hipGetLastError();
+}
+
+__global__ void k_m_diag(double alpha, double* out) {
+  if (threadIdx.x != 0) return;
+  const double v = 1.0 / alpha;
+  out[T64] = v;
+  out[T32] = (double)round_to<float>(v);
+  out[T16] = (double)(float)round_to<f16>(v);
+  out[TB16] = (double)bf16_to_float(round_to<bf16>(v));
+}
+
+hipError_t m_diag(hipStream_t st, double alpha, double* out) {
+  hipLaunchKernelGGL(k_m_diag, dim3(1), dim3(64), 0, st, alpha, out);
+  return hipGetLastError();
+}
+
+template <class T>
+__global__ void k_sell_to_csr(int64_t n, const int32_t* __restrict__ rp, const uint32_t* __restrict__ off,
+                              const T* __restrict__ v, double* __restrict__ out) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const uint32_t base = off[i / 64] + (uint32_t)(i % 64);
+  for (int64_t k = rp[i]; k < rp[i + 1]; k++)
+    out[k] = widen<double>(v[base + (uint32_t)(k - rp[i]) * 64]);
+}
+
+hipError_t sell_to_csr_values(hipStream_t st, int64_t n, const int32_t* rp, const uint32_t* off,
+                              const void* v, int t, double* out) {
+  const dim3 g((unsigned)((n + 255) / 256)), b(256);
+  switch (t) {
+    case T64: hipLaunchKernelGGL(k_sell_to_csr<double>, g, b, 0, st, n, rp, off, (const double*)v, out); break;
+    case T32: hipLaunchKernelGGL(k_sell_to_csr<float>, g, b, 0, st, n, rp, off, (const float*)v, out); break;
+    case T16: hipLaunchKernelGGL(k_sell_to_csr<f16>, g, b, 0, st, n, rp, off, (const f16*)v, out); break;
+    case TB16: hipLaunchKernelGGL(k_sell_to_csr<bf16>, g, b, 0, st, n, rp, off, (const bf16*)v, out); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+}  // namespace f3r

@@ -1,0 +1,255 @@
+"""GPU parity: the HIP path through the C ABI against the CPU oracle, on the
+same seeded inputs.
+
+Bars (each derived in the design notes):
+  * set-up (scaling, rounded value copies): bit-exact;
+  * level SpMVs and M applications: bit-exact (same per-row summation order,
+    no contraction on either side);
+  * Richardson calls without a weight update: bit-exact;
+  * calls with reductions (weight updates, FGMRES levels): within the fp16/
+    fp32 rounding bounds stated per test;
+  * end to end: both reach the fp64 relative residual, outer iteration counts
+    agree within one, and the solution difference is within the condition-
+    number bound kappa (res_gpu + res_oracle).
+"""
+import numpy as np
+import pytest
+
+import oracle as O
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    import paper_2505_20719_amd as P
+    P.lib()
+
+
+def P():
+    import paper_2505_20719_amd as P
+    return P
+
+
+def dev(x):
+    return torch.as_tensor(np.ascontiguousarray(x, dtype=np.float64), device="cuda")
+
+
+def host(t):
+    return t.detach().cpu().numpy()
+
+
+ORACLE_VARIANT = {0: O.FP16_F3R, 1: O.FP32_F3R, 2: O.FP64_F3R, 3: O.FGMRES64, 4: O.BF16_F3R}
+
+MATS = {
+    "poisson2d_64": lambda: W.poisson2d(64),
+    "poisson3d_30": lambda: W.poisson3d(30),       # n = 27000: ragged last block
+    "convdiff_12": lambda: W.convdiff_q1(12),       # nonsymmetric 27-point
+    "elastic_6": lambda: W.elasticity_bonds(6),     # 3x3 blocks, n = 648
+}
+
+
+def pair(name, variant=0):
+    A = MATS[name]()
+    print(f"[case] {name} n={A.n} variant={variant}", flush=True)
+    g = P().Solver(A.row_ptr, A.col_idx, A.val, P().params_default(variant))
+    o = O.Oracle(A.row_ptr, A.col_idx, A.val, O.default_params(ORACLE_VARIANT[variant]))
+    return A, g, o
+
+
+@pytest.mark.parametrize("name", list(MATS))
+def test_setup_bit_exact(name):
+    A, g, o = pair(name)
+    assert np.array_equal(g.debug_scaling(), o.scaling())
+    for p in (O.F64, O.F32, O.F16):
+        assert np.array_equal(g.debug_level_values(p), o.level_values(p)), p
+    A, g, o = pair(name, 4)
+    assert np.array_equal(g.debug_level_values(O.BF16), o.level_values(O.BF16))
+
+
+@pytest.mark.parametrize("name", list(MATS))
+def test_level_spmv_bit_exact(name):
+    A, g, o = pair(name)
+    rs = np.random.default_rng(3)
+    x = rs.uniform(-1, 1, A.n)
+    assert np.array_equal(host(g.debug_spmv(0, dev(x))), o.spmv(x, scaled=0))
+    x32 = O.round_to(O.F32, x)
+    assert np.array_equal(host(g.debug_spmv(1, dev(x32))), o.spmv(x32, 1, O.F32, O.F32, O.F32))
+    x16 = O.round_to(O.F16, x)
+    assert np.array_equal(host(g.debug_spmv(2, dev(x16))), o.spmv(x16, 1, O.F16, O.F32, O.F32))
+    assert np.array_equal(host(g.debug_spmv(3, dev(x16))), o.spmv(x16, 1, O.F16, O.F32, O.F32))
+
+
+@pytest.mark.parametrize("name", list(MATS))
+def test_m_apply_bit_exact(name):
+    A, g, o = pair(name)
+    r = np.random.default_rng(4).uniform(-1, 1, A.n)
+    r16 = O.round_to(O.F16, r)
+    assert np.array_equal(host(g.debug_apply_m(O.F16, dev(r16))), o.apply_m(r16, O.F16, O.F32))
+    r32 = O.round_to(O.F32, r)
+    assert np.array_equal(host(g.debug_apply_m(O.F32, dev(r32))), o.apply_m(r32, O.F32, O.F32))
+    A, g, o = pair(name, 2)  # fp64 factors
+    assert np.array_equal(host(g.debug_apply_m(O.F64, dev(r))), o.apply_m(r, O.F64, O.F64))
+
+
+@pytest.mark.parametrize("name", ["poisson2d_64", "convdiff_12", "poisson3d_30"])
+def test_richardson_call_lockstep(name):
+    A, g, o = pair(name)
+    rs = np.random.default_rng(5)
+    w = np.array([1.1, 0.9])
+    for cntr in (5, 63):  # no weight update in these calls: bit-exact
+        g.set_weights(3, w, cntr)
+        o.set_weights(3, w, cntr)
+        v = O.round_to(O.F32, rs.uniform(-1, 1, A.n) / np.sqrt(A.n))
+        zg = host(g.debug_apply_level(3, dev(v)))
+        zo = o.apply_level(3, v)
+        assert np.array_equal(zg, zo), cntr
+    # c_ntr = 64: locally optimal weights computed with reductions; the
+    # weights agree to fp32 rounding and z to a few fp16 ulps
+    g.set_weights(3, w, 64)
+    o.set_weights(3, w, 64)
+    v = O.round_to(O.F32, rs.uniform(-1, 1, A.n) / np.sqrt(A.n))
+    zg = host(g.debug_apply_level(3, dev(v)))
+    zo = o.apply_level(3, v)
+    wg, cg = g.weights(3)
+    wo, co = o.weights(3)
+    assert cg == co == 65
+    assert np.allclose(wg, wo, rtol=1e-5)
+    tol = 4 * 2.0 ** -11 * np.max(np.abs(zo)) + 2.0 ** -24
+    assert np.max(np.abs(zg - zo)) <= tol
+    assert np.linalg.norm(zg - zo) <= 1e-3 * np.linalg.norm(zo)
+
+
+@pytest.mark.parametrize("level", [2, 1])
+@pytest.mark.parametrize("name", ["poisson2d_64", "convdiff_12"])
+def test_fgmres_level_lockstep(name, level):
+    A, g, o = pair(name)
+    w = np.array([1.05, 0.95])
+    g.set_weights(3, w, 2)
+    o.set_weights(3, w, 2)
+    v = O.round_to(O.F32 if level == 2 else O.F64, np.random.default_rng(6).uniform(-1, 1, A.n))
+    zg = host(g.debug_apply_level(level, dev(v)))
+    zo = o.apply_level(level, v)
+    # dots in a different order: fp32 rounding, amplified by at most the fp16
+    # rounding of the Richardson inputs (a few ulps in a few entries)
+    assert np.linalg.norm(zg - zo) <= 2e-3 * np.linalg.norm(zo)
+    assert g.weights(3)[1] == o.weights(3)[1]
+
+
+def _solve_pair(name, variant, tol=1e-10):
+    A, g, o = pair(name, variant)
+    xs, b = W.rhs(A, name)
+    xo, io = o.solve(b, tol) if variant != 3 else o.fgmres_solve(b, tol)
+    if variant == 3:
+        xg, ig = g.fgmres_solve(dev(b), tol=tol)
+    else:
+        xg, ig = g.solve(dev(b), tol=tol)
+    return A, g, o, b, host(xg), ig, xo, io
+
+
+def _cond_est(A):
+    D = A.to_scipy().toarray() if A.n <= 5000 else None
+    return np.linalg.cond(D) if D is not None else None
+
+
+@pytest.mark.parametrize("variant", [0, 1, 2, 4, 3])
+def test_end_to_end_poisson2d(variant):
+    A, g, o, b, xg, ig, xo, io = _solve_pair("poisson2d_64", variant)
+    assert ig.status == 0 and io.status == 0
+    D = A.to_scipy()
+    rg = np.linalg.norm(b - D @ xg) / np.linalg.norm(b)
+    assert rg < 1e-10 and np.isclose(rg, ig.relres_true, rtol=1e-6)
+    assert abs(ig.outer_iters - io.outer_iters) <= 1
+    kappa = 1.0 / np.tan(np.pi / (2 * 65)) ** 2
+    assert np.linalg.norm(xg - xo) / np.linalg.norm(xo) <= kappa * (rg + io.relres_true)
+    if variant in (2, 3):  # fp64 throughout: histories agree to rounding
+        hg, ho = g.history(), o.history()
+        k = min(len(hg), len(ho), 100)
+        assert np.allclose(hg[:k], ho[:k], rtol=1e-8), (hg[:k], ho[:k])
+    if variant in (0, 1, 2, 4):
+        assert ig.m_calls == 64 * ig.outer_iters and ig.r_calls == 32 * ig.outer_iters
+
+
+@pytest.mark.parametrize("name", ["poisson3d_30", "convdiff_12", "elastic_6"])
+def test_end_to_end_other_structures(name):
+    A, g, o, b, xg, ig, xo, io = _solve_pair(name, 0)
+    assert ig.status == 0 and io.status == 0
+    D = A.to_scipy()
+    rg = np.linalg.norm(b - D @ xg) / np.linalg.norm(b)
+    assert rg < 1e-10
+    assert abs(ig.outer_iters - io.outer_iters) <= 1
+    kappa = _cond_est(A)
+    if kappa is not None:
+        assert np.linalg.norm(xg - xo) / np.linalg.norm(xo) <= kappa * (rg + io.relres_true)
+
+
+def test_graph_and_direct_launch_agree_and_runs_are_deterministic():
+    import paper_2505_20719_amd as PP
+    A, g, o = pair("poisson3d_30")
+    xs, b = W.rhs(A, "poisson3d_30")
+    x1, i1 = g.solve(dev(b))
+    x2, i2 = g.solve(dev(b))
+    ov = PP.params_default(0)
+    ov.flags = PP.NO_GRAPH
+    x3, i3 = g.solve(dev(b), override=ov)
+    assert i1.graph_launches > 0 and i3.graph_launches == 0
+    assert torch.equal(x1, x2) and torch.equal(x1, x3)
+
+
+def test_edge_cases_and_errors():
+    import paper_2505_20719_amd as PP
+    A = W.poisson2d(7)  # n = 49 < 64: one partial slice
+    g = PP.Solver(A.row_ptr, A.col_idx, A.val)
+    xs, b = W.rhs(A, "tiny")
+    x, info = g.solve(dev(b))
+    assert info.status == 0 and info.relres_true < 1e-10
+    x, info = g.solve(dev(np.zeros(A.n)))
+    assert info.status == 0 and float(x.abs().max()) == 0.0
+    ov = PP.params_default(0)
+    ov.max_outer = 1
+    A2 = W.poisson2d(64)
+    g2 = PP.Solver(A2.row_ptr, A2.col_idx, A2.val)
+    xs2, b2 = W.rhs(A2, "p")
+    x, info = g2.solve(dev(b2), override=ov)
+    assert info.status == PP.NOT_CONVERGED and info.outer_iters == 1
+    # warm start from the last iterate continues the solve
+    ov2 = PP.params_default(0)
+    ov2.flags = PP.USE_X0
+    x, info = g2.solve(dev(b2), x=x, override=ov2)
+    assert info.status == 0
+    v = A.val.copy()
+    diag = [k for i in range(A.n) for k in range(A.row_ptr[i], A.row_ptr[i + 1]) if A.col_idx[k] == i]
+    v[diag[5]] = 0.0
+    with pytest.raises(PP.F3RError) as e:
+        PP.Solver(A.row_ptr, A.col_idx, v)
+    assert e.value.status == PP.ERR_MATRIX
+    v = A.val.copy()
+    v[1] = -1e6
+    with pytest.raises(PP.F3RError) as e:
+        PP.Solver(A.row_ptr, A.col_idx, v)
+    assert e.value.status == PP.ERR_RANGE
+    rp = A.row_ptr.copy()
+    rp[3], rp[4] = rp[4], rp[3]
+    with pytest.raises(PP.F3RError) as e:
+        PP.Solver(rp, A.col_idx, A.val)
+    assert e.value.status == PP.ERR_MATRIX
+
+
+def test_poisoned_richardson_output_falls_back_like_the_oracle():
+    import paper_2505_20719_amd as PP
+    A = W.poisson2d(64)
+    xs, b = W.rhs(A, "poisson2d_64")
+    p = PP.params_default(0)
+    p.poison_call = 5
+    g = PP.Solver(A.row_ptr, A.col_idx, A.val, p)
+    x, info = g.solve(dev(b))
+    po = O.default_params(O.FP16_F3R)
+    po.poison_call = 5
+    o = O.Oracle(A.row_ptr, A.col_idx, A.val, po)
+    xo, io = o.solve(b)
+    assert info.status == 0 and info.fallbacks == 1 == io.fallbacks
+    assert abs(info.outer_iters - io.outer_iters) <= 1
