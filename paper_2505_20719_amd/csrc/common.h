@@ -78,14 +78,19 @@ template <> __device__ __forceinline__ bool finite_val<f16>(f16 x) { return isfi
 template <> __device__ __forceinline__ bool finite_val<bf16>(bf16 x) { return isfinite(bf16_to_float(x)); }
 
 // ---- launch geometry -------------------------------------------------------
-// Rows are processed in slices of 64 (one row per lane of a wave64), four
-// slices per 256-thread block.  Blocks are dispatched round-robin over the 8
-// XCDs; logical block b of a kernel is placed on XCD b / per so that every
-// row-parallel kernel touches the same rows on the same XCD and the L2 of
-// that XCD keeps the vectors the previous kernel wrote.
+// Rows are processed in slices of 64 (one row per lane of a wave64).  Each
+// wave takes kR consecutive slices, so a lane owns kR rows and issues the
+// loads of all of them together (a single slice per wave leaves the waves
+// too short to keep enough bytes in flight); a 256-thread block covers
+// 4 kR slices = kRowsPerBlock rows.  Row-parallel kernels without a matrix
+// give each thread kR rows of the same block range.  Blocks are dispatched
+// round-robin over the 8 XCDs; logical block b is placed on XCD b / per, so
+// every row-parallel kernel touches the same rows on the same XCD and that
+// XCD's L2 keeps the vectors the previous kernel wrote.
 constexpr int kWave = 64;
 constexpr int kBlock = 256;
-constexpr int kRowsPerBlock = kBlock;
+constexpr int kR = 4;
+constexpr int kRowsPerBlock = kBlock * kR;
 constexpr int kXcd = 8;
 
 __device__ __forceinline__ int64_t logical_block(int64_t nb) {
@@ -113,6 +118,41 @@ template <class T> __device__ __forceinline__ T block_sum(T v, T* lds) {
   if (threadIdx.x == 0) {
 #pragma unroll
     for (int i = 0; i < kBlock / kWave; i++) s = s + lds[i];
+  }
+  __syncthreads();
+  return s;
+}
+
+// One-block reductions of per-block partials use kFinBlock threads; each
+// thread sums the entries t, t + kFinBlock, ... in index order with eight
+// loads in flight, then the block sums the threads in a fixed order.
+constexpr int kFinBlock = 1024;
+
+template <class Q> __device__ __forceinline__ Q thread_sum(const Q* __restrict__ p, int64_t cnt) {
+  const int nt = kFinBlock;
+  Q s = 0;
+  int64_t i = threadIdx.x;
+  for (; i + 7 * (int64_t)nt < cnt; i += 8 * (int64_t)nt) {
+    Q v[8];
+#pragma unroll
+    for (int u = 0; u < 8; u++) v[u] = p[i + (int64_t)u * nt];
+#pragma unroll
+    for (int u = 0; u < 8; u++) s = s + v[u];
+  }
+  for (; i < cnt; i += nt) s = s + p[i];
+  return s;
+}
+
+// sum over a kFinBlock-thread block, valid in thread 0 (lds: 16 entries)
+template <class T> __device__ __forceinline__ T fin_block_sum(T v, T* lds) {
+  v = wave_sum(v);
+  const int w = threadIdx.x / kWave;
+  if ((threadIdx.x & (kWave - 1)) == 0) lds[w] = v;
+  __syncthreads();
+  T s = 0;
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int i = 0; i < kFinBlock / kWave; i++) s = s + lds[i];
   }
   __syncthreads();
   return s;

@@ -78,6 +78,7 @@ struct f3r_handle {
   uint32_t* off = nullptr;
   void* idx = nullptr;
   uint16_t* kd = nullptr;
+  uint32_t* kdr = nullptr;
   int32_t* rp = nullptr;  // CSR row pointers, kept for debug read-back
   double* a64 = nullptr;
   void* ah[4] = {};
@@ -120,6 +121,8 @@ struct f3r_handle {
 };
 
 namespace {
+
+void destroy_graphs(f3r_handle* h);
 
 double now_ms() {
   return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now().time_since_epoch())
@@ -389,11 +392,11 @@ void enqueue_fgmres(Ctx& c, int d, const Basis& vin, const void* alias_raw, cons
       enqueue_m(c, d, bj, stop, zj, fbj);
     }
     const int pid = d == 1 ? F3R_PROBE_SPMV_L1 : d == 2 ? F3R_PROBE_SPMV_L2 : -1;
+    double* hcol = L.S + L.L.H + (int64_t)j * (m + 1);
     probe_begin(c, pid);
     HIPCHK(spmv_dots(c.st, h->A, h->ah[L.pa], L.pa, zj, L.zt, &bj, fbj, vec_at(L.V, L.pv, j + 1, n),
                      L.pv, v0, vb, j + 1, h->partials, stop));
     probe_end(c, pid);
-    double* hcol = L.S + L.L.H + (int64_t)j * (m + 1);
     HIPCHK(finalize_sums(c.st, L.q, h->partials, nb, j + 1, L.S + L.L.scale, hcol, stop));
     HIPCHK(axpy_norm(c.st, n, vec_at(L.V, L.pv, j + 1, n), L.pv, v0, vb, j + 1, hcol, L.S + L.L.scale,
                      h->partials, stop));
@@ -814,7 +817,8 @@ f3r_status f3r_setup(const f3r_csr* A, const f3r_params* p, void* hip_stream, f3
     HIPCHK(hipMemsetAsync(flags, 0, sizeof(int), h->st));
     HIPCHK(row_check(h->st, n, h->rp, ci, val, h->s, h->kd, len, flags));
     uint32_t* wdev = (uint32_t*)h->dalloc((size_t)ns * 4);
-    HIPCHK(slice_widths(h->st, n, len, wdev));
+    h->kdr = (uint32_t*)h->dalloc((size_t)ns * 4);
+    HIPCHK(slice_widths(h->st, n, len, h->kd, wdev, h->kdr));
     int hflags = 0;
     HIPCHK(hipMemcpyAsync(&hflags, flags, sizeof(int), hipMemcpyDeviceToHost, h->st));
     std::vector<uint32_t> w((size_t)ns), off((size_t)ns + 1);
@@ -874,6 +878,7 @@ f3r_status f3r_setup(const f3r_csr* A, const f3r_params* p, void* hip_stream, f3
     h->A.idx = h->idx;
     h->A.idx16 = so.idx16;
     h->A.kd = h->kd;
+    h->A.kdr = h->kdr;
     // the CSR copies are no longer needed
     HIPCHK(hipFree(ci));
     HIPCHK(hipFree(val));

@@ -19,17 +19,20 @@ inline int q_of(int t) { return t == T64 ? T64 : T32; }
 // reads 64 consecutive elements per k).  Entries are in CSR column order;
 // rows are padded to the slice width with value 0 and the row's own column.
 // idx holds int16 offsets col - row when every offset fits, else int32
-// columns.  kd[r] is the position of the diagonal inside row r.
+// columns.  kd[r] is the position of the diagonal inside row r; kdr[s] packs
+// the smallest (low 16 bits) and largest (high 16 bits) kd of slice s.
 struct SellDesc {
   int64_t n = 0, ns = 0;
   const uint32_t* off = nullptr;
   const void* idx = nullptr;
   int idx16 = 0;
   const uint16_t* kd = nullptr;
+  const uint32_t* kdr = nullptr;
 };
 
 __host__ __device__ inline int64_t n_slices(int64_t n) { return (n + 63) / 64; }
-__host__ __device__ inline int64_t n_blocks(int64_t n) { return (n_slices(n) + 3) / 4; }
+// blocks of a row-parallel kernel: 16 slices (1024 rows) per block
+__host__ __device__ inline int64_t n_blocks(int64_t n) { return (n_slices(n) + 15) / 16; }
 
 // A basis vector held lazily normalised: value_i = raw_i * (*scale) (times
 // s_i when s != nullptr), rounded to the consumer's storage type.
@@ -102,6 +105,7 @@ struct ChildInit {  // state of a child FGMRES level reset by its parent
 hipError_t givens(hipStream_t st, int q, const void* partials, int64_t nb,
                   double* S, int* I, const LevelLayout& L, int j, int solve_y,
                   double inv_bnorm, double* host_out, const ChildInit* child);
+
 hipError_t backsolve(hipStream_t st, int q, double* S, int* I, const LevelLayout& L);
 
 // The basis of one FGMRES level: V_0 = v0, V_j = vb + (j-1) n, each held

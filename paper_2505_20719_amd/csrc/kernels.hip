@@ -1,8 +1,8 @@
 // Solve-phase kernels of libf3r for gfx950.
 //
 // Every sparse kernel works on the SELL-64 layout described in kernels.h:
-// one row per lane of a wave64, a slice of 64 rows per wave, four slices per
-// 256-thread block.  A lane walks its row in CSR column order with separate
+// one row per lane of a wave64 and kR slices per wave (kR rows per lane),
+// 4 waves per block.  A lane walks each row in CSR column order with separate
 // multiply and add (no contraction), so a row sum is rounded exactly like
 // the left-to-right sum that defines the level SpMV (Table 1 precisions;
 // fp32 arithmetic when inputs are narrower, Sec. 4.2).  Reductions are
@@ -24,6 +24,86 @@ template <class TI> __device__ __forceinline__ int64_t col_of(TI d, int64_t row)
 template <> __device__ __forceinline__ int64_t col_of<int16_t>(int16_t d, int64_t row) { return row + d; }
 template <> __device__ __forceinline__ int64_t col_of<int32_t>(int32_t d, int64_t) { return d; }
 
+// The kR rows of one lane: row index, first element of the row in the SELL
+// arrays, slice width, and whether the row exists.  A missing row (past n or
+// past the last slice) is pointed at entry 0 of row 0 so that every load it
+// takes part in stays inside the arrays; its sums are never used.
+struct RowSlot {
+  int64_t row;
+  uint32_t e0;
+  int w;
+  bool ok;
+};
+
+__device__ __forceinline__ void make_slots(const SellDesc& A, int64_t gw, int lane,
+                                           RowSlot (&s)[kR]) {
+#pragma unroll
+  for (int r = 0; r < kR; r++) {
+    const int64_t slice = gw * kR + r;
+    const bool sok = slice < A.ns;
+    const int64_t sl = sok ? slice : 0;
+    const uint32_t o0 = A.off[sl], o1 = A.off[sl + 1];
+    const int64_t row = slice * kWave + lane;
+    const bool ok = sok && row < A.n;
+    s[r].ok = ok;
+    s[r].row = ok ? row : 0;
+    s[r].e0 = ok ? o0 + (uint32_t)lane : 0u;
+    s[r].w = ok ? (int)((o1 - o0) / kWave) : 0;
+  }
+}
+
+// For each of the lane's rows, acc_r += sum over entries k in [kb_r, ke_r)
+// of round(a_k x_{c_k}), left to right.  The loop runs over [lo_r, hi_r), a
+// range that is uniform over the slice (so the loads never wait for per-row
+// data) and contains [kb_r, ke_r).  Entries go in chunks of U: every value
+// and index load of a chunk (all rows) is issued unconditionally, with k
+// clamped into [0, hi_r) (entries the wave reads anyway), then every gather,
+// then the sums, whose predicate is a select.  No load sits behind a branch,
+// so a wave keeps kR x U entries in flight; the order of the sums of a row
+// (and so its rounding) is that of the definition.
+template <int U, class TI, class TV, class Q, class XF>
+__device__ __forceinline__ void rows_sum(const TV* __restrict__ val, const TI* __restrict__ idx,
+                                         const RowSlot (&s)[kR], const int (&lo)[kR],
+                                         const int (&hi)[kR], const int (&kb)[kR],
+                                         const int (&ke)[kR], Q (&acc)[kR], const XF& x,
+                                         bool neg = false) {
+  int it = 0;
+#pragma unroll
+  for (int r = 0; r < kR; r++) it = max(it, hi[r] - lo[r]);
+  for (int i0 = 0; i0 < it; i0 += U) {
+    TV v[kR][U];
+    TI d[kR][U];
+#pragma unroll
+    for (int r = 0; r < kR; r++) {
+#pragma unroll
+      for (int u = 0; u < U; u++) {
+        const int k = max(min(lo[r] + i0 + u, hi[r] - 1), 0);
+        v[r][u] = val[s[r].e0 + (uint32_t)k * 64];
+        d[r][u] = idx[s[r].e0 + (uint32_t)k * 64];
+      }
+    }
+    Q xv[kR][U];
+#pragma unroll
+    for (int r = 0; r < kR; r++) {
+#pragma unroll
+      for (int u = 0; u < U; u++) xv[r][u] = x(col_of<TI>(d[r][u], s[r].row));
+    }
+#pragma unroll
+    for (int r = 0; r < kR; r++) {
+#pragma unroll
+      for (int u = 0; u < U; u++) {
+        const int k = lo[r] + i0 + u;
+        Q m = widen<Q>(v[r][u]);
+        m = neg ? -m : m;
+        const Q t = acc[r] + m * xv[r][u];
+        acc[r] = (k >= kb[r] && k < ke[r]) ? t : acc[r];
+      }
+    }
+  }
+}
+
+constexpr int kUnroll = 4;
+
 // ---------------------------------------------------------------------------
 // vector loaders (value of entry c as the consumer's arithmetic type Q)
 // ---------------------------------------------------------------------------
@@ -33,20 +113,24 @@ template <class TT, class Q> struct LdVec {
   __device__ __forceinline__ Q operator()(int64_t c) const { return widen<Q>(p[c]); }
 };
 
-// round_to<TT>(raw_c * sc) with the product in Q
+// round_to<TT>(raw_c * sc) with the product rounded to Q.  The scale (a Q
+// value) is kept as the double it is stored as and the product is formed in
+// fp64 and rounded once to Q: the exact product of two fp32 values fits in
+// fp64, so this is the fp32 product, and no conversion waits for the scale
+// load before the matrix loads are issued.
 template <class TIN, class TT, class Q> struct LdBasis {
   const TIN* p;
   const double* scp;
   const int* cur;
   int64_t stride;
-  Q sc;
+  double sc;
   __device__ __forceinline__ void init() {
     int64_t j = cur ? *cur : 0;
     p += j * stride;
-    sc = (Q)scp[j];
+    sc = scp[j];
   }
   __device__ __forceinline__ Q operator()(int64_t c) const {
-    Q v = widen<Q>(p[c]) * sc;
+    const Q v = (Q)(widen<double>(p[c]) * sc);
     return widen<Q>(round_to<TT>(v));
   }
 };
@@ -127,46 +211,61 @@ __global__ __launch_bounds__(kBlock) void k_spmv_dots(SellDesc A, const TA* __re
   const int64_t lb = logical_block(nb);
   if (lb >= nb) return;
   const int wave = threadIdx.x / kWave, lane = threadIdx.x & (kWave - 1);
-  const int64_t slice = lb * 4 + wave;
-  const int64_t row = slice * kWave + lane;
-  const bool active = row < A.n;
-  const bool use_alt = fb && *fb;
-  Q yv = 0;
-  if (active) {
-    const TI* idx = (const TI*)A.idx;
-    const uint32_t o0 = A.off[slice];
-    const uint32_t w = (A.off[slice + 1] - o0) / kWave;
-    uint32_t e = o0 + lane;
-    Q acc = 0;
-    if (!use_alt) {
-      for (uint32_t k = 0; k < w; k++, e += kWave)
-        acc = acc + widen<Q>(av[e]) * widen<Q>(x[col_of<TI>(idx[e], row)]);
-    } else {
-      alt.init();
-      for (uint32_t k = 0; k < w; k++, e += kWave)
-        acc = acc + widen<Q>(av[e]) * alt(col_of<TI>(idx[e], row));
-    }
-    const TY yr = round_to<TY>(acc);
-    y[row] = yr;
-    yv = widen<Q>(yr);
+  RowSlot s[kR];
+  make_slots(A, lb * 4 + wave, lane, s);
+  int kb[kR], ke[kR], kc[kR];
+  Q acc[kR];
+#pragma unroll
+  for (int r = 0; r < kR; r++) {
+    kb[r] = 0;
+    ke[r] = s[r].w;
+    kc[r] = max(s[r].w, 1);
+    acc[r] = 0;
+  }
+  const TI* idx = (const TI*)A.idx;
+  if (!(fb && *fb)) {
+    rows_sum<kUnroll, TI>(av, idx, s, kb, kc, kb, ke, acc, LdVec<TX, Q>{x});
+  } else {
+    alt.init();
+    rows_sum<kUnroll, TI>(av, idx, s, kb, kc, kb, ke, acc, alt);
+  }
+  Q yv[kR];
+#pragma unroll
+  for (int r = 0; r < kR; r++) {
+    const TY yr = round_to<TY>(acc[r]);
+    if (s[r].ok) y[s[r].row] = yr;
+    yv[r] = s[r].ok ? widen<Q>(yr) : Q(0);
   }
   for (int c0 = 0; c0 < nv; c0 += kDotChunk) {
     const int cn = nv - c0 < kDotChunk ? nv - c0 : kDotChunk;
-    for (int l = 0; l < cn; l++) {
-      const int ll = c0 + l;
-      const TY* V = ll == 0 ? v0 : vb + (int64_t)(ll - 1) * A.n;
-      Q p = active ? yv * widen<Q>(V[row]) : Q(0);
-      p = wave_sum(p);
-      if (lane == 0) lds[wave][l] = p;
+    for (int l0 = 0; l0 < cn; l0 += 4) {
+      Q vv[4][kR];
+#pragma unroll
+      for (int u = 0; u < 4; u++) {
+        const int ll = c0 + min(l0 + u, cn - 1);
+        const TY* V = ll == 0 ? v0 : vb + (int64_t)(ll - 1) * A.n;
+#pragma unroll
+        for (int r = 0; r < kR; r++) vv[u][r] = widen<Q>(V[s[r].row]);
+      }
+#pragma unroll
+      for (int u = 0; u < 4; u++) {
+        if (l0 + u < cn) {
+          Q p = 0;
+#pragma unroll
+          for (int r = 0; r < kR; r++) p = p + yv[r] * vv[u][r];
+          p = wave_sum(p);
+          if (lane == 0) lds[wave][l0 + u] = p;
+        }
+      }
     }
     __syncthreads();
     if ((int)threadIdx.x < cn) {
       const int t = threadIdx.x;
-      Q s = lds[0][t];
-      s = s + lds[1][t];
-      s = s + lds[2][t];
-      s = s + lds[3][t];
-      part[(int64_t)(c0 + t) * nb + lb] = s;
+      Q sum = lds[0][t];
+      sum = sum + lds[1][t];
+      sum = sum + lds[2][t];
+      sum = sum + lds[3][t];
+      part[(int64_t)(c0 + t) * nb + lb] = sum;
     }
     __syncthreads();
   }
@@ -211,16 +310,15 @@ hipError_t spmv_dots(hipStream_t st, const SellDesc& A, const void* av, int ta, 
 // one-block finalisation of per-block partial sums
 // ---------------------------------------------------------------------------
 template <class Q>
-__global__ __launch_bounds__(kBlock) void k_finalize(const Q* __restrict__ part, int64_t nb,
-                                                     const double* scales, double* dst,
-                                                     const int* stop) {
-  if (stop && *stop) return;
-  __shared__ Q lds[kBlock / kWave];
+__global__ __launch_bounds__(kFinBlock) void k_finalize(const Q* __restrict__ part, int64_t nb,
+                                                        const double* scales, double* dst,
+                                                        const int* stop) {
+  __shared__ Q lds[kFinBlock / kWave];
   const int l = blockIdx.x;
-  Q s = 0;
-  for (int64_t i = threadIdx.x; i < nb; i += kBlock) s = s + part[(int64_t)l * nb + i];
-  s = block_sum(s, lds);
-  if (threadIdx.x == 0) {
+  // partial loads first; the stop flag is read while they are in flight
+  Q s = thread_sum(part + (int64_t)l * nb, nb);
+  s = fin_block_sum(s, lds);
+  if (threadIdx.x == 0 && !(stop && *stop)) {
     if (scales) s = s * (Q)scales[l];
     dst[l] = (double)s;
   }
@@ -230,10 +328,10 @@ hipError_t finalize_sums(hipStream_t st, int q, const void* partials, int64_t nb
                          const double* scales, double* dst, const int* stop) {
   if (count <= 0) return hipSuccess;
   if (q == T64)
-    hipLaunchKernelGGL(k_finalize<double>, dim3(count), dim3(kBlock), 0, st,
+    hipLaunchKernelGGL(k_finalize<double>, dim3(count), dim3(kFinBlock), 0, st,
                        (const double*)partials, nb, scales, dst, stop);
   else
-    hipLaunchKernelGGL(k_finalize<float>, dim3(count), dim3(kBlock), 0, st,
+    hipLaunchKernelGGL(k_finalize<float>, dim3(count), dim3(kFinBlock), 0, st,
                        (const float*)partials, nb, scales, dst, stop);
   return hipGetLastError();
 }
@@ -247,35 +345,55 @@ template <class TY, class Q>
 __global__ __launch_bounds__(kBlock) void k_axpy_norm(int64_t n, TY* __restrict__ w,
                                                       const TY* __restrict__ v0,
                                                       const TY* __restrict__ vb, int nv,
-                                                      const double* h, const double* scales,
+                                                      const double* __restrict__ h,
+                                                      const double* __restrict__ scales,
                                                       Q* __restrict__ part, int64_t nb,
                                                       const int* stop) {
   if (stop && *stop) return;
-  __shared__ Q hs[kMaxM];
-  __shared__ Q sc[kMaxM];
   __shared__ Q lds[kBlock / kWave];
   const int64_t lb = logical_block(nb);
   if (lb >= nb) return;
-  for (int t = threadIdx.x; t < nv; t += kBlock) {
-    hs[t] = (Q)h[t];
-    sc[t] = (Q)scales[t];
+  int64_t row[kR];
+  bool ok[kR];
+  Q acc[kR];
+#pragma unroll
+  for (int r = 0; r < kR; r++) {
+    const int64_t rr = lb * kRowsPerBlock + (int64_t)r * kBlock + threadIdx.x;
+    ok[r] = rr < n;
+    row[r] = ok[r] ? rr : n - 1;
+    acc[r] = widen<Q>(w[row[r]]);
   }
-  __syncthreads();
-  const int64_t row = lb * kRowsPerBlock + threadIdx.x;
-  Q wv = 0;
-  if (row < n) {
-    Q acc = widen<Q>(w[row]);
-    for (int l = 0; l < nv; l++) {
+  for (int l0 = 0; l0 < nv; l0 += 4) {
+    Q vv[4][kR];
+#pragma unroll
+    for (int u = 0; u < 4; u++) {
+      const int l = min(l0 + u, nv - 1);
       const TY* V = l == 0 ? v0 : vb + (int64_t)(l - 1) * n;
-      const Q v = widen<Q>(round_to<TY>(widen<Q>(V[row]) * sc[l]));
-      acc = acc - hs[l] * v;
+#pragma unroll
+      for (int r = 0; r < kR; r++) vv[u][r] = widen<Q>(V[row[r]]);
     }
-    const TY wr = round_to<TY>(acc);
-    w[row] = wr;
-    wv = widen<Q>(wr);
+#pragma unroll
+    for (int u = 0; u < 4; u++) {
+      const int l = min(l0 + u, nv - 1);
+      const Q hl = (Q)h[l], sl = (Q)scales[l];
+#pragma unroll
+      for (int r = 0; r < kR; r++) {
+        const Q v = widen<Q>(round_to<TY>(vv[u][r] * sl));
+        const Q t = acc[r] - hl * v;
+        acc[r] = (l0 + u < nv) ? t : acc[r];
+      }
+    }
   }
-  const Q s = block_sum(wv * wv, lds);
-  if (threadIdx.x == 0) part[lb] = s;
+  Q sq = 0;
+#pragma unroll
+  for (int r = 0; r < kR; r++) {
+    const TY wr = round_to<TY>(acc[r]);
+    if (ok[r]) w[row[r]] = wr;
+    const Q q = ok[r] ? widen<Q>(wr) : Q(0);
+    sq = sq + q * q;
+  }
+  const Q tot = block_sum(sq, lds);
+  if (threadIdx.x == 0) part[lb] = tot;
 }
 
 hipError_t axpy_norm(hipStream_t st, int64_t n, void* w, int tw, const void* v0, const void* vb,
@@ -319,17 +437,11 @@ __device__ void init_child(const ChildInit& c, double scale0, double beta, int s
   for (int i = 0; i < c.m; i++) c.I[I_FB + i] = 0;
 }
 
+// The Givens step j of a level, from the summed squared norm s of the
+// orthogonalised w (thread 0 only).
 template <class Q>
-__global__ __launch_bounds__(kBlock) void k_givens(const Q* __restrict__ part, int64_t nb,
-                                                   double* S, int* I, LevelLayout L, int j,
-                                                   int solve_y, double inv_bnorm,
-                                                   double* host_out, ChildInit child) {
-  __shared__ Q lds[kBlock / kWave];
-  if (I[I_STOP]) return;
-  Q s = 0;
-  for (int64_t i = threadIdx.x; i < nb; i += kBlock) s = s + part[i];
-  s = block_sum(s, lds);
-  if (threadIdx.x != 0) return;
+__device__ void givens_core(Q s, double* S, int* I, const LevelLayout& L, int j, int solve_y,
+                            double inv_bnorm, double* host_out, const ChildInit& child) {
   const int ld = L.m + 1;
   double* H = S + L.H;
   double* Hraw = S + L.Hraw;
@@ -383,15 +495,27 @@ __global__ __launch_bounds__(kBlock) void k_givens(const Q* __restrict__ part, i
   if (solve_y || stop) back_substitute<Q>(S, I, L);
 }
 
+template <class Q>
+__global__ __launch_bounds__(kFinBlock) void k_givens(const Q* __restrict__ part, int64_t nb,
+                                                      double* S, int* I, LevelLayout L, int j,
+                                                      int solve_y, double inv_bnorm,
+                                                      double* host_out, ChildInit child) {
+  __shared__ Q lds[kFinBlock / kWave];
+  Q s = thread_sum(part, nb);
+  s = fin_block_sum(s, lds);
+  if (threadIdx.x != 0 || I[I_STOP]) return;
+  givens_core<Q>(s, S, I, L, j, solve_y, inv_bnorm, host_out, child);
+}
+
 hipError_t givens(hipStream_t st, int q, const void* partials, int64_t nb, double* S, int* I,
                   const LevelLayout& L, int j, int solve_y, double inv_bnorm, double* host_out,
                   const ChildInit* child) {
   ChildInit c = child ? *child : ChildInit{};
   if (q == T64)
-    hipLaunchKernelGGL(k_givens<double>, dim3(1), dim3(kBlock), 0, st, (const double*)partials,
+    hipLaunchKernelGGL(k_givens<double>, dim3(1), dim3(kFinBlock), 0, st, (const double*)partials,
                        nb, S, I, L, j, solve_y, inv_bnorm, host_out, c);
   else
-    hipLaunchKernelGGL(k_givens<float>, dim3(1), dim3(kBlock), 0, st, (const float*)partials, nb,
+    hipLaunchKernelGGL(k_givens<float>, dim3(1), dim3(kFinBlock), 0, st, (const float*)partials, nb,
                        S, I, L, j, solve_y, inv_bnorm, host_out, c);
   return hipGetLastError();
 }
@@ -427,30 +551,48 @@ __global__ __launch_bounds__(kBlock) void k_combine(int64_t n, const TZ* __restr
     fbs[t] = fb ? fb[t] : 0;
   }
   __syncthreads();
-  const int64_t row = lb * kRowsPerBlock + threadIdx.x;
-  if (row >= n) return;
-  Q acc = 0;
-  for (int j = 0; j < meff; j++) {
-    const Q zv = fbs[j] ? alt.get(j, row) : widen<Q>(Z[(int64_t)j * n + row]);
-    acc = acc + ys[j] * zv;
-  }
+  int anyfb = 0;
+  for (int j = 0; j < meff; j++) anyfb |= fbs[j];
   const int ci = cur ? *cur : 0;
   const int64_t o = (int64_t)ci * n;
-  bool fin;
-  if (s) {
-    // consumer on the unscaled outermost system: z = s_i u_i in fp64
-    const double v = s[row] * widen<double>(round_to<TV>(acc));
-    double* od = (double*)out + o;
-    const double r = accumulate ? od[row] + v : v;
-    od[row] = r;
-    fin = isfinite(r);
-  } else {
-    TV* ov = (TV*)out + o;
-    const TV r = accumulate ? round_to<TV>(widen<Q>(ov[row]) + acc) : round_to<TV>(acc);
-    ov[row] = r;
-    fin = finite_val(r);
+#pragma unroll
+  for (int r = 0; r < kR; r++) {
+    const int64_t row = lb * kRowsPerBlock + (int64_t)r * kBlock + threadIdx.x;
+    if (row >= n) continue;
+    Q acc = 0;
+    if (!anyfb) {
+      for (int j0 = 0; j0 < meff; j0 += 8) {
+        Q zz[8];
+#pragma unroll
+        for (int u = 0; u < 8; u++) zz[u] = widen<Q>(Z[(int64_t)min(j0 + u, meff - 1) * n + row]);
+#pragma unroll
+        for (int u = 0; u < 8; u++) {
+          const Q t = acc + ys[min(j0 + u, meff - 1)] * zz[u];
+          acc = (j0 + u < meff) ? t : acc;
+        }
+      }
+    } else {
+      for (int j = 0; j < meff; j++) {
+        const Q zv = fbs[j] ? alt.get(j, row) : widen<Q>(Z[(int64_t)j * n + row]);
+        acc = acc + ys[j] * zv;
+      }
+    }
+    bool fin;
+    if (s) {
+      // consumer on the unscaled outermost system: z = s_i u_i in fp64
+      const double v = s[row] * widen<double>(round_to<TV>(acc));
+      double* od = (double*)out + o;
+      const double rv = accumulate ? od[row] + v : v;
+      od[row] = rv;
+      fin = isfinite(rv);
+    } else {
+      TV* ov = (TV*)out + o;
+      const TV rv = accumulate ? round_to<TV>(widen<Q>(ov[row]) + acc) : round_to<TV>(acc);
+      ov[row] = rv;
+      fin = finite_val(rv);
+    }
+    if (out_fb && !fin) atomicOr(out_fb + ci, 1);
   }
-  if (out_fb && !fin) atomicOr(out_fb + ci, 1);
 }
 
 hipError_t combine(hipStream_t st, int64_t n, const void* Z, int tz, int tv, const double* y,
@@ -488,15 +630,19 @@ __global__ __launch_bounds__(kBlock) void k_entry(int64_t n, LD ld, TO* __restri
   __shared__ Q lds[kBlock / kWave];
   const int64_t lb = logical_block(nb);
   if (lb >= nb) return;
-  const int64_t row = lb * kRowsPerBlock + threadIdx.x;
-  Q v = 0;
-  if (row < n) {
-    ld.init();
-    const TO o = round_to<TO>(ld(row));
-    out[row] = o;
-    v = widen<Q>(o);
+  ld.init();
+  Q sq = 0;
+#pragma unroll
+  for (int r = 0; r < kR; r++) {
+    const int64_t row = lb * kRowsPerBlock + (int64_t)r * kBlock + threadIdx.x;
+    if (row < n) {
+      const TO o = round_to<TO>(ld(row));
+      out[row] = o;
+      const Q v = widen<Q>(o);
+      sq = sq + v * v;
+    }
   }
-  const Q s = block_sum(v * v, lds);
+  const Q s = block_sum(sq, lds);
   if (threadIdx.x == 0) part[lb] = s;
 }
 
@@ -516,7 +662,7 @@ hipError_t entry_cast(hipStream_t st, int64_t n, const Basis& in, void* out, int
     return with_type(in.type, [&](auto pi) -> hipError_t {
       using TIN = TYPE_OF(pi);
       using QQ = wider_t<TIN, TO>;
-      LdBasis<TIN, TO, QQ> ld{(const TIN*)in.raw, in.scale, in.cur, in.stride, (QQ)0};
+      LdBasis<TIN, TO, QQ> ld{(const TIN*)in.raw, in.scale, in.cur, in.stride, 0.0};
       hipLaunchKernelGGL((k_entry<LdBasis<TIN, TO, QQ>, TO, Q>), grid_for(n), dim3(kBlock), 0, st, n,
                          ld, (TO*)out, (Q*)partials, nb, parent_stop);
       return hipGetLastError();
@@ -525,10 +671,10 @@ hipError_t entry_cast(hipStream_t st, int64_t n, const Basis& in, void* out, int
 }
 
 template <class Q>
-__global__ __launch_bounds__(kBlock) void k_entry_fin(const Q* __restrict__ part, int64_t nb,
-                                                      ChildInit c, ChildInit child,
-                                                      const int* pstop) {
-  __shared__ Q lds[kBlock / kWave];
+__global__ __launch_bounds__(kFinBlock) void k_entry_fin(const Q* __restrict__ part, int64_t nb,
+                                                         ChildInit c, ChildInit child,
+                                                         const int* pstop) {
+  __shared__ Q lds[kFinBlock / kWave];
   if (pstop && *pstop) {
     if (threadIdx.x == 0) {
       init_child(c, 0.0, 0.0, 1);
@@ -536,9 +682,8 @@ __global__ __launch_bounds__(kBlock) void k_entry_fin(const Q* __restrict__ part
     }
     return;
   }
-  Q s = 0;
-  for (int64_t i = threadIdx.x; i < nb; i += kBlock) s = s + part[i];
-  s = block_sum(s, lds);
+  Q s = thread_sum(part, nb);
+  s = fin_block_sum(s, lds);
   if (threadIdx.x == 0) {
     const Q beta = sqrt(s);
     const Q inv = beta > (Q)0 ? (Q)1 / beta : (Q)0;
@@ -553,10 +698,10 @@ hipError_t entry_finalize(hipStream_t st, int q, const void* partials, int64_t n
                           const ChildInit& lev, const ChildInit* child, const int* parent_stop) {
   const ChildInit ch = child ? *child : ChildInit{};
   if (q == T64)
-    hipLaunchKernelGGL(k_entry_fin<double>, dim3(1), dim3(kBlock), 0, st, (const double*)partials,
+    hipLaunchKernelGGL(k_entry_fin<double>, dim3(1), dim3(kFinBlock), 0, st, (const double*)partials,
                        nb, lev, ch, parent_stop);
   else
-    hipLaunchKernelGGL(k_entry_fin<float>, dim3(1), dim3(kBlock), 0, st, (const float*)partials,
+    hipLaunchKernelGGL(k_entry_fin<float>, dim3(1), dim3(kFinBlock), 0, st, (const float*)partials,
                        nb, lev, ch, parent_stop);
   return hipGetLastError();
 }
@@ -581,21 +726,29 @@ __global__ __launch_bounds__(kBlock) void k_residual64(SellDesc A, const double*
   const int64_t lb = logical_block(nb);
   if (lb >= nb) return;
   const int wave = threadIdx.x / kWave, lane = threadIdx.x & (kWave - 1);
-  const int64_t slice = lb * 4 + wave;
-  const int64_t row = slice * kWave + lane;
-  double rv = 0;
-  if (row < A.n) {
-    const TI* idx = (const TI*)A.idx;
-    const uint32_t o0 = A.off[slice];
-    const uint32_t w = (A.off[slice + 1] - o0) / kWave;
-    uint32_t e = o0 + lane;
-    double acc = 0;
-    for (uint32_t k = 0; k < w; k++, e += kWave) acc = acc + av[e] * x[col_of<TI>(idx[e], row)];
-    rv = b[row] - acc;
-    r[row] = rv;
+  RowSlot s[kR];
+  make_slots(A, lb * 4 + wave, lane, s);
+  int kb[kR], ke[kR], kc[kR];
+  double acc[kR];
+#pragma unroll
+  for (int q = 0; q < kR; q++) {
+    kb[q] = 0;
+    ke[q] = s[q].w;
+    kc[q] = max(s[q].w, 1);
+    acc[q] = 0.0;
   }
-  const double s = block_sum(rv * rv, lds);
-  if (threadIdx.x == 0) part[lb] = s;
+  rows_sum<kUnroll, TI>(av, (const TI*)A.idx, s, kb, kc, kb, ke, acc, LdVec<double, double>{x});
+  double sq = 0.0;
+#pragma unroll
+  for (int q = 0; q < kR; q++) {
+    if (s[q].ok) {
+      const double rv = b[s[q].row] - acc[q];
+      r[s[q].row] = rv;
+      sq = sq + rv * rv;
+    }
+  }
+  const double tot = block_sum(sq, lds);
+  if (threadIdx.x == 0) part[lb] = tot;
 }
 
 hipError_t residual64(hipStream_t st, const SellDesc& A, const double* a64, const double* x,
@@ -609,13 +762,12 @@ hipError_t residual64(hipStream_t st, const SellDesc& A, const double* a64, cons
   });
 }
 
-__global__ __launch_bounds__(kBlock) void k_residual_fin(const double* __restrict__ part, int64_t nb,
-                                                         double* S, int* I, LevelLayout L,
-                                                         double inv_bnorm, double* host_out) {
-  __shared__ double lds[kBlock / kWave];
-  double s = 0;
-  for (int64_t i = threadIdx.x; i < nb; i += kBlock) s = s + part[i];
-  s = block_sum(s, lds);
+__global__ __launch_bounds__(kFinBlock) void k_residual_fin(const double* __restrict__ part, int64_t nb,
+                                                            double* S, int* I, LevelLayout L,
+                                                            double inv_bnorm, double* host_out) {
+  __shared__ double lds[kFinBlock / kWave];
+  double s = thread_sum(part, nb);
+  s = fin_block_sum(s, lds);
   if (threadIdx.x == 0) {
     const double beta = sqrt(s);
     S[L.scale] = beta > 0 ? 1.0 / beta : 0.0;
@@ -634,7 +786,7 @@ __global__ __launch_bounds__(kBlock) void k_residual_fin(const double* __restric
 
 hipError_t residual_finalize(hipStream_t st, const void* partials, int64_t nb, double* S, int* I,
                              const LevelLayout& L, double inv_bnorm, double* host_out) {
-  hipLaunchKernelGGL(k_residual_fin, dim3(1), dim3(kBlock), 0, st, (const double*)partials, nb, S,
+  hipLaunchKernelGGL(k_residual_fin, dim3(1), dim3(kFinBlock), 0, st, (const double*)partials, nb, S,
                      I, L, inv_bnorm, host_out);
   return hipGetLastError();
 }
@@ -645,18 +797,21 @@ __global__ __launch_bounds__(kBlock) void k_dot64(int64_t n, const double* __res
   __shared__ double lds[kBlock / kWave];
   const int64_t lb = logical_block(nb);
   if (lb >= nb) return;
-  const int64_t row = lb * kRowsPerBlock + threadIdx.x;
-  const double v = row < n ? x[row] * y[row] : 0.0;
+  double v = 0.0;
+#pragma unroll
+  for (int r = 0; r < kR; r++) {
+    const int64_t row = lb * kRowsPerBlock + (int64_t)r * kBlock + threadIdx.x;
+    if (row < n) v = v + x[row] * y[row];
+  }
   const double s = block_sum(v, lds);
   if (threadIdx.x == 0) part[lb] = s;
 }
 
-__global__ __launch_bounds__(kBlock) void k_sum_to(const double* __restrict__ part, int64_t nb,
-                                                   double* out) {
-  __shared__ double lds[kBlock / kWave];
-  double s = 0;
-  for (int64_t i = threadIdx.x; i < nb; i += kBlock) s = s + part[i];
-  s = block_sum(s, lds);
+__global__ __launch_bounds__(kFinBlock) void k_sum_to(const double* __restrict__ part, int64_t nb,
+                                                      double* out) {
+  __shared__ double lds[kFinBlock / kWave];
+  double s = thread_sum(part, nb);
+  s = fin_block_sum(s, lds);
   if (threadIdx.x == 0) out[0] = s;
 }
 
@@ -664,7 +819,7 @@ hipError_t dot64_to_host(hipStream_t st, int64_t n, const double* x, const doubl
                          void* partials, double* host_out) {
   const int64_t nb = n_blocks(n);
   hipLaunchKernelGGL(k_dot64, grid_for(n), dim3(kBlock), 0, st, n, x, y, (double*)partials, nb);
-  hipLaunchKernelGGL(k_sum_to, dim3(1), dim3(kBlock), 0, st, (const double*)partials, nb, host_out);
+  hipLaunchKernelGGL(k_sum_to, dim3(1), dim3(kFinBlock), 0, st, (const double*)partials, nb, host_out);
   return hipGetLastError();
 }
 
@@ -680,27 +835,39 @@ __global__ __launch_bounds__(kBlock) void k_mw(SellDesc A, const TM* __restrict_
   const int64_t lb = logical_block(nb);
   if (lb >= nb) return;
   const int wave = threadIdx.x / kWave, lane = threadIdx.x & (kWave - 1);
-  const int64_t slice = lb * 4 + wave;
-  const int64_t row = slice * kWave + lane;
-  if (row >= A.n) return;
+  const int64_t gw = lb * 4 + wave;
+  RowSlot s[kR];
+  make_slots(A, gw, lane, s);
   ld.init();
-  const TI* idx = (const TI*)A.idx;
-  const int kd = A.kd[row];
-  uint32_t e = A.off[slice] + lane;
-  Q acc = 0;
-  for (int k = 0; k < kd; k++, e += kWave) {
-    Q m = widen<Q>(mv[e]);
-    if (neg) m = -m;
-    acc = acc + m * ld(col_of<TI>(idx[e], row));
+  int lo[kR], hi[kR], kb[kR], ke[kR];
+  Q acc[kR];
+#pragma unroll
+  for (int r = 0; r < kR; r++) {
+    const int64_t slice = gw * kR + r;
+    // loop bound from the slice; the row's own diagonal position only masks
+    lo[r] = 0;
+    hi[r] = s[r].ok ? max((int)(A.kdr[slice] >> 16), 1) : 1;
+    kb[r] = 0;
+    ke[r] = s[r].ok ? (int)A.kd[s[r].row] : 0;
+    acc[r] = 0;
   }
-  t[row] = round_to<TT>(acc + ld(row));
+  Q dg[kR];  // the unit-diagonal term, loaded with the matrix entries
+#pragma unroll
+  for (int r = 0; r < kR; r++) dg[r] = ld(s[r].row);
+  rows_sum<kUnroll, TI>(mv, (const TI*)A.idx, s, lo, hi, kb, ke, acc, ld, neg != 0);
+#pragma unroll
+  for (int r = 0; r < kR; r++)
+    if (s[r].ok) t[s[r].row] = round_to<TT>(acc[r] + dg[r]);
 }
 
+// Epilogues of the G sweep.  prefetch(k, row) issues the row-local loads of
+// lane slot k before the row sums so they overlap the matrix loads.
 template <class TT, class Q> struct EpiStore {
   TT* out;
   int* fb;
   __device__ __forceinline__ void init() {}
-  __device__ __forceinline__ void operator()(int64_t r, TT y) const {
+  __device__ __forceinline__ void prefetch(int, int64_t) {}
+  __device__ __forceinline__ void operator()(int, int64_t r, TT y) const {
     out[r] = y;
     if (fb && !finite_val(y)) atomicOr(fb, 1);
   }
@@ -711,7 +878,8 @@ template <class TT, class Q> struct EpiZ1 {
   int* fb;
   Q w;
   __device__ __forceinline__ void init() { w = (Q)(*wp); }
-  __device__ __forceinline__ void operator()(int64_t r, TT y) const {
+  __device__ __forceinline__ void prefetch(int, int64_t) {}
+  __device__ __forceinline__ void operator()(int, int64_t r, TT y) const {
     const TT z = round_to<TT>(w * widen<Q>(y));
     out[r] = z;
     if (fb && !finite_val(z)) atomicOr(fb, 1);
@@ -723,9 +891,11 @@ template <class TT, class Q> struct EpiZK {
   const double* wp;
   int* fb;
   Q w;
+  Q zv[kR];
   __device__ __forceinline__ void init() { w = (Q)(*wp); }
-  __device__ __forceinline__ void operator()(int64_t r, TT y) const {
-    const TT z = round_to<TT>(widen<Q>(zp[r]) + w * widen<Q>(y));
+  __device__ __forceinline__ void prefetch(int k, int64_t r) { zv[k] = widen<Q>(zp[r]); }
+  __device__ __forceinline__ void operator()(int k, int64_t r, TT y) const {
+    const TT z = round_to<TT>(zv[k] + w * widen<Q>(y));
     out[r] = z;
     if (fb && !finite_val(z)) atomicOr(fb, 1);
   }
@@ -742,7 +912,8 @@ struct EpiS64 {
       if (fb) fb += *cur;
     }
   }
-  __device__ __forceinline__ void operator()(int64_t r, double y) const {
+  __device__ __forceinline__ void prefetch(int, int64_t) {}
+  __device__ __forceinline__ void operator()(int, int64_t r, double y) const {
     const double z = s[r] * y;
     out[r] = z;
     if (fb && !isfinite(z)) atomicOr(fb, 1);
@@ -757,22 +928,28 @@ __global__ __launch_bounds__(kBlock) void k_mg(SellDesc A, const TM* __restrict_
   const int64_t lb = logical_block(nb);
   if (lb >= nb) return;
   const int wave = threadIdx.x / kWave, lane = threadIdx.x & (kWave - 1);
-  const int64_t slice = lb * 4 + wave;
-  const int64_t row = slice * kWave + lane;
-  if (row >= A.n) return;
+  const int64_t gw = lb * 4 + wave;
+  RowSlot s[kR];
+  make_slots(A, gw, lane, s);
   epi.init();
-  const TI* idx = (const TI*)A.idx;
-  const int kd = A.kd[row];
-  const uint32_t o0 = A.off[slice];
-  const int w = (int)((A.off[slice + 1] - o0) / kWave);
-  uint32_t e = o0 + (uint32_t)(kd + 1) * kWave + lane;
-  Q acc = gd * widen<Q>(t[row]);
-  for (int k = kd + 1; k < w; k++, e += kWave) {
-    Q m = widen<Q>(mv[e]);
-    if (neg) m = -m;
-    acc = acc + m * widen<Q>(t[col_of<TI>(idx[e], row)]);
+  int lo[kR], hi[kR], kb[kR], ke[kR];
+  Q acc[kR];
+#pragma unroll
+  for (int r = 0; r < kR; r++) {
+    const int64_t slice = gw * kR + r;
+    const int kd = s[r].ok ? (int)A.kd[s[r].row] : 0;
+    // loop from just after the slice's smallest diagonal position
+    lo[r] = s[r].ok ? (int)(A.kdr[slice] & 0xffffu) + 1 : 0;
+    hi[r] = s[r].ok ? s[r].w : 1;
+    kb[r] = s[r].ok ? kd + 1 : 0;
+    ke[r] = s[r].ok ? s[r].w : 0;
+    acc[r] = gd * widen<Q>(t[s[r].row]);
+    epi.prefetch(r, s[r].row);
   }
-  epi(row, round_to<TT>(acc));
+  rows_sum<kUnroll, TI>(mv, (const TI*)A.idx, s, lo, hi, kb, ke, acc, LdVec<TT, Q>{t}, neg != 0);
+#pragma unroll
+  for (int r = 0; r < kR; r++)
+    if (s[r].ok) epi(r, s[r].row, round_to<TT>(acc[r]));
 }
 
 template <class TM, class TT> constexpr bool ok_m() {
@@ -812,7 +989,7 @@ hipError_t m_apply_w(hipStream_t st, const SellDesc& A, const void* mv, int tm, 
           return with_type(in.type, [&](auto pin) -> hipError_t {
             using TIN = TYPE_OF(pin);
             using QQ = wider_t<TIN, Q>;
-            LdBasis<TIN, TT, QQ> ld{(const TIN*)in.raw, in.scale, in.cur, in.stride, (QQ)0};
+            LdBasis<TIN, TT, QQ> ld{(const TIN*)in.raw, in.scale, in.cur, in.stride, 0.0};
             hipLaunchKernelGGL((k_mw<TI, TM, TT, QQ, LdBasis<TIN, TT, QQ>>), grid_for(A.n),
                                dim3(kBlock), 0, st, A, (const TM*)mv, neg, ld, (TT*)t, stop, cntr, nb);
             return hipGetLastError();
@@ -879,18 +1056,25 @@ __global__ __launch_bounds__(kBlock) void k_rres(SellDesc A, const TA* __restric
   const int64_t lb = logical_block(nb);
   if (lb >= nb) return;
   const int wave = threadIdx.x / kWave, lane = threadIdx.x & (kWave - 1);
-  const int64_t slice = lb * 4 + wave;
-  const int64_t row = slice * kWave + lane;
-  if (row >= A.n) return;
+  RowSlot s[kR];
+  make_slots(A, lb * 4 + wave, lane, s);
   ld.init();
-  const TI* idx = (const TI*)A.idx;
-  const uint32_t o0 = A.off[slice];
-  const uint32_t w = (A.off[slice + 1] - o0) / kWave;
-  uint32_t e = o0 + lane;
-  Q acc = 0;
-  for (uint32_t k = 0; k < w; k++, e += kWave)
-    acc = acc + widen<Q>(av[e]) * widen<Q>(z[col_of<TI>(idx[e], row)]);
-  r[row] = round_to<TR>(ld(row) - acc);
+  int kb[kR], ke[kR], kc[kR];
+  Q acc[kR];
+#pragma unroll
+  for (int q = 0; q < kR; q++) {
+    kb[q] = 0;
+    ke[q] = s[q].w;
+    kc[q] = max(s[q].w, 1);
+    acc[q] = 0;
+  }
+  Q vr[kR];  // v at the row, loaded with the matrix entries
+#pragma unroll
+  for (int q = 0; q < kR; q++) vr[q] = ld(s[q].row);
+  rows_sum<kUnroll, TI>(av, (const TI*)A.idx, s, kb, kc, kb, ke, acc, LdVec<TR, Q>{z});
+#pragma unroll
+  for (int q = 0; q < kR; q++)
+    if (s[q].ok) r[s[q].row] = round_to<TR>(vr[q] - acc[q]);
 }
 
 hipError_t rich_residual(hipStream_t st, const SellDesc& A, const void* av, int ta,
@@ -909,7 +1093,7 @@ hipError_t rich_residual(hipStream_t st, const SellDesc& A, const void* av, int 
           return with_type(in.type, [&](auto pin) -> hipError_t {
             using TIN = TYPE_OF(pin);
             using QQ = wider_t<TIN, Q>;
-            LdBasis<TIN, TR, QQ> ld{(const TIN*)in.raw, in.scale, in.cur, in.stride, (QQ)0};
+            LdBasis<TIN, TR, QQ> ld{(const TIN*)in.raw, in.scale, in.cur, in.stride, 0.0};
             hipLaunchKernelGGL((k_rres<TI, TA, TR, QQ, LdBasis<TIN, TR, QQ>>), grid_for(A.n),
                                dim3(kBlock), 0, st, A, (const TA*)av, ld, (const TR*)z, (TR*)r, stop,
                                nb);
@@ -931,21 +1115,27 @@ __global__ __launch_bounds__(kBlock) void k_rtdots(SellDesc A, const TA* __restr
   const int64_t lb = logical_block(nb);
   if (lb >= nb) return;
   const int wave = threadIdx.x / kWave, lane = threadIdx.x & (kWave - 1);
-  const int64_t slice = lb * 4 + wave;
-  const int64_t row = slice * kWave + lane;
+  RowSlot s[kR];
+  make_slots(A, lb * 4 + wave, lane, s);
+  rld.init();
+  int kb[kR], ke[kR], kc[kR];
+  Q acc[kR];
+#pragma unroll
+  for (int q = 0; q < kR; q++) {
+    kb[q] = 0;
+    ke[q] = s[q].w;
+    kc[q] = max(s[q].w, 1);
+    acc[q] = 0;
+  }
+  rows_sum<kUnroll, TI>(av, (const TI*)A.idx, s, kb, kc, kb, ke, acc, LdVec<TR, Q>{y});
   Q p1 = 0, p2 = 0;
-  if (row < A.n) {
-    rld.init();
-    const TI* idx = (const TI*)A.idx;
-    const uint32_t o0 = A.off[slice];
-    const uint32_t w = (A.off[slice + 1] - o0) / kWave;
-    uint32_t e = o0 + lane;
-    Q t = 0;
-    for (uint32_t k = 0; k < w; k++, e += kWave)
-      t = t + widen<Q>(av[e]) * widen<Q>(y[col_of<TI>(idx[e], row)]);
-    const Q rv = rld(row);
-    p1 = rv * t;
-    p2 = t * t;
+#pragma unroll
+  for (int q = 0; q < kR; q++) {
+    if (s[q].ok) {
+      const Q rv = rld(s[q].row);
+      p1 = p1 + rv * acc[q];
+      p2 = p2 + acc[q] * acc[q];
+    }
   }
   const Q s1 = block_sum(p1, lds);
   const Q s2 = block_sum(p2, lds);
@@ -979,7 +1169,7 @@ hipError_t rich_tdots(hipStream_t st, const SellDesc& A, const void* av, int ta,
             if constexpr (!std::is_same<wider_t<TIN, Q>, Q>::value) {
               return hipErrorInvalidValue;
             } else {
-              LdBasis<TIN, TR, Q> ld{(const TIN*)rin.raw, rin.scale, rin.cur, rin.stride, (Q)0};
+              LdBasis<TIN, TR, Q> ld{(const TIN*)rin.raw, rin.scale, rin.cur, rin.stride, 0.0};
               hipLaunchKernelGGL((k_rtdots<TI, TA, TR, Q, LdBasis<TIN, TR, Q>>), grid_for(A.n),
                                  dim3(kBlock), 0, st, A, (const TA*)av, (const TR*)y, ld,
                                  (Q*)partials, nb, stop);
@@ -993,18 +1183,13 @@ hipError_t rich_tdots(hipStream_t st, const SellDesc& A, const void* av, int ta,
 }
 
 template <class Q>
-__global__ __launch_bounds__(kBlock) void k_romega(const Q* __restrict__ part, int64_t nb,
-                                                   double* om, double* wcur,
-                                                   const int64_t* cntr, int c, const int* stop) {
+__global__ __launch_bounds__(kFinBlock) void k_romega(const Q* __restrict__ part, int64_t nb,
+                                                      double* om, double* wcur,
+                                                      const int64_t* cntr, int c, const int* stop) {
   if (stop && *stop) return;
-  __shared__ Q lds[kBlock / kWave];
-  Q a = 0, b = 0;
-  for (int64_t i = threadIdx.x; i < nb; i += kBlock) {
-    a = a + part[i];
-    b = b + part[nb + i];
-  }
-  const Q num = block_sum(a, lds);
-  const Q den = block_sum(b, lds);
+  __shared__ Q lds[kFinBlock / kWave];
+  const Q num = fin_block_sum(thread_sum(part, nb), lds);
+  const Q den = fin_block_sum(thread_sum(part + nb, nb), lds);
   if (threadIdx.x == 0) {
     const int64_t l = (*cntr - 1) / c;  // Eq. (5): l = c_ntr / c
     const Q wp = num / den;
@@ -1025,10 +1210,10 @@ hipError_t rich_omega(hipStream_t st, int q, const void* partials, int64_t nb, d
                       double* wcur, const int64_t* cntr, int c, const int* stop) {
   if (c <= 0) return hipErrorInvalidValue;
   if (q == T64)
-    hipLaunchKernelGGL(k_romega<double>, dim3(1), dim3(kBlock), 0, st, (const double*)partials, nb,
+    hipLaunchKernelGGL(k_romega<double>, dim3(1), dim3(kFinBlock), 0, st, (const double*)partials, nb,
                        omega_k, wcur, cntr, c, stop);
   else
-    hipLaunchKernelGGL(k_romega<float>, dim3(1), dim3(kBlock), 0, st, (const float*)partials, nb,
+    hipLaunchKernelGGL(k_romega<float>, dim3(1), dim3(kFinBlock), 0, st, (const float*)partials, nb,
                        omega_k, wcur, cntr, c, stop);
   return hipGetLastError();
 }
@@ -1041,13 +1226,16 @@ __global__ __launch_bounds__(kBlock) void k_zupd(int64_t n, const TR* __restrict
   if (stop && *stop) return;
   const int64_t lb = logical_block(nb);
   if (lb >= nb) return;
-  const int64_t row = lb * kRowsPerBlock + threadIdx.x;
-  if (row >= n) return;
   const Q w = (Q)(*wcur);
-  const Q p = w * widen<Q>(y[row]);
-  const TR zz = zp ? round_to<TR>(widen<Q>(zp[row]) + p) : round_to<TR>(p);
-  z[row] = zz;
-  if (fb && !finite_val(zz)) atomicOr(fb, 1);
+#pragma unroll
+  for (int r = 0; r < kR; r++) {
+    const int64_t row = lb * kRowsPerBlock + (int64_t)r * kBlock + threadIdx.x;
+    if (row >= n) continue;
+    const Q p = w * widen<Q>(y[row]);
+    const TR zz = zp ? round_to<TR>(widen<Q>(zp[row]) + p) : round_to<TR>(p);
+    z[row] = zz;
+    if (fb && !finite_val(zz)) atomicOr(fb, 1);
+  }
 }
 
 hipError_t rich_zupdate(hipStream_t st, int64_t n, const void* zprev, const void* y, int tr,

@@ -20,8 +20,10 @@ enum SetupFlags {
 hipError_t row_check(hipStream_t st, int64_t n, const int32_t* rp, const int32_t* ci,
                      const double* val, double* s, uint16_t* kd, int32_t* len, int* flags);
 
-// width[s] = max row length over the 64 rows of slice s
-hipError_t slice_widths(hipStream_t st, int64_t n, const int32_t* len, uint32_t* width);
+// width[s] = max row length, kdr[s] = min | max << 16 of the diagonal
+// positions over the rows of slice s
+hipError_t slice_widths(hipStream_t st, int64_t n, const int32_t* len, const uint16_t* kd,
+                        uint32_t* width, uint32_t* kdr);
 
 struct SellOut {
   void* idx = nullptr;          // int16 offsets or int32 columns

@@ -51,18 +51,27 @@ hipError_t row_check(hipStream_t st, int64_t n, const int32_t* rp, const int32_t
   return hipGetLastError();
 }
 
-__global__ void k_slice_widths(int64_t n, const int32_t* __restrict__ len, uint32_t* __restrict__ w) {
+__global__ void k_slice_widths(int64_t n, const int32_t* __restrict__ len,
+                               const uint16_t* __restrict__ kd, uint32_t* __restrict__ w,
+                               uint32_t* __restrict__ kdr) {
   const int64_t sl = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (sl >= n_slices(n)) return;
   int32_t m = 0;
-  for (int64_t r = sl * 64; r < sl * 64 + 64 && r < n; r++) m = len[r] > m ? len[r] : m;
+  int kmax = 0, kmin = 65535;
+  for (int64_t r = sl * 64; r < sl * 64 + 64 && r < n; r++) {
+    m = len[r] > m ? len[r] : m;
+    kmax = kd[r] > kmax ? kd[r] : kmax;
+    kmin = kd[r] < kmin ? kd[r] : kmin;
+  }
   w[sl] = (uint32_t)m;
+  kdr[sl] = (uint32_t)kmin | ((uint32_t)kmax << 16);
 }
 
-hipError_t slice_widths(hipStream_t st, int64_t n, const int32_t* len, uint32_t* width) {
+hipError_t slice_widths(hipStream_t st, int64_t n, const int32_t* len, const uint16_t* kd,
+                        uint32_t* width, uint32_t* kdr) {
   const int64_t ns = n_slices(n);
   hipLaunchKernelGGL(k_slice_widths, dim3((unsigned)((ns + 255) / 256)), dim3(256), 0, st, n, len,
-                     width);
+                     kd, width, kdr);
   return hipGetLastError();
 }
 
