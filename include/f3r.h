@@ -87,7 +87,7 @@ typedef struct {
   int32_t nlev;                  /* number of solver levels (1..8) */
   f3r_level lev[F3R_MAX_LEVELS]; /* lev[0] is the outermost FGMRES, fp64 */
   int32_t prec_m;                /* storage precision of M (Table 1) */
-  int32_t m_identity;            /* 1: M = I */
+  int32_t m_identity;            /* must be 0 (M = I is not provided) */
   int32_t c;                     /* weight-update cycle of Alg. 1; 0 = never */
   double alpha;                  /* diagonal factor used to build M (Sec. 5.2) */
   double omega_init;             /* initial Richardson weights (Alg. 1: 1) */
@@ -185,6 +185,44 @@ void f3r_destroy(f3r_handle* h);
 
 /* Static English text of a status code. */
 const char* f3r_status_str(f3r_status s);
+
+/* ---- batches of independent systems -------------------------------------
+   Many systems of different sizes solved by one persistent kernel launch:
+   each workgroup of the launch takes the next system from a queue ordered
+   by decreasing size and runs the whole nest of Sec. 4.2 on it, with the
+   per-iteration stopping test of Sec. 5 taken on the device.  The
+   arithmetic of every stored value is that of Table 1, as in f3r_solve;
+   only the summation order of dot products and norms differs. */
+typedef struct f3r_batch f3r_batch;
+
+/* Sets up `count` systems (A: host array of count CSR matrices, each copied
+   and scaled as by f3r_setup).  The parameters must describe the narrow
+   F3R nest: nlev = 4; levels FGMRES (fp64, fp64), FGMRES (fp32, fp32),
+   FGMRES (narrow matrix, fp32 vectors), Richardson (narrow, narrow), with
+   prec_m = narrow, where narrow is F3R_FP16 or F3R_BF16 (the defaults of
+   F3R_VARIANT_FP16 and F3R_VARIANT_BF16); m1 <= 128 and m2, m3, m4 <= 16.
+   Flags: only F3R_USE_X0.  Weights and c_ntr restart for every system and
+   solve (Alg. 1).  Errors as f3r_setup; F3R_ERR_ARG also for parameters
+   outside this set.  *out is NULL on error. */
+f3r_status f3r_setup_batched(int32_t count, const f3r_csr* A, const f3r_params* p,
+                             void* hip_stream, f3r_batch** out);
+
+/* Solves every system: b[i], x[i] are device pointers (n_i doubles) held in
+   host arrays of `count` entries; x[i] is overwritten (or read first with
+   F3R_USE_X0).  infos: NULL or a host array of `count` records (solve_ms is
+   the wall time of the whole batch).  Returns F3R_OK when every system
+   converged, F3R_NOT_CONVERGED when some did not, else the most severe
+   error of any system; the call returns after the launch has finished. */
+f3r_status f3r_solve_batched(f3r_batch* bt, const double* const* b, double* const* x,
+                             double tol, f3r_info* infos);
+
+/* Residual estimates after every outermost iteration of system `sys` in the
+   last batched solve; conventions of f3r_get_history. */
+f3r_status f3r_batch_get_history(const f3r_batch* bt, int32_t sys, double* buf,
+                                 int64_t cap, int64_t* len);
+
+/* Frees every resource of the batch. NULL is allowed. */
+void f3r_batch_destroy(f3r_batch* bt);
 
 /* ---- single steps, for lockstep checks against a reference ------------
    Every vector is a device array of n doubles holding values representable

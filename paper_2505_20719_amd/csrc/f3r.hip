@@ -19,25 +19,13 @@
 #include <vector>
 
 #include "f3r.h"
+#include "host.h"
 #include "kernels.h"
 #include "setup.h"
 
 using namespace f3r;
 
 namespace {
-
-struct DevErr {
-  hipError_t e;
-};
-#define HIPCHK(x)                              \
-  do {                                         \
-    hipError_t _e = (x);                       \
-    if (_e != hipSuccess) throw DevErr{_e};    \
-  } while (0)
-
-struct StatusErr {
-  f3r_status s;
-};
 
 struct LevelRT {
   f3r_level cfg{};
@@ -108,16 +96,9 @@ struct f3r_handle {
   double probe_ms = 0;
   int64_t probe_n = 0;
   double setup_ms = 0;
-  std::vector<void*> allocs;
+  DevAllocs al;
 
-  void* dalloc(size_t bytes) {
-    void* p = nullptr;
-    if (bytes == 0) bytes = 8;
-    hipError_t e = hipMalloc(&p, bytes);
-    if (e != hipSuccess) throw StatusErr{F3R_ERR_NOMEM};
-    allocs.push_back(p);
-    return p;
-  }
+  void* dalloc(size_t bytes) { return al.get(bytes); }
 };
 
 namespace {
@@ -163,6 +144,7 @@ f3r_status check_params(const f3r_params* p) {
   if (width(plast) == 1 && p->prec_m != plast) return F3R_ERR_ARG;
   if (!(p->alpha > 0.0) || !std::isfinite(p->alpha)) return F3R_ERR_ARG;
   if (p->c < 0 || p->max_outer < 1) return F3R_ERR_ARG;
+  if (p->m_identity != 0) return F3R_ERR_ARG;  // M = I is not provided
   return F3R_OK;
 }
 
@@ -777,7 +759,7 @@ void f3r_destroy(f3r_handle* h) {
   if (h->st) (void)hipStreamSynchronize(h->st);
   destroy_graphs(h);
   for (hipEvent_t e : h->ev) (void)hipEventDestroy(e);
-  for (void* p : h->allocs) (void)hipFree(p);
+  h->al.release_all();
   if (h->hpin) (void)hipHostFree(h->hpin);
   if (h->cap) (void)hipStreamDestroy(h->cap);
   delete h;
@@ -787,13 +769,8 @@ f3r_status f3r_setup(const f3r_csr* A, const f3r_params* p, void* hip_stream, f3
   if (!out) return F3R_ERR_ARG;
   *out = nullptr;
   if (!A || !A->row_ptr || !A->col_idx || !A->val || A->n <= 0 || A->nnz < A->n) return F3R_ERR_ARG;
-  if (A->n >= ((int64_t)1 << 31) - 64 || A->nnz >= ((int64_t)1 << 31)) return F3R_ERR_ARG;
   f3r_status ps = check_params(p);
   if (ps != F3R_OK) return ps;
-  if (A->row_ptr[0] != 0 || A->row_ptr[A->n] != A->nnz) return F3R_ERR_MATRIX;
-  // every row range must lie inside [0, nnz] before a kernel walks it
-  for (int64_t i = 0; i < A->n; i++)
-    if (A->row_ptr[i + 1] < A->row_ptr[i]) return F3R_ERR_MATRIX;
   f3r_handle* h = new f3r_handle();
   h->p = *p;
   h->n = A->n;
@@ -803,90 +780,27 @@ f3r_status f3r_setup(const f3r_csr* A, const f3r_params* p, void* hip_stream, f3
   f3r_status st = guarded(h, nullptr, [&]() -> f3r_status {
     HIPCHK(hipGetDevice(&h->device));
     HIPCHK(hipStreamCreateWithFlags(&h->cap, hipStreamNonBlocking));
-    const int64_t n = A->n, nnz = A->nnz, ns = n_slices(n);
-    int32_t* ci = (int32_t*)h->dalloc((size_t)nnz * 4);
-    double* val = (double*)h->dalloc((size_t)nnz * 8);
-    h->rp = (int32_t*)h->dalloc((size_t)(n + 1) * 4);
-    HIPCHK(hipMemcpyAsync(h->rp, A->row_ptr, (size_t)(n + 1) * 4, hipMemcpyHostToDevice, h->st));
-    HIPCHK(hipMemcpyAsync(ci, A->col_idx, (size_t)nnz * 4, hipMemcpyHostToDevice, h->st));
-    HIPCHK(hipMemcpyAsync(val, A->val, (size_t)nnz * 8, hipMemcpyHostToDevice, h->st));
-    h->s = (double*)h->dalloc((size_t)n * 8);
-    h->kd = (uint16_t*)h->dalloc((size_t)n * 2);
-    int32_t* len = (int32_t*)h->dalloc((size_t)n * 4);
-    int* flags = (int*)h->dalloc(sizeof(int));
-    HIPCHK(hipMemsetAsync(flags, 0, sizeof(int), h->st));
-    HIPCHK(row_check(h->st, n, h->rp, ci, val, h->s, h->kd, len, flags));
-    uint32_t* wdev = (uint32_t*)h->dalloc((size_t)ns * 4);
-    h->kdr = (uint32_t*)h->dalloc((size_t)ns * 4);
-    HIPCHK(slice_widths(h->st, n, len, h->kd, wdev, h->kdr));
-    int hflags = 0;
-    HIPCHK(hipMemcpyAsync(&hflags, flags, sizeof(int), hipMemcpyDeviceToHost, h->st));
-    std::vector<uint32_t> w((size_t)ns), off((size_t)ns + 1);
-    HIPCHK(hipMemcpyAsync(w.data(), wdev, (size_t)ns * 4, hipMemcpyDeviceToHost, h->st));
-    HIPCHK(hipStreamSynchronize(h->st));
-    if (hflags & SF_MATRIX) return F3R_ERR_MATRIX;
-    if (hflags & SF_LONGROW) return F3R_ERR_ARG;
-    uint64_t acc = 0;
-    for (int64_t sidx = 0; sidx < ns; sidx++) {
-      off[(size_t)sidx] = (uint32_t)acc;
-      acc += (uint64_t)w[(size_t)sidx] * 64;
-      if (acc >= 0xFFFFFFF0ull) return F3R_ERR_ARG;
-    }
-    off[(size_t)ns] = (uint32_t)acc;
-    h->padded = (int64_t)acc;
-    h->off = (uint32_t*)h->dalloc((size_t)(ns + 1) * 4);
-    HIPCHK(hipMemcpyAsync(h->off, off.data(), (size_t)(ns + 1) * 4, hipMemcpyHostToDevice, h->st));
-    SellOut so;
-    so.idx16 = (hflags & SF_IDX32) ? 0 : 1;
-    so.idx = h->dalloc((size_t)acc * (so.idx16 ? 2 : 4));
-    so.a64 = (double*)h->dalloc((size_t)acc * 8);
-    so.alpha = p->alpha;
-    h->m_shared = p->alpha == 1.0;
-    bool need[4] = {true, false, false, false};  // fp64 copy: fp64 levels and the comparison solver
-    int mask = 0;
-    for (int d = 1; d < p->nlev; d++) {
-      need[p->lev[d].prec_a] = true;
-      mask |= 1 << p->lev[d].prec_a;
-    }
-    if (h->m_shared) {
-      need[p->prec_m] = true;
-      mask |= 1 << p->prec_m;
-    } else {
-      so.mv[p->prec_m] = h->dalloc((size_t)acc * tsz(p->prec_m));
-      if (p->prec_m != T64) so.mv[T64] = h->dalloc((size_t)acc * 8);
-      mask |= 1 << p->prec_m;
-    }
-    for (int t = 0; t < 4; t++)
-      if (need[t]) so.ah[t] = h->dalloc((size_t)acc * tsz(t));
-    so.range_mask = mask;
-    HIPCHK(to_sell(h->st, n, h->rp, ci, val, h->s, h->off, len, so, flags));
-    double* gd = (double*)h->dalloc(4 * sizeof(double));
-    HIPCHK(m_diag(h->st, p->alpha, gd));
-    HIPCHK(hipMemcpyAsync(h->gd, gd, 4 * sizeof(double), hipMemcpyDeviceToHost, h->st));
-    HIPCHK(hipMemcpyAsync(&hflags, flags, sizeof(int), hipMemcpyDeviceToHost, h->st));
-    HIPCHK(hipStreamSynchronize(h->st));
-    if (hflags & SF_RANGE) return F3R_ERR_RANGE;
-    h->idx = so.idx;
-    h->a64 = so.a64;
+    // fp64 copy: fp64 levels and the comparison solver
+    const bool need[4] = {true, false, false, false};
+    MatrixDev m;
+    const f3r_status bs = build_matrix(h->st, A, p, need, h->al, m);
+    if (bs != F3R_OK) return bs;
+    const int64_t n = A->n;
+    h->A = m.A;
+    h->off = (uint32_t*)m.A.off;
+    h->idx = (void*)m.A.idx;
+    h->kd = (uint16_t*)m.A.kd;
+    h->kdr = (uint32_t*)m.A.kdr;
+    h->rp = m.rp;
+    h->a64 = m.a64;
     for (int t = 0; t < 4; t++) {
-      h->ah[t] = so.ah[t];
-      h->mv[t] = so.mv[t];
+      h->ah[t] = m.ah[t];
+      h->mv[t] = m.mv[t];
+      h->gd[t] = m.gd[t];
     }
-    h->A.n = n;
-    h->A.ns = ns;
-    h->A.off = h->off;
-    h->A.idx = h->idx;
-    h->A.idx16 = so.idx16;
-    h->A.kd = h->kd;
-    h->A.kdr = h->kdr;
-    // the CSR copies are no longer needed
-    HIPCHK(hipFree(ci));
-    HIPCHK(hipFree(val));
-    HIPCHK(hipFree(len));
-    HIPCHK(hipFree(wdev));
-    h->allocs.erase(std::remove_if(h->allocs.begin(), h->allocs.end(),
-                                   [&](void* q) { return q == ci || q == val || q == len || q == wdev; }),
-                    h->allocs.end());
+    h->m_shared = m.m_shared;
+    h->s = m.s;
+    h->padded = m.padded;
     // workspaces
     int maxdots = p->lev[0].m + 2;
     maxdots = std::max(maxdots, 66);
@@ -1103,8 +1017,7 @@ f3r_status f3r_debug_level_values(f3r_handle* h, int32_t prec, double* vals_host
     HIPCHK(sell_to_csr_values(h->st, h->n, h->rp, h->off, h->ah[prec], prec, d));
     HIPCHK(hipMemcpyAsync(vals_host, d, (size_t)h->nnz * 8, hipMemcpyDeviceToHost, h->st));
     HIPCHK(hipStreamSynchronize(h->st));
-    HIPCHK(hipFree(d));
-    h->allocs.pop_back();
+    h->al.release(d);
     return F3R_OK;
   });
 }

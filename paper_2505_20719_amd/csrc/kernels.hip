@@ -13,161 +13,9 @@
 
 #include "common.h"
 #include "kernels.h"
+#include "sell.h"
 
 namespace f3r {
-
-template <class T> struct is_dbl : std::is_same<T, double> {};
-template <class A, class B, class C = float> using wider_t =
-    typename std::conditional<is_dbl<A>::value || is_dbl<B>::value || is_dbl<C>::value, double, float>::type;
-
-template <class TI> __device__ __forceinline__ int64_t col_of(TI d, int64_t row);
-template <> __device__ __forceinline__ int64_t col_of<int16_t>(int16_t d, int64_t row) { return row + d; }
-template <> __device__ __forceinline__ int64_t col_of<int32_t>(int32_t d, int64_t) { return d; }
-
-// The kR rows of one lane: row index, first element of the row in the SELL
-// arrays, slice width, and whether the row exists.  A missing row (past n or
-// past the last slice) is pointed at entry 0 of row 0 so that every load it
-// takes part in stays inside the arrays; its sums are never used.
-struct RowSlot {
-  int64_t row;
-  uint32_t e0;
-  int w;
-  bool ok;
-};
-
-__device__ __forceinline__ void make_slots(const SellDesc& A, int64_t gw, int lane,
-                                           RowSlot (&s)[kR]) {
-#pragma unroll
-  for (int r = 0; r < kR; r++) {
-    const int64_t slice = gw * kR + r;
-    const bool sok = slice < A.ns;
-    const int64_t sl = sok ? slice : 0;
-    const uint32_t o0 = A.off[sl], o1 = A.off[sl + 1];
-    const int64_t row = slice * kWave + lane;
-    const bool ok = sok && row < A.n;
-    s[r].ok = ok;
-    s[r].row = ok ? row : 0;
-    s[r].e0 = ok ? o0 + (uint32_t)lane : 0u;
-    s[r].w = ok ? (int)((o1 - o0) / kWave) : 0;
-  }
-}
-
-// For each of the lane's rows, acc_r += sum over entries k in [kb_r, ke_r)
-// of round(a_k x_{c_k}), left to right.  The loop runs over [lo_r, hi_r), a
-// range that is uniform over the slice (so the loads never wait for per-row
-// data) and contains [kb_r, ke_r).  Entries go in chunks of U: every value
-// and index load of a chunk (all rows) is issued unconditionally, with k
-// clamped into [0, hi_r) (entries the wave reads anyway), then every gather,
-// then the sums, whose predicate is a select.  No load sits behind a branch,
-// so a wave keeps kR x U entries in flight; the order of the sums of a row
-// (and so its rounding) is that of the definition.
-template <int U, class TI, class TV, class Q, class XF>
-__device__ __forceinline__ void rows_sum(const TV* __restrict__ val, const TI* __restrict__ idx,
-                                         const RowSlot (&s)[kR], const int (&lo)[kR],
-                                         const int (&hi)[kR], const int (&kb)[kR],
-                                         const int (&ke)[kR], Q (&acc)[kR], const XF& x,
-                                         bool neg = false) {
-  int it = 0;
-#pragma unroll
-  for (int r = 0; r < kR; r++) it = max(it, hi[r] - lo[r]);
-  for (int i0 = 0; i0 < it; i0 += U) {
-    TV v[kR][U];
-    TI d[kR][U];
-#pragma unroll
-    for (int r = 0; r < kR; r++) {
-#pragma unroll
-      for (int u = 0; u < U; u++) {
-        const int k = max(min(lo[r] + i0 + u, hi[r] - 1), 0);
-        v[r][u] = val[s[r].e0 + (uint32_t)k * 64];
-        d[r][u] = idx[s[r].e0 + (uint32_t)k * 64];
-      }
-    }
-    Q xv[kR][U];
-#pragma unroll
-    for (int r = 0; r < kR; r++) {
-#pragma unroll
-      for (int u = 0; u < U; u++) xv[r][u] = x(col_of<TI>(d[r][u], s[r].row));
-    }
-#pragma unroll
-    for (int r = 0; r < kR; r++) {
-#pragma unroll
-      for (int u = 0; u < U; u++) {
-        const int k = lo[r] + i0 + u;
-        Q m = widen<Q>(v[r][u]);
-        m = neg ? -m : m;
-        const Q t = acc[r] + m * xv[r][u];
-        acc[r] = (k >= kb[r] && k < ke[r]) ? t : acc[r];
-      }
-    }
-  }
-}
-
-constexpr int kUnroll = 4;
-
-// ---------------------------------------------------------------------------
-// vector loaders (value of entry c as the consumer's arithmetic type Q)
-// ---------------------------------------------------------------------------
-template <class TT, class Q> struct LdVec {
-  const TT* p;
-  __device__ __forceinline__ void init() {}
-  __device__ __forceinline__ Q operator()(int64_t c) const { return widen<Q>(p[c]); }
-};
-
-// round_to<TT>(raw_c * sc) with the product rounded to Q.  The scale (a Q
-// value) is kept as the double it is stored as and the product is formed in
-// fp64 and rounded once to Q: the exact product of two fp32 values fits in
-// fp64, so this is the fp32 product, and no conversion waits for the scale
-// load before the matrix loads are issued.
-template <class TIN, class TT, class Q> struct LdBasis {
-  const TIN* p;
-  const double* scp;
-  const int* cur;
-  int64_t stride;
-  double sc;
-  __device__ __forceinline__ void init() {
-    int64_t j = cur ? *cur : 0;
-    p += j * stride;
-    sc = scp[j];
-  }
-  __device__ __forceinline__ Q operator()(int64_t c) const {
-    const Q v = (Q)(widen<double>(p[c]) * sc);
-    return widen<Q>(round_to<TT>(v));
-  }
-};
-
-// round_to<TT>(s_c * (raw_c * sc)) with fp64 products (outermost -> scaled
-// inner system, P(v) = S F(S v))
-template <class TT, class Q> struct LdSBasis {
-  const double* p;
-  const double* scp;
-  const double* s;
-  const int* cur;
-  int64_t stride;
-  double sc;
-  __device__ __forceinline__ void init() {
-    int64_t j = cur ? *cur : 0;
-    p += j * stride;
-    sc = scp[j];
-  }
-  __device__ __forceinline__ Q operator()(int64_t c) const {
-    double v = s[c] * (p[c] * sc);
-    return widen<Q>(round_to<TT>(v));
-  }
-};
-
-// j-th vector of a level basis (V_0 separate, V_j = vb + (j-1) n), used by
-// the non-finite fallback
-template <class TIN, class Q> struct LdLevelBasis {
-  const TIN* v0;
-  const TIN* vb;
-  const double* scales;
-  int64_t n;
-  __device__ __forceinline__ Q get(int j, int64_t c) const {
-    const TIN* V = j == 0 ? v0 : vb + (int64_t)(j - 1) * n;
-    Q v = widen<Q>(V[c]) * (Q)scales[j];
-    return widen<Q>(round_to<TIN>(v));
-  }
-};
 
 template <class F> static hipError_t with_type(int t, F&& f) {
   switch (t) {

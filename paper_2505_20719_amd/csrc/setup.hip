@@ -1,5 +1,8 @@
 // Set-up kernels: one thread per row of the CSR input.
+#include <vector>
+
 #include "common.h"
+#include "host.h"
 #include "kernels.h"
 #include "setup.h"
 
@@ -169,6 +172,104 @@ hipError_t sell_to_csr_values(hipStream_t st, int64_t n, const int32_t* rp, cons
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// host driver of the set-up kernels
+// ---------------------------------------------------------------------------
+f3r_status build_matrix(hipStream_t st, const f3r_csr* A, const f3r_params* p, const bool need_in[4],
+                        DevAllocs& al, MatrixDev& m) {
+  if (!A || !A->row_ptr || !A->col_idx || !A->val || A->n <= 0 || A->nnz < A->n) return F3R_ERR_ARG;
+  if (A->n >= ((int64_t)1 << 31) - 64 || A->nnz >= ((int64_t)1 << 31)) return F3R_ERR_ARG;
+  if (A->row_ptr[0] != 0 || A->row_ptr[A->n] != A->nnz) return F3R_ERR_MATRIX;
+  // every row range must lie inside [0, nnz] before a kernel walks it
+  for (int64_t i = 0; i < A->n; i++)
+    if (A->row_ptr[i + 1] < A->row_ptr[i]) return F3R_ERR_MATRIX;
+  const int64_t n = A->n, nnz = A->nnz, ns = n_slices(n);
+  m.n = n;
+  m.nnz = nnz;
+  int32_t* ci = (int32_t*)al.get((size_t)nnz * 4);
+  double* val = (double*)al.get((size_t)nnz * 8);
+  m.rp = (int32_t*)al.get((size_t)(n + 1) * 4);
+  HIPCHK(hipMemcpyAsync(m.rp, A->row_ptr, (size_t)(n + 1) * 4, hipMemcpyHostToDevice, st));
+  HIPCHK(hipMemcpyAsync(ci, A->col_idx, (size_t)nnz * 4, hipMemcpyHostToDevice, st));
+  HIPCHK(hipMemcpyAsync(val, A->val, (size_t)nnz * 8, hipMemcpyHostToDevice, st));
+  m.s = (double*)al.get((size_t)n * 8);
+  uint16_t* kd = (uint16_t*)al.get((size_t)n * 2);
+  int32_t* len = (int32_t*)al.get((size_t)n * 4);
+  int* flags = (int*)al.get(sizeof(int));
+  HIPCHK(hipMemsetAsync(flags, 0, sizeof(int), st));
+  HIPCHK(row_check(st, n, m.rp, ci, val, m.s, kd, len, flags));
+  uint32_t* wdev = (uint32_t*)al.get((size_t)ns * 4);
+  uint32_t* kdr = (uint32_t*)al.get((size_t)ns * 4);
+  HIPCHK(slice_widths(st, n, len, kd, wdev, kdr));
+  int hflags = 0;
+  HIPCHK(hipMemcpyAsync(&hflags, flags, sizeof(int), hipMemcpyDeviceToHost, st));
+  std::vector<uint32_t> w((size_t)ns), off((size_t)ns + 1);
+  HIPCHK(hipMemcpyAsync(w.data(), wdev, (size_t)ns * 4, hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  if (hflags & SF_MATRIX) return F3R_ERR_MATRIX;
+  if (hflags & SF_LONGROW) return F3R_ERR_ARG;
+  uint64_t acc = 0;
+  for (int64_t sidx = 0; sidx < ns; sidx++) {
+    off[(size_t)sidx] = (uint32_t)acc;
+    acc += (uint64_t)w[(size_t)sidx] * 64;
+    if (acc >= 0xFFFFFFF0ull) return F3R_ERR_ARG;
+  }
+  off[(size_t)ns] = (uint32_t)acc;
+  m.padded = (int64_t)acc;
+  uint32_t* offd = (uint32_t*)al.get((size_t)(ns + 1) * 4);
+  HIPCHK(hipMemcpyAsync(offd, off.data(), (size_t)(ns + 1) * 4, hipMemcpyHostToDevice, st));
+  SellOut so;
+  so.idx16 = (hflags & SF_IDX32) ? 0 : 1;
+  so.idx = al.get((size_t)acc * (so.idx16 ? 2 : 4));
+  so.a64 = (double*)al.get((size_t)acc * 8);
+  so.alpha = p->alpha;
+  m.m_shared = p->alpha == 1.0;
+  bool need[4] = {need_in[0], need_in[1], need_in[2], need_in[3]};
+  int mask = 0;
+  for (int d = 1; d < p->nlev; d++) {
+    need[p->lev[d].prec_a] = true;
+    mask |= 1 << p->lev[d].prec_a;
+  }
+  if (m.m_shared) {
+    need[p->prec_m] = true;
+    mask |= 1 << p->prec_m;
+  } else {
+    so.mv[p->prec_m] = al.get((size_t)acc * type_size(p->prec_m));
+    if (p->prec_m != T64) so.mv[T64] = al.get((size_t)acc * 8);
+    mask |= 1 << p->prec_m;
+  }
+  for (int t = 0; t < 4; t++)
+    if (need[t]) so.ah[t] = al.get((size_t)acc * type_size(t));
+  so.range_mask = mask;
+  HIPCHK(to_sell(st, n, m.rp, ci, val, m.s, offd, len, so, flags));
+  double* gd = (double*)al.get(4 * sizeof(double));
+  HIPCHK(m_diag(st, p->alpha, gd));
+  HIPCHK(hipMemcpyAsync(m.gd, gd, 4 * sizeof(double), hipMemcpyDeviceToHost, st));
+  HIPCHK(hipMemcpyAsync(&hflags, flags, sizeof(int), hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  if (hflags & SF_RANGE) return F3R_ERR_RANGE;
+  m.a64 = so.a64;
+  for (int t = 0; t < 4; t++) {
+    m.ah[t] = so.ah[t];
+    m.mv[t] = so.mv[t];
+  }
+  m.A.n = n;
+  m.A.ns = ns;
+  m.A.off = offd;
+  m.A.idx = so.idx;
+  m.A.idx16 = so.idx16;
+  m.A.kd = kd;
+  m.A.kdr = kdr;
+  // the CSR copies are no longer needed
+  al.release(ci);
+  al.release(val);
+  al.release(len);
+  al.release(wdev);
+  al.release(flags);
+  al.release(gd);
+  return F3R_OK;
 }
 
 }  // namespace f3r

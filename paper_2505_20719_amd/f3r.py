@@ -80,6 +80,13 @@ EXPORTS = {
     "f3r_set_weights": (C.c_int32, [C.c_void_p, C.c_int32, C.c_void_p, C.c_int64]),
     "f3r_destroy": (None, [C.c_void_p]),
     "f3r_status_str": (C.c_char_p, [C.c_int32]),
+    "f3r_setup_batched": (C.c_int32, [C.c_int32, C.POINTER(Csr), C.POINTER(Params), C.c_void_p,
+                                      C.POINTER(C.c_void_p)]),
+    "f3r_solve_batched": (C.c_int32, [C.c_void_p, C.POINTER(C.c_void_p), C.POINTER(C.c_void_p),
+                                      C.c_double, C.POINTER(Info)]),
+    "f3r_batch_get_history": (C.c_int32, [C.c_void_p, C.c_int32, C.c_void_p, C.c_int64,
+                                          C.POINTER(C.c_int64)]),
+    "f3r_batch_destroy": (None, [C.c_void_p]),
     "f3r_debug_spmv": (C.c_int32, [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p]),
     "f3r_debug_apply_m": (C.c_int32, [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p]),
     "f3r_debug_apply_level": (C.c_int32, [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p]),
@@ -226,3 +233,64 @@ class Solver:
     def _check(st, where):
         if st != OK:
             raise F3RError(st, where)
+
+
+class BatchSolver:
+    """f3r_setup_batched / f3r_solve_batched: many independent systems solved
+    by one persistent launch."""
+
+    def __init__(self, matrices, params: Params | None = None):
+        """matrices: sequence of (row_ptr, col_idx, val) host arrays."""
+        self.L = lib()
+        self.params = params if params is not None else params_default()
+        self._keep = []
+        csrs = (Csr * len(matrices))()
+        self.sizes = []
+        for i, (rp, ci, va) in enumerate(matrices):
+            rp = np.ascontiguousarray(rp, dtype=np.int32)
+            ci = np.ascontiguousarray(ci, dtype=np.int32)
+            va = np.ascontiguousarray(va, dtype=np.float64)
+            self._keep += [rp, ci, va]
+            csrs[i] = Csr(rp.size - 1, ci.size, rp.ctypes.data, ci.ctypes.data, va.ctypes.data)
+            self.sizes.append(int(rp.size - 1))
+        self.count = len(matrices)
+        h = C.c_void_p()
+        st = self.L.f3r_setup_batched(self.count, csrs, C.byref(self.params), _stream_ptr(), C.byref(h))
+        self._keep = []  # the library copied the matrices
+        if st != OK:
+            raise F3RError(st, "f3r_setup_batched")
+        self.h = h
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.L.f3r_batch_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def solve(self, bs, xs=None, tol=1e-10, raise_on_error=True):
+        """bs: list of fp64 CUDA tensors; returns (xs, infos, status)."""
+        import torch
+        if len(bs) != self.count:
+            raise ValueError("one right-hand side per system")
+        if xs is None:
+            xs = [torch.zeros(n, dtype=torch.float64, device=b.device) for n, b in zip(self.sizes, bs)]
+        bp = (C.c_void_p * self.count)(*[_dptr(b).value for b in bs])
+        xp = (C.c_void_p * self.count)(*[_dptr(x).value for x in xs])
+        infos = (Info * self.count)()
+        st = self.L.f3r_solve_batched(self.h, bp, xp, tol, infos)
+        if st < 0 and raise_on_error:
+            raise F3RError(st, "f3r_solve_batched")
+        return xs, list(infos), st
+
+    def history(self, sys):
+        n = C.c_int64()
+        Solver._check(self.L.f3r_batch_get_history(self.h, sys, None, 0, C.byref(n)), "batch history")
+        buf = np.zeros(max(n.value, 1))
+        Solver._check(self.L.f3r_batch_get_history(self.h, sys, buf.ctypes.data, n.value, C.byref(n)),
+                      "batch history")
+        return buf[: n.value].copy()

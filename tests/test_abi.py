@@ -18,7 +18,8 @@ def test_header_declares_the_boundary():
     names = declared_functions()
     for must in ("f3r_setup", "f3r_solve", "f3r_fgmres_solve", "f3r_get_history",
                  "f3r_get_weights", "f3r_set_weights", "f3r_params_default", "f3r_destroy",
-                 "f3r_status_str"):
+                 "f3r_status_str", "f3r_setup_batched", "f3r_solve_batched",
+                 "f3r_batch_get_history", "f3r_batch_destroy"):
         assert must in names
 
 
