@@ -1,15 +1,22 @@
 #!/usr/bin/env python3
 """Benchmark of the F3R hot path on one MI355X.
 
-Workload: the 3D 7-point Poisson system on a 128^3 grid (n = 2,097,152,
-nnz = 14,581,760), x* uniform on [-1, 1] from a seeded SplitMix64 stream,
-b = A x*, tolerance 1e-10 on the fp64 relative residual.  One step is one
-fp16-F3R solve (F100, F8, F4, R2, M; c = 64) from x0 = 0 to the tolerance
-with b already in HBM; set-up (scaling, level copies, M, device format) is
-timed once and reported beside it.  The same GPU also runs fp64
-FGMRES(64)+M, fp32-F3R and fp64-F3R for the comparison the metric names.
+Default workload: the 3D 7-point Poisson system on a 128^3 grid
+(n = 2,097,152, nnz = 14,581,760), x* uniform on [-1, 1] from a seeded
+SplitMix64 stream, b = A x*, tolerance 1e-10 on the fp64 relative residual.
+One step is one fp16-F3R solve (F100, F8, F4, R2, M; c = 64) from x0 = 0 to
+the tolerance with b already in HBM; set-up (scaling, level copies, M,
+device format) is timed once and reported beside it.  The same GPU also runs
+fp64 FGMRES(64)+M, fp32-F3R and fp64-F3R for the comparison the metric
+names.
 
-Prints one JSON line.  --gpus above 1 is refused: this build runs on one GPU.
+--workload selects another synthetic system shaped like the paper's
+workloads: convdiff_q1_100 (nonsymmetric 27-point, fp16 and bf16 inner
+storage compared), elasticity_bonds_64 (3x3 blocks, 61.7M entries),
+poisson2d_64 (small), or varcoef2d_batch256 (256 independent systems solved
+by one persistent launch, against the same systems solved one at a time).
+
+Prints one JSON line.  --gpus above 1 is refused: the solver runs on one GPU.
 """
 from __future__ import annotations
 
@@ -99,19 +106,94 @@ def cpu_baseline(A, b, outer_iters_gpu, outer_sample):
     }
 
 
+WORKLOADS = {
+    # name: (generator, description, extra variants timed beside fp16-F3R)
+    "poisson3d_128": (lambda W: W.poisson3d(128), "3D 7-point Poisson 128^3", ("fp32", "fp64")),
+    "convdiff_q1_100": (lambda W: W.convdiff_q1(100),
+                        "3D Q1 convection-diffusion 100^3 (27-point, nonsymmetric, lognormal sigma 1.5, "
+                        "Peclet 50)", ("bf16", "fp32", "fp64")),
+    "elasticity_bonds_64": (lambda W: W.elasticity_bonds(64),
+                            "elasticity-like bond model, 3x3 blocks on a jittered 64^3 lattice, 26 neighbours",
+                            ("bf16",)),
+    "poisson2d_64": (lambda W: W.poisson2d(64), "2D 5-point Poisson 64^2", ("fp32", "fp64")),
+    "varcoef2d_batch256": (None, "256 variable-coefficient 2D 5-point systems, sides U{32..256}", ()),
+}
+
+
+def bench_batch(args, P, W, torch):
+    """Batched solve: one persistent launch vs the same systems one at a time."""
+    count = 256
+    sizes = W.batch_sizes(count, 32, 256)
+    mats = [W.varcoef2d(int(sz), tag=f"batch/{i}") for i, sz in enumerate(sizes)]
+    rhss = [W.rhs(A, f"batch/{i}") for i, A in enumerate(mats)]
+    ntot = sum(A.n for A in mats)
+    log(f"[bench] batch of {count} systems, {ntot} unknowns")
+    t = time.perf_counter()
+    bs = P.BatchSolver([(A.row_ptr, A.col_idx, A.val) for A in mats])
+    torch.cuda.synchronize()
+    setup_s = time.perf_counter() - t
+    bt = [torch.as_tensor(b, device="cuda") for _, b in rhss]
+    (xs, infos, st), times, total = timed_solves(lambda: bs.solve(bt), args.steps, args.warmup)
+    assert st == 0, [i.status for i in infos]
+    mean_s = total / args.steps
+    outs = [i.outer_iters for i in infos]
+    worst = max(i.relres_true for i in infos)
+    log(f"[bench] batched: {mean_s * 1e3:.1f} ms, {count / mean_s:.1f} systems/s, outer {min(outs)}..{max(outs)}")
+    one = 0.0
+    one_outer = []
+    for i, A in enumerate(mats):
+        g = P.Solver(A.row_ptr, A.col_idx, A.val)
+        g.solve(bt[i])  # records the graphs of this system
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        _, inf = g.solve(bt[i])
+        torch.cuda.synchronize()
+        one += time.perf_counter() - t
+        assert inf.status == 0
+        one_outer.append(inf.outer_iters)
+        g.close()
+    log(f"[bench] one at a time: {one * 1e3:.1f} ms, {count / one:.1f} systems/s")
+    cfg = {
+        "workload": f"varcoef2d_batch256: {WORKLOADS['varcoef2d_batch256'][1]} "
+                    f"({ntot} unknowns in total), k = exp(xi), x* ~ U[-1,1] seeded, b = A x*",
+        "tol": 1e-10,
+        "solver": "fp16-F3R (F100, F8, F4, R2, M), c=64, one persistent launch, one 512-thread "
+                  "workgroup per system, largest first",
+        "setup_s": round(setup_s, 4),
+        "batch_s": round(mean_s, 6),
+        "batch_median_s": round(statistics.median(times), 6),
+        "one_at_a_time_s": round(one, 6),
+        "one_at_a_time_systems_per_s": round(count / one, 2),
+        "speedup_vs_one_at_a_time": round(one / mean_s, 3),
+        "outer_iters_min_mean_max": [min(outs), round(float(np.mean(outs)), 2), max(outs)],
+        "one_at_a_time_outer_mean": round(float(np.mean(one_outer)), 2),
+        "worst_relres_true": worst,
+    }
+    return {
+        "metric": "batched F3R solves to 1e-10 per second (systems/s, one persistent launch)",
+        "value": round(count / mean_s, 3), "unit": "systems/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(mean_s * 1e3, 4), "higher_is_better": True,
+        "scaling": "strong", "vs_baseline": None, "dtype": "f16/f32/f64", "data": "synthetic",
+        "config": cfg, "roofline": None, "cpu_baseline": None,
+    }
+
+
+VARIANTS = {"fp32": "VARIANT_FP32", "fp64": "VARIANT_FP64", "bf16": "VARIANT_BF16"}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--grid", type=int, default=128, help="Poisson grid side (128 = the workload)")
+    ap.add_argument("--workload", default="poisson3d_128", choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-outer", type=int, default=1)
     ap.add_argument("--only-f3r", action="store_true", help="time the fp16-F3R solves only (profiling)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU; --gpus {args.gpus} is not supported by this build "
-              "(the solver is single-GPU; see the design notes for how it would shard)",
+        print(f"bench.py runs on one GPU; --gpus {args.gpus} is not supported "
+              "(the solver is single-GPU; the design notes describe how it would shard)",
               file=sys.stderr)
         sys.exit(2)
 
@@ -121,9 +203,12 @@ def main():
     import workloads as W
 
     torch.cuda.set_device(0)
-    N = args.grid
-    A = W.poisson3d(N)
-    name = f"poisson3d_{N}"
+    name = args.workload
+    if name == "varcoef2d_batch256":
+        print(json.dumps(bench_batch(args, P, W, torch)), flush=True)
+        return
+    gen, desc, extra = WORKLOADS[name]
+    A = gen(W)
     xs, b = W.rhs(A, name)
     bt = torch.as_tensor(b, device="cuda")
     log(f"[bench] {name} n={A.n} nnz={A.nnz}")
@@ -142,7 +227,7 @@ def main():
     err_xstar = float(np.linalg.norm(xh - xs) / np.linalg.norm(xs))
 
     result_cfg = {
-        "workload": f"{name}: 3D 7-point Poisson {N}^3 (n={A.n}, nnz={A.nnz}), x* ~ U[-1,1] seeded, b = A x*",
+        "workload": f"{name}: {desc} (n={A.n}, nnz={A.nnz}), x* ~ U[-1,1] seeded, b = A x*",
         "tol": 1e-10,
         "solver": "fp16-F3R (F100, F8, F4, R2, M), c=64, M = two-SpMV truncated SGS inverse",
         "setup_s": round(setup_s, 4),
@@ -151,26 +236,34 @@ def main():
         "f3r_fp16_m_calls": info16.m_calls,
         "relres_true": info16.relres_true,
         "err_vs_xstar": err_xstar,
-        "device_format": f"SELL-64, {info16.idx_bits}-bit column indices",
+        "device_format": f"SELL-64, {info16.idx_bits}-bit column indices, "
+                         f"{info16.padded_nnz / A.nnz:.4f} padded/stored entries",
+        "tuned_rows_per_lane": {"m_lower": info16.rows_per_lane[0], "m_upper": info16.rows_per_lane[1],
+                                "r_residual": info16.rows_per_lane[2], "tune_ms": round(info16.tune_ms, 3)},
     }
 
     if not args.only_f3r:
-        (xf, infof), tf, totf = timed_solves(lambda: s16.fgmres_solve(bt, tol=1e-10, m=64),
-                                             max(1, min(args.steps, 3)), 1)
+        reps = max(1, min(args.steps, 3))
+        (xf, infof), tf, totf = timed_solves(lambda: s16.fgmres_solve(bt, tol=1e-10, m=64), reps, 1)
         assert infof.status == 0, infof.as_dict()
-        fg_s = totf / max(1, min(args.steps, 3))
+        fg_s = totf / reps
         log(f"[bench] fp64 FGMRES(64): {fg_s * 1e3:.2f} ms/solve, iters={infof.outer_iters}")
         result_cfg.update({"fgmres64_s": round(fg_s, 6), "fgmres64_iters": infof.outer_iters,
+                           "fgmres64_err_vs_xstar": float(np.linalg.norm(xf.cpu().numpy() - xs)
+                                                          / np.linalg.norm(xs)),
                            "speedup_vs_fgmres64": round(fg_s / mean_s, 3)})
-        for variant, key in ((P.VARIANT_FP32, "fp32"), (P.VARIANT_FP64, "fp64")):
-            s = P.Solver(A.row_ptr, A.col_idx, A.val, P.params_default(variant))
-            (_, iv), tv, totv = timed_solves(lambda: s.solve(bt, tol=1e-10), 2, 1)
+        for key in extra:
+            s = P.Solver(A.row_ptr, A.col_idx, A.val, P.params_default(getattr(P, VARIANTS[key])))
+            (xv, iv), tv, totv = timed_solves(lambda: s.solve(bt, tol=1e-10), 2, 1)
             assert iv.status == 0, iv.as_dict()
             result_cfg[f"f3r_{key}_s"] = round(totv / 2, 6)
             result_cfg[f"f3r_{key}_outer_iters"] = iv.outer_iters
+            result_cfg[f"f3r_{key}_err_vs_xstar"] = float(np.linalg.norm(xv.cpu().numpy() - xs)
+                                                          / np.linalg.norm(xs))
             log(f"[bench] {key}-F3R: {totv / 2 * 1e3:.2f} ms/solve, outer={iv.outer_iters}")
             s.close()
-        result_cfg["speedup_fp16_vs_fp64_f3r"] = round(result_cfg["f3r_fp64_s"] / mean_s, 3)
+        if "fp64" in extra:
+            result_cfg["speedup_fp16_vs_fp64_f3r"] = round(result_cfg["f3r_fp64_s"] / mean_s, 3)
 
     # live per-kernel timing of the hot kernels inside one solve (HIP events
     # on the solve's stream, direct launches)
@@ -215,7 +308,7 @@ def main():
         "dtype": "f16/f32/f64",
         "data": "synthetic",
         "config": result_cfg,
-        "spmv_gbs": round(achieved, 1),
+        "spmv_gbs": round(kern["spmv_l2"]["gbs"], 1),
         "roofline": roofline,
         "cpu_baseline": cpu,
     }

@@ -97,7 +97,11 @@ typedef struct {
   int32_t probe_kernel;          /* F3R_PROBE_*: time every launch of that kernel
                                     with HIP events on the solve's stream; the
                                     solve then launches without hipGraphs */
-  int32_t reserved[6];
+  int32_t rows_per_lane;         /* shape of the M sweeps and of the Richardson
+                                    residual: 0 = picked by timing the
+                                    candidates 1, 2, 4 at set-up; 1, 2 or 4 =
+                                    fixed.  Results do not depend on it. */
+  int32_t reserved[5];
 } f3r_params;
 
 typedef struct {
@@ -128,6 +132,9 @@ typedef struct {
   double probe_ms;       /* summed duration of the probed kernel's launches */
   int64_t probe_launches; /* launches of the probed kernel */
   int64_t padded_nnz;    /* stored entries of the device format incl. padding */
+  int32_t rows_per_lane[3]; /* shapes in use: W sweep, G sweep, Richardson residual */
+  int32_t pad_;
+  double tune_ms;        /* set-up time spent timing the candidate shapes */
 } f3r_info;
 
 typedef struct f3r_handle f3r_handle;

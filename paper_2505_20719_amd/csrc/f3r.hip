@@ -96,6 +96,9 @@ struct f3r_handle {
   double probe_ms = 0;
   int64_t probe_n = 0;
   double setup_ms = 0;
+  // rows per lane of the W sweep, the G sweep and the Richardson residual
+  int kr[3] = {4, 4, 4};
+  double tune_ms = 0;
   DevAllocs al;
 
   void* dalloc(size_t bytes) { return al.get(bytes); }
@@ -145,6 +148,8 @@ f3r_status check_params(const f3r_params* p) {
   if (!(p->alpha > 0.0) || !std::isfinite(p->alpha)) return F3R_ERR_ARG;
   if (p->c < 0 || p->max_outer < 1) return F3R_ERR_ARG;
   if (p->m_identity != 0) return F3R_ERR_ARG;  // M = I is not provided
+  if (p->rows_per_lane != 0 && p->rows_per_lane != 1 && p->rows_per_lane != 2 && p->rows_per_lane != 4)
+    return F3R_ERR_ARG;
   return F3R_OK;
 }
 
@@ -286,22 +291,23 @@ void enqueue_rich(Ctx& c, int d, const Basis& vin, const int* stop, void* out, i
       rsrc = vin;
     } else {
       probe_begin(c, F3R_PROBE_R_RESIDUAL);
-      HIPCHK(rich_residual(c.st, h->A, av, R.pa, vin, zprev, R.rr, tr, stop));
+      HIPCHK(rich_residual(c.st, h->A, av, R.pa, vin, zprev, R.rr, tr, stop, h->kr[2]));
       probe_end(c, F3R_PROBE_R_RESIDUAL);
       rsrc.raw = R.rr;
       rsrc.type = tr;
     }
     probe_begin(c, F3R_PROBE_M_LOWER);
-    HIPCHK(m_apply_w(c.st, h->A, mv, tm, neg, rsrc, R.rt, tr, stop, k == 0 ? R.cntr_dev : nullptr));
+    HIPCHK(m_apply_w(c.st, h->A, mv, tm, neg, rsrc, R.rt, tr, stop, k == 0 ? R.cntr_dev : nullptr,
+                     h->kr[0]));
     probe_end(c, F3R_PROBE_M_LOWER);
     if (!upd) {
       probe_begin(c, F3R_PROBE_M_UPPER);
       HIPCHK(m_apply_g(c.st, h->A, mv, tm, neg, gd, R.rt, tr, k == 0 ? 1 : 2, R.omega + k, zprev, zk,
-                       tr, nullptr, zfb, stop));
+                       tr, nullptr, zfb, stop, nullptr, h->kr[1]));
       probe_end(c, F3R_PROBE_M_UPPER);
     } else {
       HIPCHK(m_apply_g(c.st, h->A, mv, tm, neg, gd, R.rt, tr, 0, nullptr, nullptr, R.ry, tr, nullptr,
-                       nullptr, stop));
+                       nullptr, stop, nullptr, h->kr[1]));
       HIPCHK(rich_tdots(c.st, h->A, av, R.pa, R.ry, tr, rsrc, h->partials, stop));
       HIPCHK(rich_omega(c.st, q_of(tr), h->partials, nb, R.omega + k, R.wcur, R.cntr_dev, h->p.c,
                         stop));
@@ -392,6 +398,71 @@ void enqueue_fgmres(Ctx& c, int d, const Basis& vin, const void* alias_raw, cons
   lb.scales = L.S + L.L.scale;
   HIPCHK(combine(c.st, n, L.Z, L.zt, L.pv, L.S + L.L.y, L.I + I_MEFF, out.ptr, out.s, out.cur, 0, &lb,
                  L.I + I_FB, out.fb));
+}
+
+// Set-up autotuner: times the candidate shapes (rows per lane 1, 2, 4) of
+// the three sweeps of the Richardson level on this matrix and keeps the
+// fastest of each.  The sweeps have no reductions, so the shape changes
+// only the time, never a result.
+void autotune(f3r_handle* h) {
+  const int fixed = h->p.rows_per_lane;
+  if (fixed) {
+    h->kr[0] = h->kr[1] = h->kr[2] = fixed;
+    return;
+  }
+  if (h->rich < 0) return;
+  const double t0 = now_ms();
+  LevelRT& R = h->lev[h->rich];
+  const int tr = R.pv;
+  int tm, neg;
+  const void* mv = m_values(h, tm, neg);
+  const double gd = h->gd[tm];
+  const int64_t n = h->n;
+  // inputs with ordinary finite values (byte pattern 0x3C in every format)
+  HIPCHK(hipMemsetAsync(R.rr, 0x3C, (size_t)n * tsz(tr), h->st));
+  HIPCHK(hipMemsetAsync(R.rz[0], 0x3C, (size_t)n * tsz(tr), h->st));
+  const int tin = h->p.lev[h->rich - 1].prec_v;
+  HIPCHK(hipMemsetAsync(h->tmp64, 0x3C, (size_t)n * tsz(tin), h->st));
+  Basis vec;
+  vec.raw = R.rr;
+  vec.type = tr;
+  Basis basis;
+  basis.raw = h->tmp64;
+  basis.type = tin;
+  basis.scale = h->one;
+  hipEvent_t e0, e1;
+  HIPCHK(hipEventCreate(&e0));
+  HIPCHK(hipEventCreate(&e1));
+  const int cand[3] = {1, 2, 4};
+  for (int f = 0; f < 3; f++) {
+    float best = 0.f;
+    for (int c = 0; c < 3; c++) {
+      const int kr = cand[c];
+      auto launch = [&]() {
+        if (f == 0)
+          HIPCHK(m_apply_w(h->st, h->A, mv, tm, neg, vec, R.rt, tr, nullptr, nullptr, kr));
+        else if (f == 1)
+          HIPCHK(m_apply_g(h->st, h->A, mv, tm, neg, gd, R.rr, tr, 2, h->one, R.rz[0], R.rt, tr,
+                           nullptr, nullptr, nullptr, nullptr, kr));
+        else
+          HIPCHK(rich_residual(h->st, h->A, h->ah[R.pa], R.pa, basis, R.rz[0], R.rt, tr, nullptr, kr));
+      };
+      launch();
+      HIPCHK(hipEventRecord(e0, h->st));
+      for (int i = 0; i < 5; i++) launch();
+      HIPCHK(hipEventRecord(e1, h->st));
+      HIPCHK(hipEventSynchronize(e1));
+      float ms = 0.f;
+      HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+      if (c == 0 || ms < best) {
+        best = ms;
+        h->kr[f] = kr;
+      }
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  h->tune_ms = now_ms() - t0;
 }
 
 // initial weight in the Richardson level's arithmetic
@@ -666,6 +737,8 @@ f3r_status outer_solve(f3r_handle* h, const double* b, double* x, double tol, in
     info->probe_ms = h->probe_ms;
     info->probe_launches = h->probe_n;
     info->padded_nnz = h->padded;
+    for (int f = 0; f < 3; f++) info->rows_per_lane[f] = h->kr[f];
+    info->tune_ms = h->tune_ms;
   }
   return status;
 }
@@ -813,6 +886,7 @@ f3r_status f3r_setup(const f3r_csr* A, const f3r_params* p, void* hip_stream, f3
     HIPCHK(hipHostMalloc((void**)&h->hpin, 64 * sizeof(double), hipHostMallocDefault));
     std::memset(h->hpin, 0, 64 * sizeof(double));
     alloc_levels(h);
+    autotune(h);
     HIPCHK(hipStreamSynchronize(h->st));
     return F3R_OK;
   });

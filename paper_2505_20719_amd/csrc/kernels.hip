@@ -31,6 +31,17 @@ template <class F> static hipError_t with_idx(int idx16, F&& f) {
 }
 #define TYPE_OF(p) typename std::remove_pointer<decltype(p)>::type
 
+// rows per lane (and the entry chunk that goes with it) of the sweeps whose
+// shape the set-up autotuner picks; their results do not depend on it
+template <class F> static hipError_t with_kr(int kr, F&& f) {
+  switch (kr) {
+    case 1: return f(std::integral_constant<int, 1>{}, std::integral_constant<int, 8>{});
+    case 2: return f(std::integral_constant<int, 2>{}, std::integral_constant<int, 4>{});
+    case 4: return f(std::integral_constant<int, 4>{}, std::integral_constant<int, 4>{});
+  }
+  return hipErrorInvalidValue;
+}
+
 static inline dim3 grid_for(int64_t n) { return dim3((unsigned)physical_grid(n_blocks(n))); }
 
 // Storage combinations the library instantiates: a level with vectors in
@@ -674,7 +685,7 @@ hipError_t dot64_to_host(hipStream_t st, int64_t n, const double* x, const doubl
 // ---------------------------------------------------------------------------
 // primary preconditioner: W and G sweeps (Sec. 5.2: two SpMVs)
 // ---------------------------------------------------------------------------
-template <class TI, class TM, class TT, class Q, class LD>
+template <int KR, int U, class TI, class TM, class TT, class Q, class LD>
 __global__ __launch_bounds__(kBlock) void k_mw(SellDesc A, const TM* __restrict__ mv, int neg,
                                                LD ld, TT* __restrict__ t, const int* stop,
                                                int64_t* cntr, int64_t nb) {
@@ -684,14 +695,14 @@ __global__ __launch_bounds__(kBlock) void k_mw(SellDesc A, const TM* __restrict_
   if (lb >= nb) return;
   const int wave = threadIdx.x / kWave, lane = threadIdx.x & (kWave - 1);
   const int64_t gw = lb * 4 + wave;
-  RowSlot s[kR];
+  RowSlot s[KR];
   make_slots(A, gw, lane, s);
   ld.init();
-  int lo[kR], hi[kR], kb[kR], ke[kR];
-  Q acc[kR];
+  int lo[KR], hi[KR], kb[KR], ke[KR];
+  Q acc[KR];
 #pragma unroll
-  for (int r = 0; r < kR; r++) {
-    const int64_t slice = gw * kR + r;
+  for (int r = 0; r < KR; r++) {
+    const int64_t slice = gw * KR + r;
     // loop bound from the slice; the row's own diagonal position only masks
     lo[r] = 0;
     hi[r] = s[r].ok ? max((int)(A.kdr[slice] >> 16), 1) : 1;
@@ -699,12 +710,12 @@ __global__ __launch_bounds__(kBlock) void k_mw(SellDesc A, const TM* __restrict_
     ke[r] = s[r].ok ? (int)A.kd[s[r].row] : 0;
     acc[r] = 0;
   }
-  Q dg[kR];  // the unit-diagonal term, loaded with the matrix entries
+  Q dg[KR];  // the unit-diagonal term, loaded with the matrix entries
 #pragma unroll
-  for (int r = 0; r < kR; r++) dg[r] = ld(s[r].row);
-  rows_sum<kUnroll, TI>(mv, (const TI*)A.idx, s, lo, hi, kb, ke, acc, ld, neg != 0);
+  for (int r = 0; r < KR; r++) dg[r] = ld(s[r].row);
+  rows_sum<U, TI>(mv, (const TI*)A.idx, s, lo, hi, kb, ke, acc, ld, neg != 0);
 #pragma unroll
-  for (int r = 0; r < kR; r++)
+  for (int r = 0; r < KR; r++)
     if (s[r].ok) t[s[r].row] = round_to<TT>(acc[r] + dg[r]);
 }
 
@@ -739,7 +750,7 @@ template <class TT, class Q> struct EpiZK {
   const double* wp;
   int* fb;
   Q w;
-  Q zv[kR];
+  Q zv[4];  // one per row of the lane (at most four)
   __device__ __forceinline__ void init() { w = (Q)(*wp); }
   __device__ __forceinline__ void prefetch(int k, int64_t r) { zv[k] = widen<Q>(zp[r]); }
   __device__ __forceinline__ void operator()(int k, int64_t r, TT y) const {
@@ -768,7 +779,7 @@ struct EpiS64 {
   }
 };
 
-template <class TI, class TM, class TT, class Q, class EPI>
+template <int KR, int U, class TI, class TM, class TT, class Q, class EPI>
 __global__ __launch_bounds__(kBlock) void k_mg(SellDesc A, const TM* __restrict__ mv, int neg, Q gd,
                                                const TT* __restrict__ t, EPI epi, const int* stop,
                                                int64_t nb) {
@@ -777,14 +788,14 @@ __global__ __launch_bounds__(kBlock) void k_mg(SellDesc A, const TM* __restrict_
   if (lb >= nb) return;
   const int wave = threadIdx.x / kWave, lane = threadIdx.x & (kWave - 1);
   const int64_t gw = lb * 4 + wave;
-  RowSlot s[kR];
+  RowSlot s[KR];
   make_slots(A, gw, lane, s);
   epi.init();
-  int lo[kR], hi[kR], kb[kR], ke[kR];
-  Q acc[kR];
+  int lo[KR], hi[KR], kb[KR], ke[KR];
+  Q acc[KR];
 #pragma unroll
-  for (int r = 0; r < kR; r++) {
-    const int64_t slice = gw * kR + r;
+  for (int r = 0; r < KR; r++) {
+    const int64_t slice = gw * KR + r;
     const int kd = s[r].ok ? (int)A.kd[s[r].row] : 0;
     // loop from just after the slice's smallest diagonal position
     lo[r] = s[r].ok ? (int)(A.kdr[slice] & 0xffffu) + 1 : 0;
@@ -794,9 +805,9 @@ __global__ __launch_bounds__(kBlock) void k_mg(SellDesc A, const TM* __restrict_
     acc[r] = gd * widen<Q>(t[s[r].row]);
     epi.prefetch(r, s[r].row);
   }
-  rows_sum<kUnroll, TI>(mv, (const TI*)A.idx, s, lo, hi, kb, ke, acc, LdVec<TT, Q>{t}, neg != 0);
+  rows_sum<U, TI>(mv, (const TI*)A.idx, s, lo, hi, kb, ke, acc, LdVec<TT, Q>{t}, neg != 0);
 #pragma unroll
-  for (int r = 0; r < kR; r++)
+  for (int r = 0; r < KR; r++)
     if (s[r].ok) epi(r, s[r].row, round_to<TT>(acc[r]));
 }
 
@@ -808,8 +819,11 @@ template <class TM, class TT> constexpr bool ok_m() {
 }
 
 hipError_t m_apply_w(hipStream_t st, const SellDesc& A, const void* mv, int tm, int neg,
-                     const Basis& in, void* t, int tt, const int* stop, int64_t* cntr) {
-  const int64_t nb = n_blocks(A.n);
+                     const Basis& in, void* t, int tt, const int* stop, int64_t* cntr, int kr) {
+  return with_kr(kr, [&](auto KRc, auto Uc) {
+  constexpr int KR = decltype(KRc)::value, U = decltype(Uc)::value;
+  const int64_t nb = n_blocks_kr(A.n, KR);
+  const dim3 grid((unsigned)physical_grid(nb));
   return with_idx(A.idx16, [&](auto pi) {
     using TI = TYPE_OF(pi);
     return with_type(tm, [&](auto pm) {
@@ -823,14 +837,14 @@ hipError_t m_apply_w(hipStream_t st, const SellDesc& A, const void* mv, int tm, 
           if (in.s) {
             if (in.type != T64 || !is_dbl<TT>::value) return hipErrorInvalidValue;
             LdSBasis<TT, Q> ld{(const double*)in.raw, in.scale, in.s, in.cur, in.stride, 0.0};
-            hipLaunchKernelGGL((k_mw<TI, TM, TT, Q, LdSBasis<TT, Q>>), grid_for(A.n), dim3(kBlock),
+            hipLaunchKernelGGL((k_mw<KR, U, TI, TM, TT, Q, LdSBasis<TT, Q>>), grid, dim3(kBlock),
                                0, st, A, (const TM*)mv, neg, ld, (TT*)t, stop, cntr, nb);
             return hipGetLastError();
           }
           if (!in.scale) {
             if (in.type != tt) return hipErrorInvalidValue;
             LdVec<TT, Q> ld{(const TT*)in.raw};
-            hipLaunchKernelGGL((k_mw<TI, TM, TT, Q, LdVec<TT, Q>>), grid_for(A.n), dim3(kBlock), 0,
+            hipLaunchKernelGGL((k_mw<KR, U, TI, TM, TT, Q, LdVec<TT, Q>>), grid, dim3(kBlock), 0,
                                st, A, (const TM*)mv, neg, ld, (TT*)t, stop, cntr, nb);
             return hipGetLastError();
           }
@@ -838,7 +852,7 @@ hipError_t m_apply_w(hipStream_t st, const SellDesc& A, const void* mv, int tm, 
             using TIN = TYPE_OF(pin);
             using QQ = wider_t<TIN, Q>;
             LdBasis<TIN, TT, QQ> ld{(const TIN*)in.raw, in.scale, in.cur, in.stride, 0.0};
-            hipLaunchKernelGGL((k_mw<TI, TM, TT, QQ, LdBasis<TIN, TT, QQ>>), grid_for(A.n),
+            hipLaunchKernelGGL((k_mw<KR, U, TI, TM, TT, QQ, LdBasis<TIN, TT, QQ>>), grid,
                                dim3(kBlock), 0, st, A, (const TM*)mv, neg, ld, (TT*)t, stop, cntr, nb);
             return hipGetLastError();
           });
@@ -846,14 +860,17 @@ hipError_t m_apply_w(hipStream_t st, const SellDesc& A, const void* mv, int tm, 
       });
     });
   });
+});
 }
 
 hipError_t m_apply_g(hipStream_t st, const SellDesc& A, const void* mv, int tm, int neg, double gd,
                      const void* t, int tt, int mode, const double* omega, const void* zprev,
                      void* out, int tout, const double* s, int* fbflag, const int* stop,
-                     const int* cur) {
-  const int64_t nb = n_blocks(A.n);
+                     const int* cur, int kr) {
   if (mode != 3 && tout != tt) return hipErrorInvalidValue;
+  return with_kr(kr, [&](auto KRc, auto Uc) {
+  constexpr int KR = decltype(KRc)::value, U = decltype(Uc)::value;
+  const int64_t nb = n_blocks_kr(A.n, KR);
   return with_idx(A.idx16, [&](auto pi) {
     using TI = TYPE_OF(pi);
     return with_type(tm, [&](auto pm) {
@@ -864,25 +881,25 @@ hipError_t m_apply_g(hipStream_t st, const SellDesc& A, const void* mv, int tm, 
           return hipErrorInvalidValue;
         } else {
           using Q = wider_t<TM, TT>;
-          const dim3 g = grid_for(A.n), b(kBlock);
+          const dim3 g((unsigned)physical_grid(nb)), b(kBlock);
           if (mode == 0) {
             EpiStore<TT, Q> ep{(TT*)out, fbflag};
-            hipLaunchKernelGGL((k_mg<TI, TM, TT, Q, EpiStore<TT, Q>>), g, b, 0, st, A,
+            hipLaunchKernelGGL((k_mg<KR, U, TI, TM, TT, Q, EpiStore<TT, Q>>), g, b, 0, st, A,
                                (const TM*)mv, neg, (Q)gd, (const TT*)t, ep, stop, nb);
           } else if (mode == 1) {
             EpiZ1<TT, Q> ep{(TT*)out, omega, fbflag, (Q)0};
-            hipLaunchKernelGGL((k_mg<TI, TM, TT, Q, EpiZ1<TT, Q>>), g, b, 0, st, A, (const TM*)mv,
+            hipLaunchKernelGGL((k_mg<KR, U, TI, TM, TT, Q, EpiZ1<TT, Q>>), g, b, 0, st, A, (const TM*)mv,
                                neg, (Q)gd, (const TT*)t, ep, stop, nb);
           } else if (mode == 2) {
             EpiZK<TT, Q> ep{(TT*)out, (const TT*)zprev, omega, fbflag, (Q)0};
-            hipLaunchKernelGGL((k_mg<TI, TM, TT, Q, EpiZK<TT, Q>>), g, b, 0, st, A, (const TM*)mv,
+            hipLaunchKernelGGL((k_mg<KR, U, TI, TM, TT, Q, EpiZK<TT, Q>>), g, b, 0, st, A, (const TM*)mv,
                                neg, (Q)gd, (const TT*)t, ep, stop, nb);
           } else {
             if constexpr (!is_dbl<TT>::value) {
               return hipErrorInvalidValue;
             } else {
               EpiS64 ep{(double*)out, s, fbflag, cur, A.n};
-              hipLaunchKernelGGL((k_mg<TI, TM, TT, Q, EpiS64>), g, b, 0, st, A, (const TM*)mv, neg,
+              hipLaunchKernelGGL((k_mg<KR, U, TI, TM, TT, Q, EpiS64>), g, b, 0, st, A, (const TM*)mv, neg,
                                  (Q)gd, (const TT*)t, ep, stop, nb);
             }
           }
@@ -891,12 +908,13 @@ hipError_t m_apply_g(hipStream_t st, const SellDesc& A, const void* mv, int tm, 
       });
     });
   });
+});
 }
 
 // ---------------------------------------------------------------------------
 // Richardson pieces (Alg. 1)
 // ---------------------------------------------------------------------------
-template <class TI, class TA, class TR, class Q, class LD>
+template <int KR, int U, class TI, class TA, class TR, class Q, class LD>
 __global__ __launch_bounds__(kBlock) void k_rres(SellDesc A, const TA* __restrict__ av, LD ld,
                                                  const TR* __restrict__ z, TR* __restrict__ r,
                                                  const int* stop, int64_t nb) {
@@ -904,30 +922,33 @@ __global__ __launch_bounds__(kBlock) void k_rres(SellDesc A, const TA* __restric
   const int64_t lb = logical_block(nb);
   if (lb >= nb) return;
   const int wave = threadIdx.x / kWave, lane = threadIdx.x & (kWave - 1);
-  RowSlot s[kR];
+  RowSlot s[KR];
   make_slots(A, lb * 4 + wave, lane, s);
   ld.init();
-  int kb[kR], ke[kR], kc[kR];
-  Q acc[kR];
+  int kb[KR], ke[KR], kc[KR];
+  Q acc[KR];
 #pragma unroll
-  for (int q = 0; q < kR; q++) {
+  for (int q = 0; q < KR; q++) {
     kb[q] = 0;
     ke[q] = s[q].w;
     kc[q] = max(s[q].w, 1);
     acc[q] = 0;
   }
-  Q vr[kR];  // v at the row, loaded with the matrix entries
+  Q vr[KR];  // v at the row, loaded with the matrix entries
 #pragma unroll
-  for (int q = 0; q < kR; q++) vr[q] = ld(s[q].row);
-  rows_sum<kUnroll, TI>(av, (const TI*)A.idx, s, kb, kc, kb, ke, acc, LdVec<TR, Q>{z});
+  for (int q = 0; q < KR; q++) vr[q] = ld(s[q].row);
+  rows_sum<U, TI>(av, (const TI*)A.idx, s, kb, kc, kb, ke, acc, LdVec<TR, Q>{z});
 #pragma unroll
-  for (int q = 0; q < kR; q++)
+  for (int q = 0; q < KR; q++)
     if (s[q].ok) r[s[q].row] = round_to<TR>(vr[q] - acc[q]);
 }
 
 hipError_t rich_residual(hipStream_t st, const SellDesc& A, const void* av, int ta,
-                         const Basis& in, const void* z, void* r, int tr, const int* stop) {
-  const int64_t nb = n_blocks(A.n);
+                         const Basis& in, const void* z, void* r, int tr, const int* stop, int kr) {
+  return with_kr(kr, [&](auto KRc, auto Uc) {
+  constexpr int KR = decltype(KRc)::value, U = decltype(Uc)::value;
+  const int64_t nb = n_blocks_kr(A.n, KR);
+  const dim3 grid((unsigned)physical_grid(nb));
   return with_idx(A.idx16, [&](auto pi) {
     using TI = TYPE_OF(pi);
     return with_type(ta, [&](auto pa) {
@@ -942,7 +963,7 @@ hipError_t rich_residual(hipStream_t st, const SellDesc& A, const void* av, int 
             using TIN = TYPE_OF(pin);
             using QQ = wider_t<TIN, Q>;
             LdBasis<TIN, TR, QQ> ld{(const TIN*)in.raw, in.scale, in.cur, in.stride, 0.0};
-            hipLaunchKernelGGL((k_rres<TI, TA, TR, QQ, LdBasis<TIN, TR, QQ>>), grid_for(A.n),
+            hipLaunchKernelGGL((k_rres<KR, U, TI, TA, TR, QQ, LdBasis<TIN, TR, QQ>>), grid,
                                dim3(kBlock), 0, st, A, (const TA*)av, ld, (const TR*)z, (TR*)r, stop,
                                nb);
             return hipGetLastError();
@@ -951,6 +972,7 @@ hipError_t rich_residual(hipStream_t st, const SellDesc& A, const void* av, int 
       });
     });
   });
+});
 }
 
 template <class TI, class TA, class TR, class Q, class LD>

@@ -36,7 +36,7 @@ class Params(C.Structure):
                 ("m_identity", C.c_int32), ("c", C.c_int32), ("alpha", C.c_double),
                 ("omega_init", C.c_double), ("max_outer", C.c_int32), ("flags", C.c_uint32),
                 ("poison_call", C.c_int32), ("probe_kernel", C.c_int32),
-                ("reserved", C.c_int32 * 6)]
+                ("rows_per_lane", C.c_int32), ("reserved", C.c_int32 * 5)]
 
 
 class Csr(C.Structure):
@@ -51,11 +51,13 @@ class Info(C.Structure):
                 ("breakdowns", C.c_int64), ("relres_est", C.c_double),
                 ("relres_true", C.c_double), ("setup_ms", C.c_double), ("solve_ms", C.c_double),
                 ("graph_launches", C.c_int64), ("idx_bits", C.c_int32), ("sell_c", C.c_int32),
-                ("probe_ms", C.c_double), ("probe_launches", C.c_int64), ("padded_nnz", C.c_int64)]
+                ("probe_ms", C.c_double), ("probe_launches", C.c_int64), ("padded_nnz", C.c_int64),
+                ("rows_per_lane", C.c_int32 * 3), ("pad_", C.c_int32), ("tune_ms", C.c_double)]
 
     def as_dict(self):
-        d = {k: getattr(self, k) for k, _ in self._fields_ if k != "spmv"}
+        d = {k: getattr(self, k) for k, _ in self._fields_ if k not in ("spmv", "rows_per_lane")}
         d["spmv"] = list(self.spmv)
+        d["rows_per_lane"] = list(self.rows_per_lane)
         return d
 
 

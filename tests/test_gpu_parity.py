@@ -253,3 +253,34 @@ def test_poisoned_richardson_output_falls_back_like_the_oracle():
     xo, io = o.solve(b)
     assert info.status == 0 and info.fallbacks == 1 == io.fallbacks
     assert abs(info.outer_iters - io.outer_iters) <= 1
+
+
+def test_autotuned_shapes_change_time_not_results():
+    # every rows-per-lane shape of the M sweeps and the Richardson residual,
+    # fixed or picked by the set-up timing, gives bitwise the same solve
+    PP = P()
+    A = MATS["poisson3d_30"]()
+    xs, b = W.rhs(A, "poisson3d_30")
+    ref = None
+    for kr in (0, 1, 2, 4):
+        prm = PP.params_default(0)
+        prm.rows_per_lane = kr
+        print(f"[case] poisson3d_30 rows_per_lane={kr}", flush=True)
+        g = PP.Solver(A.row_ptr, A.col_idx, A.val, prm)
+        x, info = g.solve(dev(b))
+        assert info.status == 0
+        shapes = list(info.rows_per_lane)
+        assert all(v in (1, 2, 4) for v in shapes)
+        if kr:
+            assert shapes == [kr] * 3 and info.tune_ms == 0.0
+        else:
+            assert info.tune_ms > 0.0
+        if ref is None:
+            ref = (x, g.history())
+        else:
+            assert torch.equal(x, ref[0]) and np.array_equal(g.history(), ref[1])
+        g.close()
+    bad = PP.params_default(0)
+    bad.rows_per_lane = 3
+    with pytest.raises(PP.F3RError):
+        PP.Solver(A.row_ptr, A.col_idx, A.val, bad)

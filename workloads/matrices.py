@@ -60,20 +60,21 @@ def _stencil_csr(shape, offsets, coeffs, name=""):
     z, y, x = z.reshape(-1), y.reshape(-1), x.reshape(-1)
     rows_idx = np.arange(n, dtype=np.int64)
     K = len(offsets)
-    valid = np.zeros((n, K), dtype=bool)
-    cols = np.zeros((n, K), dtype=np.int64)
-    vals = np.zeros((n, K), dtype=np.float64)
+    # built offset-major (contiguous per offset), then transposed once
+    valid = np.zeros((K, n), dtype=bool)
+    cols = np.zeros((K, n), dtype=np.int64)
+    vals = np.zeros((K, n), dtype=np.float64)
     for kk, o in enumerate(order):
         dz, dy, dx = offsets[o]
-        ok = (z + dz >= 0) & (z + dz < nz) & (y + dy >= 0) & (y + dy < ny) & (x + dx >= 0) & (x + dx < nx)
-        valid[:, kk] = ok
-        cols[:, kk] = rows_idx + lin[o]
-        vals[:, kk] = np.broadcast_to(np.asarray(coeffs[o], dtype=np.float64), shape).reshape(-1)
+        valid[kk] = (z + dz >= 0) & (z + dz < nz) & (y + dy >= 0) & (y + dy < ny) & (x + dx >= 0) & (x + dx < nx)
+        cols[kk] = rows_idx + lin[o]
+        vals[kk] = np.broadcast_to(np.asarray(coeffs[o], dtype=np.float64), shape).reshape(-1)
+    valid = np.ascontiguousarray(valid.T)
     counts = valid.sum(axis=1)
     row_ptr = np.zeros(n + 1, dtype=np.int64)
     np.cumsum(counts, out=row_ptr[1:])
-    col_idx = cols[valid].astype(np.int32)
-    val = vals[valid]
+    col_idx = np.ascontiguousarray(cols.T)[valid].astype(np.int32)
+    val = np.ascontiguousarray(vals.T)[valid]
     return CSR(n, row_ptr.astype(np.int32), col_idx, val, name)
 
 
@@ -195,9 +196,10 @@ def elasticity_bonds(N: int = 64, nu: float = 0.3, sigma: float = 1.0,
     order = np.argsort(lin, kind="stable")
     nd = 3 * nn
     K = len(offs) * 3
-    valid = np.zeros((nn, 3, K), dtype=bool)
-    cols = np.zeros((nn, 3, K), dtype=np.int64)
-    vals = np.zeros((nn, 3, K))
+    # built offset-major (contiguous per offset), then transposed once
+    valid = np.zeros((K, nn, 3), dtype=bool)
+    cols = np.zeros((K, nn, 3), dtype=np.int32)
+    vals = np.zeros((K, nn, 3))
     node = np.arange(nn, dtype=np.int64)
     for kk, o in enumerate(order):
         dz, dy, dx = offs[o]
@@ -205,12 +207,12 @@ def elasticity_bonds(N: int = 64, nu: float = 0.3, sigma: float = 1.0,
               & (xi + dx >= 0) & (xi + dx < N))
         qn = node + lin[o]
         for cp in range(3):
-            valid[:, :, 3 * kk + cp] = ok[:, None]
-            cols[:, :, 3 * kk + cp] = (3 * qn + cp)[:, None]
-            vals[:, :, 3 * kk + cp] = blocks[offs[o]][:, :, cp]
-    valid = valid.reshape(nd, K)
-    cols = cols.reshape(nd, K)
-    vals = vals.reshape(nd, K)
+            valid[3 * kk + cp] = ok[:, None]
+            cols[3 * kk + cp] = (3 * qn + cp)[:, None]
+            vals[3 * kk + cp] = blocks[offs[o]][:, :, cp]
+    valid = np.ascontiguousarray(valid.transpose(1, 2, 0)).reshape(nd, K)
+    cols = np.ascontiguousarray(cols.transpose(1, 2, 0)).reshape(nd, K)
+    vals = np.ascontiguousarray(vals.transpose(1, 2, 0)).reshape(nd, K)
     counts = valid.sum(axis=1)
     row_ptr = np.zeros(nd + 1, dtype=np.int64)
     np.cumsum(counts, out=row_ptr[1:])
