@@ -253,6 +253,12 @@ f3r_status f3r_debug_apply_m(f3r_handle* h, int32_t prec, const double* r,
 f3r_status f3r_debug_apply_level(f3r_handle* h, int32_t level, const double* v,
                                  double* z);
 
+/* out_i = in_i rounded to prec with the library's conversion (round to
+   nearest, ties to even, directly from fp64; Table 1 casts) and widened back
+   exactly.  in, out: device arrays of n doubles.  No handle is needed. */
+f3r_status f3r_debug_round(int32_t prec, const double* in, double* out, int64_t n,
+                           void* hip_stream);
+
 /* Host copies of the set-up results in CSR order: the scaling s (n doubles)
    and the scaled values rounded to prec (nnz doubles). */
 f3r_status f3r_debug_scaling(f3r_handle* h, double* s_host);

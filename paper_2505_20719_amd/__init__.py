@@ -5,4 +5,4 @@ from .f3r import (BF16, ERR_ARG, ERR_BREAKDOWN, ERR_DEVICE, ERR_MATRIX, ERR_NOME
                   PERSIST_WEIGHTS, PROBE_M_LOWER, PROBE_M_UPPER, PROBE_NONE, PROBE_R_RESIDUAL,
                   PROBE_SPMV_L0, PROBE_SPMV_L1, PROBE_SPMV_L2, RICHARDSON, USE_X0, VARIANT_BF16, VARIANT_FGMRES64,
                   VARIANT_FP16, VARIANT_FP32, VARIANT_FP64, BatchSolver, F3RError, Info, Params, Solver,
-                  lib, params_default)
+                  debug_round, lib, params_default)

@@ -1022,12 +1022,13 @@ f3r_status f3r_debug_apply_m(f3r_handle* h, int32_t prec, const double* r, doubl
     void* t = h->tmp64b;
     double* outb = (double*)h->partials;  // n values fit: partials hold >= 66 n / 256 doubles
     (void)outb;
-    hipError_t e = m_apply_w(h->st, h->A, mv, tm, neg, in, t, prec, nullptr, nullptr);
+    // the sweep shapes of the solve (picked at set-up)
+    hipError_t e = m_apply_w(h->st, h->A, mv, tm, neg, in, t, prec, nullptr, nullptr, h->kr[0]);
     if (e == hipErrorInvalidValue) return F3R_ERR_ARG;
     HIPCHK(e);
     // y (type prec) into tmp64 (the input is dead now)
     HIPCHK(m_apply_g(h->st, h->A, mv, tm, neg, gd, t, prec, 0, nullptr, nullptr, h->tmp64, prec,
-                     nullptr, nullptr, nullptr));
+                     nullptr, nullptr, nullptr, nullptr, h->kr[1]));
     HIPCHK(convert(h->st, n, h->tmp64, prec, y, T64));
     HIPCHK(hipStreamSynchronize(h->st));
     return F3R_OK;
@@ -1074,6 +1075,20 @@ f3r_status f3r_debug_apply_level(f3r_handle* h, int32_t level, const double* v, 
     HIPCHK(hipStreamSynchronize(h->st));
     return F3R_OK;
   });
+}
+
+f3r_status f3r_debug_round(int32_t prec, const double* in, double* out, int64_t n, void* hip_stream) {
+  if (!prec_ok(prec) || !in || !out || n < 0) return F3R_ERR_ARG;
+  if (n == 0) return F3R_OK;
+  hipStream_t st = (hipStream_t)hip_stream;
+  void* tmp = nullptr;
+  if (hipMalloc(&tmp, (size_t)n * tsz(prec)) != hipSuccess) return F3R_ERR_NOMEM;
+  f3r_status r = F3R_OK;
+  if (convert(st, n, in, T64, tmp, prec) != hipSuccess || convert(st, n, tmp, prec, out, T64) != hipSuccess ||
+      hipStreamSynchronize(st) != hipSuccess)
+    r = F3R_ERR_DEVICE;
+  (void)hipFree(tmp);
+  return r;
 }
 
 f3r_status f3r_debug_scaling(f3r_handle* h, double* s_host) {

@@ -93,6 +93,7 @@ EXPORTS = {
     "f3r_debug_apply_m": (C.c_int32, [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p]),
     "f3r_debug_apply_level": (C.c_int32, [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p]),
     "f3r_debug_scaling": (C.c_int32, [C.c_void_p, C.c_void_p]),
+    "f3r_debug_round": (C.c_int32, [C.c_int32, C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p]),
     "f3r_debug_level_values": (C.c_int32, [C.c_void_p, C.c_int32, C.c_void_p]),
 }
 
@@ -130,6 +131,16 @@ def _dptr(t):
     if not (isinstance(t, torch.Tensor) and t.is_cuda and t.dtype == torch.float64 and t.is_contiguous()):
         raise TypeError("expected a contiguous float64 CUDA tensor")
     return C.c_void_p(t.data_ptr())
+
+
+def debug_round(prec: int, x):
+    """The library's rounding of a CUDA fp64 tensor to `prec`, widened back."""
+    import torch
+    out = torch.empty_like(x)
+    st = lib().f3r_debug_round(prec, _dptr(x), _dptr(out), x.numel(), _stream_ptr())
+    if st != OK:
+        raise F3RError(st, "f3r_debug_round")
+    return out
 
 
 class Solver:

@@ -89,7 +89,14 @@ def test_m_apply_bit_exact(name):
     A, g, o = pair(name)
     r = np.random.default_rng(4).uniform(-1, 1, A.n)
     r16 = O.round_to(O.F16, r)
-    assert np.array_equal(host(g.debug_apply_m(O.F16, dev(r16))), o.apply_m(r16, O.F16, O.F32))
+    ref16 = o.apply_m(r16, O.F16, O.F32)
+    assert np.array_equal(host(g.debug_apply_m(O.F16, dev(r16))), ref16)
+    for kr in (1, 2, 4):  # every sweep shape the set-up tuner can pick
+        prm = P().params_default(0)
+        prm.rows_per_lane = kr
+        gk = P().Solver(A.row_ptr, A.col_idx, A.val, prm)
+        assert np.array_equal(host(gk.debug_apply_m(O.F16, dev(r16))), ref16), kr
+        gk.close()
     r32 = O.round_to(O.F32, r)
     assert np.array_equal(host(g.debug_apply_m(O.F32, dev(r32))), o.apply_m(r32, O.F32, O.F32))
     A, g, o = pair(name, 2)  # fp64 factors
