@@ -238,8 +238,9 @@ def main():
         "err_vs_xstar": err_xstar,
         "device_format": f"SELL-64, {info16.idx_bits}-bit column indices, "
                          f"{info16.padded_nnz / A.nnz:.4f} padded/stored entries",
-        "tuned_rows_per_lane": {"m_lower": info16.rows_per_lane[0], "m_upper": info16.rows_per_lane[1],
-                                "r_residual": info16.rows_per_lane[2], "tune_ms": round(info16.tune_ms, 3)},
+        "tuned_shapes": {k: f"{info16.rows_per_lane[i]} rows/lane, chunks of {info16.entry_chunk[i]}"
+                         for i, k in enumerate(("m_lower", "m_upper", "r_residual"))},
+        "tune_ms": round(info16.tune_ms, 3),
     }
 
     if not args.only_f3r:

@@ -99,8 +99,9 @@ typedef struct {
                                     solve then launches without hipGraphs */
   int32_t rows_per_lane;         /* shape of the M sweeps and of the Richardson
                                     residual: 0 = picked by timing the
-                                    candidates 1, 2, 4 at set-up; 1, 2 or 4 =
-                                    fixed.  Results do not depend on it. */
+                                    candidate shapes at set-up; 1, 2 or 4 =
+                                    that many rows per lane.  Results do not
+                                    depend on it. */
   int32_t reserved[5];
 } f3r_params;
 
@@ -133,7 +134,7 @@ typedef struct {
   int64_t probe_launches; /* launches of the probed kernel */
   int64_t padded_nnz;    /* stored entries of the device format incl. padding */
   int32_t rows_per_lane[3]; /* shapes in use: W sweep, G sweep, Richardson residual */
-  int32_t pad_;
+  int32_t entry_chunk[3];   /* entries per load chunk of the same three sweeps */
   double tune_ms;        /* set-up time spent timing the candidate shapes */
 } f3r_info;
 

@@ -96,8 +96,9 @@ struct f3r_handle {
   double probe_ms = 0;
   int64_t probe_n = 0;
   double setup_ms = 0;
-  // rows per lane of the W sweep, the G sweep and the Richardson residual
-  int kr[3] = {4, 4, 4};
+  // shapes (10 x rows per lane + entry chunk) of the W sweep, the G sweep
+  // and the Richardson residual
+  int kr[3] = {44, 44, 44};
   double tune_ms = 0;
   DevAllocs al;
 
@@ -400,14 +401,15 @@ void enqueue_fgmres(Ctx& c, int d, const Basis& vin, const void* alias_raw, cons
                  L.I + I_FB, out.fb));
 }
 
-// Set-up autotuner: times the candidate shapes (rows per lane 1, 2, 4) of
-// the three sweeps of the Richardson level on this matrix and keeps the
-// fastest of each.  The sweeps have no reductions, so the shape changes
-// only the time, never a result.
+// Set-up autotuner: times the candidate shapes (rows per lane and entry
+// chunk) of the three sweeps of the Richardson level on this matrix and
+// keeps the fastest of each.  The sweeps have no reductions, so the shape
+// changes only the time, never a result.
 void autotune(f3r_handle* h) {
   const int fixed = h->p.rows_per_lane;
   if (fixed) {
-    h->kr[0] = h->kr[1] = h->kr[2] = fixed;
+    const int code = fixed == 1 ? 18 : fixed == 2 ? 24 : 44;
+    h->kr[0] = h->kr[1] = h->kr[2] = code;
     return;
   }
   if (h->rich < 0) return;
@@ -433,10 +435,11 @@ void autotune(f3r_handle* h) {
   hipEvent_t e0, e1;
   HIPCHK(hipEventCreate(&e0));
   HIPCHK(hipEventCreate(&e1));
-  const int cand[3] = {1, 2, 4};
+  const int cand[5] = {18, 24, 44, 23, 43};
+  const int ncand = tsz(tr) == 2 ? 5 : 3;
   for (int f = 0; f < 3; f++) {
     float best = 0.f;
-    for (int c = 0; c < 3; c++) {
+    for (int c = 0; c < ncand; c++) {
       const int kr = cand[c];
       auto launch = [&]() {
         if (f == 0)
@@ -737,7 +740,10 @@ f3r_status outer_solve(f3r_handle* h, const double* b, double* x, double tol, in
     info->probe_ms = h->probe_ms;
     info->probe_launches = h->probe_n;
     info->padded_nnz = h->padded;
-    for (int f = 0; f < 3; f++) info->rows_per_lane[f] = h->kr[f];
+    for (int f = 0; f < 3; f++) {
+      info->rows_per_lane[f] = h->kr[f] / 10;
+      info->entry_chunk[f] = h->kr[f] % 10;
+    }
     info->tune_ms = h->tune_ms;
   }
   return status;

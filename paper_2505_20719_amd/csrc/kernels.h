@@ -160,11 +160,12 @@ hipError_t dot64_to_host(hipStream_t st, int64_t n, const double* x, const doubl
 // the W values, or the scaled matrix negated when neg = 1.  The input u is
 // a stored vector (`in.raw`, type in.type == tt, scale == nullptr) or a basis.
 // cntr_inc (nullable): the Richardson call counter, advanced by one even when
-// the call is skipped.  kr: rows per lane (1, 2 or 4; the result does not
-// depend on it).
+// the call is skipped.  kr: sweep shape 10 KR + U (KR rows per lane, entry
+// chunks of U: 18, 24, 44, and 23, 43 for narrow vectors); the result does
+// not depend on it.
 hipError_t m_apply_w(hipStream_t st, const SellDesc& A, const void* mv, int tm, int neg,
                      const Basis& in, void* t, int tt, const int* stop, int64_t* cntr_inc,
-                     int kr = 4);
+                     int kr = 44);
 
 // y = round(gd t_i + sum_{k > kd} g_k t_c): G = (1/alpha)(I - U/alpha).
 // mode 0: out = y; 1: out = round(w y); 2: out = round(zprev + w y) with
@@ -173,12 +174,12 @@ hipError_t m_apply_w(hipStream_t st, const SellDesc& A, const void* mv, int tm, 
 hipError_t m_apply_g(hipStream_t st, const SellDesc& A, const void* mv, int tm, int neg,
                      double gd, const void* t, int tt, int mode, const double* omega,
                      const void* zprev, void* out, int tout, const double* s,
-                     int* fbflag, const int* stop, const int* cur = nullptr, int kr = 4);
+                     int* fbflag, const int* stop, const int* cur = nullptr, int kr = 44);
 
 // r = round(u_i - sum_k a_k z_c) with u given by `in` (basis) and z stored.
 hipError_t rich_residual(hipStream_t st, const SellDesc& A, const void* av, int ta,
                          const Basis& in, const void* z, void* r, int tr, const int* stop,
-                         int kr = 4);
+                         int kr = 44);
 // t = A y kept in q; partials [0] = sum r_i t_i, [1] = sum t_i t_i; r given
 // by `rin` (a basis, or a stored vector with scale == nullptr).
 hipError_t rich_tdots(hipStream_t st, const SellDesc& A, const void* av, int ta,

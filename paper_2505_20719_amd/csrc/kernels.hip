@@ -31,16 +31,21 @@ template <class F> static hipError_t with_idx(int idx16, F&& f) {
 }
 #define TYPE_OF(p) typename std::remove_pointer<decltype(p)>::type
 
-// rows per lane (and the entry chunk that goes with it) of the sweeps whose
-// shape the set-up autotuner picks; their results do not depend on it
-template <class F> static hipError_t with_kr(int kr, F&& f) {
-  switch (kr) {
-    case 1: return f(std::integral_constant<int, 1>{}, std::integral_constant<int, 8>{});
-    case 2: return f(std::integral_constant<int, 2>{}, std::integral_constant<int, 4>{});
-    case 4: return f(std::integral_constant<int, 4>{}, std::integral_constant<int, 4>{});
+// Shape of the sweeps whose shape the set-up autotuner picks (their results
+// do not depend on it), coded as 10 KR + U: KR rows per lane, entries in
+// chunks of U.  Chunks of 3 exist for narrow vectors only (7-point stencils
+// have 3 entries on each side of the diagonal).
+template <class F> static hipError_t with_kr(int code, F&& f) {
+  switch (code) {
+    case 18: return f(std::integral_constant<int, 1>{}, std::integral_constant<int, 8>{});
+    case 24: return f(std::integral_constant<int, 2>{}, std::integral_constant<int, 4>{});
+    case 44: return f(std::integral_constant<int, 4>{}, std::integral_constant<int, 4>{});
+    case 23: return f(std::integral_constant<int, 2>{}, std::integral_constant<int, 3>{});
+    case 43: return f(std::integral_constant<int, 4>{}, std::integral_constant<int, 3>{});
   }
   return hipErrorInvalidValue;
 }
+template <int U, class TT> constexpr bool shape_ok() { return U != 3 || sizeof(TT) == 2; }
 
 static inline dim3 grid_for(int64_t n) { return dim3((unsigned)physical_grid(n_blocks(n))); }
 
@@ -830,7 +835,7 @@ hipError_t m_apply_w(hipStream_t st, const SellDesc& A, const void* mv, int tm, 
       using TM = TYPE_OF(pm);
       return with_type(tt, [&](auto pt) -> hipError_t {
         using TT = TYPE_OF(pt);
-        if constexpr (!ok_m<TM, TT>()) {
+        if constexpr (!ok_m<TM, TT>() || !shape_ok<U, TT>()) {
           return hipErrorInvalidValue;
         } else {
           using Q = wider_t<TM, TT>;
@@ -877,7 +882,7 @@ hipError_t m_apply_g(hipStream_t st, const SellDesc& A, const void* mv, int tm, 
       using TM = TYPE_OF(pm);
       return with_type(tt, [&](auto pt) -> hipError_t {
         using TT = TYPE_OF(pt);
-        if constexpr (!ok_m<TM, TT>()) {
+        if constexpr (!ok_m<TM, TT>() || !shape_ok<U, TT>()) {
           return hipErrorInvalidValue;
         } else {
           using Q = wider_t<TM, TT>;
@@ -955,7 +960,7 @@ hipError_t rich_residual(hipStream_t st, const SellDesc& A, const void* av, int 
       using TA = TYPE_OF(pa);
       return with_type(tr, [&](auto pr) -> hipError_t {
         using TR = TYPE_OF(pr);
-        if constexpr (!ok_m<TA, TR>()) {
+        if constexpr (!ok_m<TA, TR>() || !shape_ok<U, TR>()) {
           return hipErrorInvalidValue;
         } else {
           using Q = wider_t<TA, TR>;

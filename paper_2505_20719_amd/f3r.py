@@ -52,12 +52,13 @@ class Info(C.Structure):
                 ("relres_true", C.c_double), ("setup_ms", C.c_double), ("solve_ms", C.c_double),
                 ("graph_launches", C.c_int64), ("idx_bits", C.c_int32), ("sell_c", C.c_int32),
                 ("probe_ms", C.c_double), ("probe_launches", C.c_int64), ("padded_nnz", C.c_int64),
-                ("rows_per_lane", C.c_int32 * 3), ("pad_", C.c_int32), ("tune_ms", C.c_double)]
+                ("rows_per_lane", C.c_int32 * 3), ("entry_chunk", C.c_int32 * 3), ("tune_ms", C.c_double)]
 
     def as_dict(self):
-        d = {k: getattr(self, k) for k, _ in self._fields_ if k not in ("spmv", "rows_per_lane")}
-        d["spmv"] = list(self.spmv)
-        d["rows_per_lane"] = list(self.rows_per_lane)
+        arrays = ("spmv", "rows_per_lane", "entry_chunk")
+        d = {k: getattr(self, k) for k, _ in self._fields_ if k not in arrays}
+        for k in arrays:
+            d[k] = list(getattr(self, k))
         return d
 
 

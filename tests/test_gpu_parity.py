@@ -278,6 +278,7 @@ def test_autotuned_shapes_change_time_not_results():
         assert info.status == 0
         shapes = list(info.rows_per_lane)
         assert all(v in (1, 2, 4) for v in shapes)
+        assert all(c in (3, 4, 8) for c in info.entry_chunk)
         if kr:
             assert shapes == [kr] * 3 and info.tune_ms == 0.0
         else:
