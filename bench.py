@@ -190,6 +190,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-outer", type=int, default=1)
     ap.add_argument("--only-f3r", action="store_true", help="time the fp16-F3R solves only (profiling)")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="first run one plain device copy of MIB MiB (reference for HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU; --gpus {args.gpus} is not supported "
@@ -203,6 +205,13 @@ def main():
     import workloads as W
 
     torch.cuda.set_device(0)
+    if args.copy_calibration:
+        src = torch.ones(args.copy_calibration << 18, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"[bench] calibration copy of {args.copy_calibration} MiB done")
+        del src, dst
     name = args.workload
     if name == "varcoef2d_batch256":
         print(json.dumps(bench_batch(args, P, W, torch)), flush=True)
