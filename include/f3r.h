@@ -63,6 +63,8 @@ typedef int32_t f3r_status;
 #define F3R_USE_X0 1u          /* x holds the initial guess on entry */
 #define F3R_PERSIST_WEIGHTS 2u /* keep omega and c_ntr from the previous solve */
 #define F3R_NO_GRAPH 4u        /* launch kernels one by one, no hipGraph */
+#define F3R_BATCH_LOCKSTEP 8u  /* batches: solve the systems in lockstep with
+                                  the per-kernel path (see f3r_setup_batched) */
 
 /* kernels that f3r_params.probe_kernel can time with HIP events */
 #define F3R_PROBE_NONE 0
@@ -204,14 +206,23 @@ const char* f3r_status_str(f3r_status s);
 typedef struct f3r_batch f3r_batch;
 
 /* Sets up `count` systems (A: host array of count CSR matrices, each copied
-   and scaled as by f3r_setup).  The parameters must describe the narrow
-   F3R nest: nlev = 4; levels FGMRES (fp64, fp64), FGMRES (fp32, fp32),
-   FGMRES (narrow matrix, fp32 vectors), Richardson (narrow, narrow), with
-   prec_m = narrow, where narrow is F3R_FP16 or F3R_BF16 (the defaults of
-   F3R_VARIANT_FP16 and F3R_VARIANT_BF16); m1 <= 128 and m2, m3, m4 <= 16.
-   Flags: only F3R_USE_X0.  Weights and c_ntr restart for every system and
-   solve (Alg. 1).  Errors as f3r_setup; F3R_ERR_ARG also for parameters
-   outside this set.  *out is NULL on error. */
+   and scaled as by f3r_setup).  Two execution modes:
+   - default: one persistent launch, one workgroup per system (above).  The
+     parameters must describe the narrow F3R nest: nlev = 4; levels FGMRES
+     (fp64, fp64), FGMRES (fp32, fp32), FGMRES (narrow matrix, fp32
+     vectors), Richardson (narrow, narrow), with prec_m = narrow, where
+     narrow is F3R_FP16 or F3R_BF16 (the defaults of F3R_VARIANT_FP16 and
+     F3R_VARIANT_BF16); m1 <= 128 and m2, m3, m4 <= 16.  Flags: only
+     F3R_USE_X0.
+   - F3R_BATCH_LOCKSTEP in p->flags: the systems become the diagonal blocks
+     of one matrix (each padded with identity rows to a multiple of 1024
+     rows) solved by the per-kernel path of f3r_solve: every kernel covers
+     all systems, sums and level state are per system, and each system stops
+     at its own tolerance (its rows are then skipped).  Any nest f3r_setup
+     accepts; the Richardson call counter c_ntr is shared by the systems.
+   Weights and c_ntr restart for every solve (Alg. 1).  Errors as f3r_setup;
+   F3R_ERR_ARG also for parameters outside the mode's set.  *out is NULL on
+   error. */
 f3r_status f3r_setup_batched(int32_t count, const f3r_csr* A, const f3r_params* p,
                              void* hip_stream, f3r_batch** out);
 

@@ -38,6 +38,7 @@ struct f3r_batch {
   double setup_ms = 0;
   std::vector<BatchOut> hout;
   std::vector<double> hist;
+  f3r_handle* ls = nullptr;  // lockstep mode: the stacked systems
 };
 
 namespace {
@@ -96,6 +97,7 @@ extern "C" {
 
 void f3r_batch_destroy(f3r_batch* bt) {
   if (!bt) return;
+  if (bt->ls) f3r_destroy(bt->ls);
   (void)hipSetDevice(bt->device);
   if (bt->st) (void)hipStreamSynchronize(bt->st);
   bt->al.release_all();
@@ -106,7 +108,25 @@ f3r_status f3r_setup_batched(int32_t count, const f3r_csr* A, const f3r_params* 
                              f3r_batch** out) {
   if (!out) return F3R_ERR_ARG;
   *out = nullptr;
-  if (count < 1 || !A) return F3R_ERR_ARG;
+  if (count < 1 || !A || !p) return F3R_ERR_ARG;
+  if (p->flags & F3R_BATCH_LOCKSTEP) {
+    f3r_params q = *p;
+    q.flags &= ~F3R_BATCH_LOCKSTEP;
+    if (q.poison_call != 0 || q.probe_kernel != 0 || (q.flags & F3R_PERSIST_WEIGHTS)) return F3R_ERR_ARG;
+    f3r_batch* bt = new f3r_batch();
+    bt->p = *p;
+    bt->count = count;
+    bt->st = (hipStream_t)hip_stream;
+    const double t0 = now_ms();
+    const f3r_status st = stacked_setup(count, A, &q, hip_stream, &bt->ls);
+    bt->setup_ms = now_ms() - t0;
+    if (st != F3R_OK) {
+      f3r_batch_destroy(bt);
+      return st;
+    }
+    *out = bt;
+    return F3R_OK;
+  }
   const f3r_status ps = check_batch_params(p);
   if (ps != F3R_OK) return ps;
   f3r_batch* bt = new f3r_batch();
@@ -187,6 +207,12 @@ f3r_status f3r_solve_batched(f3r_batch* bt, const double* const* b, double* cons
   if (!bt || !b || !x || !(tol > 0.0)) return F3R_ERR_ARG;
   for (int i = 0; i < bt->count; i++)
     if (!b[i] || !x[i]) return F3R_ERR_ARG;
+  if (bt->ls) {
+    const f3r_status st = stacked_solve(bt->ls, b, x, tol, infos);
+    if (infos)
+      for (int i = 0; i < bt->count; i++) infos[i].setup_ms = bt->setup_ms;
+    return st;
+  }
   int32_t herr = 0;
   const double t0 = now_ms();
   f3r_status st = guarded_b(
@@ -271,6 +297,7 @@ f3r_status f3r_solve_batched(f3r_batch* bt, const double* const* b, double* cons
 f3r_status f3r_batch_get_history(const f3r_batch* bt, int32_t sys, double* buf, int64_t cap,
                                  int64_t* len) {
   if (!bt || sys < 0 || sys >= bt->count || cap < 0 || (cap > 0 && !buf)) return F3R_ERR_ARG;
+  if (bt->ls) return stacked_history(bt->ls, sys, buf, cap, len);
   const int64_t avail = bt->hout[(size_t)sys].outer;
   const int64_t k = std::min(cap, avail);
   const double* h = bt->hist.data() + (size_t)sys * (size_t)bt->p.max_outer;

@@ -86,7 +86,24 @@ struct f3r_handle {
   double* hpin = nullptr;  // pinned host words
   std::map<std::string, hipGraphExec_t> graphs;
   std::vector<hipGraph_t> graph_objs;
-  std::vector<double> history;
+  // several independent systems as the diagonal blocks of one matrix (see
+  // SysLayout): rows of system s start at sys_row0[s] (a multiple of 1024)
+  // and its first sys_n[s] rows are its own (the rest are identity rows)
+  int nsys = 1;
+  std::vector<int64_t> sys_row0, sys_n;
+  double* Sall = nullptr;  // per-system level scalars, nsys x dS
+  int* Iall = nullptr;     // per-system level flags and counters, nsys x dI
+  int64_t dS = 0, dI = 0;
+  double* ibn = nullptr;   // device: 1 / ||b_s|| per system
+  int* mask = nullptr;     // device: nsys ints (systems to hold)
+  // stacked systems: row ranges on the device, the caller's vector pointers
+  // and the stacked right-hand side and solution
+  int64_t* row0_dev = nullptr;
+  int64_t* nrows_dev = nullptr;
+  double** ptrs_dev = nullptr;
+  double* bcat = nullptr;
+  double* xcat = nullptr;
+  std::vector<std::vector<double>> history;  // per system
   // stats of the last solve
   int64_t graph_launches = 0;
   // kernel probe: event pairs around every launch of one kernel
@@ -166,6 +183,9 @@ void alloc_levels(f3r_handle* h) {
   const int64_t n = h->n;
   h->lev.assign(p.nlev, LevelRT{});
   h->rich = -1;
+  h->dS = 0;
+  h->dI = 0;
+  std::vector<int64_t> soff((size_t)p.nlev, 0), ioff((size_t)p.nlev, 0);
   for (int d = 0; d < p.nlev; d++) {
     LevelRT& L = h->lev[d];
     L.cfg = p.lev[d];
@@ -180,10 +200,10 @@ void alloc_levels(f3r_handle* h) {
       L.Z = h->dalloc((size_t)m * n * tsz(L.zt));
       if (d + 1 == p.nlev) L.tmp = h->dalloc((size_t)n * tsz(L.pv));
       L.L.init(m);
-      L.S = (double*)h->dalloc((size_t)L.L.total * sizeof(double));
-      L.I = (int*)h->dalloc((size_t)level_ints(m) * sizeof(int));
-      HIPCHK(hipMemsetAsync(L.S, 0, (size_t)L.L.total * sizeof(double), h->st));
-      HIPCHK(hipMemsetAsync(L.I, 0, (size_t)level_ints(m) * sizeof(int), h->st));
+      soff[d] = h->dS;
+      ioff[d] = h->dI;
+      h->dS += L.L.total;
+      h->dI += level_ints(m);
     } else {
       h->rich = d;
       L.rt = h->dalloc((size_t)n * tsz(L.pv));
@@ -191,11 +211,36 @@ void alloc_levels(f3r_handle* h) {
       L.rr = h->dalloc((size_t)n * tsz(L.pv));
       L.rz[0] = h->dalloc((size_t)n * tsz(L.pv));
       L.rz[1] = h->dalloc((size_t)n * tsz(L.pv));
-      L.omega = (double*)h->dalloc(64 * sizeof(double));
-      L.wcur = (double*)h->dalloc(sizeof(double));
+      soff[d] = h->dS;  // omega_1..64, then w_cur
+      h->dS += 65;
       L.cntr_dev = (int64_t*)h->dalloc(sizeof(int64_t));
-      HIPCHK(set_omega(h->st, L.omega, m, L.q == T32 ? (double)(float)p.omega_init : p.omega_init));
     }
+  }
+  // the scalars and flags of every level of every system in two arrays, so
+  // that system s's state is at a fixed distance from system 0's
+  const size_t ns = (size_t)h->nsys;
+  h->Sall = (double*)h->dalloc(ns * (size_t)h->dS * sizeof(double));
+  h->Iall = (int*)h->dalloc(ns * (size_t)std::max<int64_t>(h->dI, 1) * sizeof(int));
+  HIPCHK(hipMemsetAsync(h->Sall, 0, ns * (size_t)h->dS * sizeof(double), h->st));
+  HIPCHK(hipMemsetAsync(h->Iall, 0, ns * (size_t)std::max<int64_t>(h->dI, 1) * sizeof(int), h->st));
+  for (int d = 0; d < p.nlev; d++) {
+    LevelRT& L = h->lev[d];
+    if (L.cfg.kind == F3R_FGMRES) {
+      L.S = h->Sall + soff[d];
+      L.I = h->Iall + ioff[d];
+    } else {
+      L.omega = h->Sall + soff[d];
+      L.wcur = L.omega + 64;
+    }
+  }
+  h->A.sys.dS = h->dS;
+  h->A.sys.dI = h->dI;
+  h->ibn = (double*)h->dalloc(ns * sizeof(double));
+  h->mask = (int*)h->dalloc(ns * sizeof(int));
+  if (h->rich >= 0) {
+    const LevelRT& R = h->lev[h->rich];
+    HIPCHK(set_omega(h->st, h->A.sys, R.omega, R.cfg.m,
+                     R.q == T32 ? (double)(float)p.omega_init : p.omega_init));
   }
 }
 
@@ -310,9 +355,10 @@ void enqueue_rich(Ctx& c, int d, const Basis& vin, const int* stop, void* out, i
       HIPCHK(m_apply_g(c.st, h->A, mv, tm, neg, gd, R.rt, tr, 0, nullptr, nullptr, R.ry, tr, nullptr,
                        nullptr, stop, nullptr, h->kr[1]));
       HIPCHK(rich_tdots(c.st, h->A, av, R.pa, R.ry, tr, rsrc, h->partials, stop));
-      HIPCHK(rich_omega(c.st, q_of(tr), h->partials, nb, R.omega + k, R.wcur, R.cntr_dev, h->p.c,
-                        stop));
-      HIPCHK(rich_zupdate(c.st, h->n, k == 0 ? nullptr : zprev, R.ry, tr, R.wcur, zk, zfb, stop));
+      HIPCHK(rich_omega(c.st, h->A.sys, q_of(tr), h->partials, nb, R.omega + k, R.wcur, R.cntr_dev,
+                        h->p.c, stop));
+      HIPCHK(rich_zupdate(c.st, h->A.sys, h->n, k == 0 ? nullptr : zprev, R.ry, tr, R.wcur, zk, zfb,
+                          stop));
     }
     zprev = zk;
   }
@@ -353,10 +399,11 @@ void enqueue_fgmres(Ctx& c, int d, const Basis& vin, const void* alias_raw, cons
   const void* v0 = aliased ? alias_raw : L.V;
   if (!aliased) {
     ChildInit self{L.S, L.I, m, L.L.g, L.L.scale};
-    HIPCHK(entry_cast(c.st, n, vin, L.V, L.pv, h->partials, pstop));
-    HIPCHK(entry_finalize(c.st, L.q, h->partials, nb, self, child_alias ? &ci_child : nullptr, pstop));
+    HIPCHK(entry_cast(c.st, h->A.sys, n, vin, L.V, L.pv, h->partials, pstop));
+    HIPCHK(entry_finalize(c.st, h->A.sys, L.q, h->partials, nb, self,
+                          child_alias ? &ci_child : nullptr, pstop));
   } else if (child_alias) {
-    HIPCHK(child_init0(c.st, L.S, L.I, L.L, ci_child));
+    HIPCHK(child_init0(c.st, h->A.sys, L.S, L.I, L.L, ci_child));
   }
   const void* vb = vec_at(L.V, L.pv, 1, n);
   const int* stop = L.I + I_STOP;
@@ -386,19 +433,19 @@ void enqueue_fgmres(Ctx& c, int d, const Basis& vin, const void* alias_raw, cons
     HIPCHK(spmv_dots(c.st, h->A, h->ah[L.pa], L.pa, zj, L.zt, &bj, fbj, vec_at(L.V, L.pv, j + 1, n),
                      L.pv, v0, vb, j + 1, h->partials, stop));
     probe_end(c, pid);
-    HIPCHK(finalize_sums(c.st, L.q, h->partials, nb, j + 1, L.S + L.L.scale, hcol, stop));
-    HIPCHK(axpy_norm(c.st, n, vec_at(L.V, L.pv, j + 1, n), L.pv, v0, vb, j + 1, hcol, L.S + L.L.scale,
-                     h->partials, stop));
-    HIPCHK(givens(c.st, L.q, h->partials, nb, L.S, L.I, L.L, j, j == m - 1, 1.0, nullptr,
-                  child_alias ? &ci_child : nullptr));
+    HIPCHK(finalize_sums(c.st, h->A.sys, L.q, h->partials, nb, j + 1, L.S + L.L.scale, hcol, stop));
+    HIPCHK(axpy_norm(c.st, h->A.sys, n, vec_at(L.V, L.pv, j + 1, n), L.pv, v0, vb, j + 1, hcol,
+                     L.S + L.L.scale, h->partials, stop));
+    HIPCHK(givens(c.st, h->A.sys, L.q, h->partials, nb, L.S, L.I, L.L, j, j == m - 1, nullptr,
+                  nullptr, child_alias ? &ci_child : nullptr));
   }
   LevelBasis lb;
   lb.v0 = v0;
   lb.vb = vb;
   lb.type = L.pv;
   lb.scales = L.S + L.L.scale;
-  HIPCHK(combine(c.st, n, L.Z, L.zt, L.pv, L.S + L.L.y, L.I + I_MEFF, out.ptr, out.s, out.cur, 0, &lb,
-                 L.I + I_FB, out.fb));
+  HIPCHK(combine(c.st, h->A.sys, n, L.Z, L.zt, L.pv, L.S + L.L.y, L.I + I_MEFF, out.ptr, out.s,
+                 out.cur, 0, &lb, L.I + I_FB, out.fb, pstop));
 }
 
 // Set-up autotuner: times the candidate shapes (rows per lane and entry
@@ -420,6 +467,11 @@ void autotune(f3r_handle* h) {
   const void* mv = m_values(h, tm, neg);
   const double gd = h->gd[tm];
   const int64_t n = h->n;
+  // The candidates run on the matrix without its system layout: the
+  // pointers passed here (a constant 1.0 as scale and weight, scratch
+  // vectors) are not per-system state, so no kernel may shift them.
+  SellDesc At = h->A;
+  At.sys = SysLayout{};
   // inputs with ordinary finite values (byte pattern 0x3C in every format)
   HIPCHK(hipMemsetAsync(R.rr, 0x3C, (size_t)n * tsz(tr), h->st));
   HIPCHK(hipMemsetAsync(R.rz[0], 0x3C, (size_t)n * tsz(tr), h->st));
@@ -443,12 +495,12 @@ void autotune(f3r_handle* h) {
       const int kr = cand[c];
       auto launch = [&]() {
         if (f == 0)
-          HIPCHK(m_apply_w(h->st, h->A, mv, tm, neg, vec, R.rt, tr, nullptr, nullptr, kr));
+          HIPCHK(m_apply_w(h->st, At, mv, tm, neg, vec, R.rt, tr, nullptr, nullptr, kr));
         else if (f == 1)
-          HIPCHK(m_apply_g(h->st, h->A, mv, tm, neg, gd, R.rr, tr, 2, h->one, R.rz[0], R.rt, tr,
+          HIPCHK(m_apply_g(h->st, At, mv, tm, neg, gd, R.rr, tr, 2, h->one, R.rz[0], R.rt, tr,
                            nullptr, nullptr, nullptr, nullptr, kr));
         else
-          HIPCHK(rich_residual(h->st, h->A, h->ah[R.pa], R.pa, basis, R.rz[0], R.rt, tr, nullptr, kr));
+          HIPCHK(rich_residual(h->st, At, h->ah[R.pa], R.pa, basis, R.rz[0], R.rt, tr, nullptr, kr));
       };
       launch();
       HIPCHK(hipEventRecord(e0, h->st));
@@ -512,12 +564,14 @@ struct SolveStats {
   double est = 0, relres = 0;
 };
 
-void f2_call(f3r_handle* h, SolveStats& ss, bool use_graph) {
+// one call of the second level for every system; returns the number of
+// Richardson calls of it that update the weights
+int64_t f2_call(f3r_handle* h, SolveStats& ss, bool use_graph) {
   LevelRT& L0 = h->lev[0];
   const int64_t ncalls = r_calls_per_f2(h->p);
   RSched rs = make_sched(h, ncalls, ss.r_calls);
   if (h->rich >= 0 && h->cntr == 1)  // Alg. 1: the first call sets every weight to omega_init
-    HIPCHK(set_omega(h->st, h->lev[h->rich].omega, h->lev[h->rich].cfg.m, omega_init_q(h)));
+    HIPCHK(set_omega(h->st, h->A.sys, h->lev[h->rich].omega, h->lev[h->rich].cfg.m, omega_init_q(h)));
   Basis in;
   in.raw = L0.V;
   in.type = T64;
@@ -559,9 +613,12 @@ void f2_call(f3r_handle* h, SolveStats& ss, bool use_graph) {
     Ctx c{h, h->st, &rs};
     enqueue_fgmres(c, 1, in, nullptr, L0.I + I_STOP, out, false);
   }
-  for (int64_t i = 0; i < ncalls; i++) ss.upd_calls += rs.upd[(size_t)i];
+  int64_t upd = 0;
+  for (int64_t i = 0; i < ncalls; i++) upd += rs.upd[(size_t)i];
+  ss.upd_calls += upd;
   h->cntr += ncalls;
   ss.r_calls += ncalls;
+  return upd;
 }
 
 void baseline_prec(f3r_handle* h) {
@@ -581,172 +638,246 @@ void baseline_prec(f3r_handle* h) {
                    T64, h->s, L0.I + I_FB, L0.I + I_STOP, L0.I + I_CUR));
 }
 
+// Per-system record of one solve.
+struct SysStat {
+  f3r_status status = F3R_NOT_CONVERGED;
+  int outer = 0, restarts = 0;
+  int64_t r_calls = 0, upd_calls = 0, m_calls = 0;
+  double est = 0, relres = 0;
+  bool hold = false;   // finished (or failed): its rows are skipped by every kernel
+  bool run = false;    // iterating in the current cycle
+};
+
+void upload_holds(f3r_handle* h, const std::vector<SysStat>& ss) {
+  std::vector<int> m((size_t)h->nsys);
+  for (int s = 0; s < h->nsys; s++) m[(size_t)s] = ss[(size_t)s].hold ? 1 : 0;
+  // ordered after the stream's earlier work, complete before m goes away
+  HIPCHK(hipStreamSynchronize(h->st));
+  HIPCHK(hipMemcpy(h->mask, m.data(), m.size() * sizeof(int), hipMemcpyHostToDevice));
+  HIPCHK(sys_hold(h->st, h->A.sys, h->lev[0].I, h->mask));
+}
+
+// The outermost FGMRES(m1) of every system in lockstep: one F2 call and one
+// outermost step per iteration for all systems that are still iterating;
+// a system whose estimate reaches tol (or breaks down) stops its rows on
+// the device and waits for the end of the cycle, where x += Z y and the true
+// residual are formed for every system at once.  With one system this is
+// exactly the restarted FGMRES of Sec. 4.2 with the host check of Sec. 5.2.
 f3r_status outer_solve(f3r_handle* h, const double* b, double* x, double tol, int m1, int max_outer,
-                       bool baseline, bool use_graph, f3r_info* info) {
+                       bool baseline, bool use_graph, f3r_info* infos) {
   const int64_t n = h->n;
   const int64_t nb = n_blocks(n);
+  const int ns = h->nsys;
+  const SysLayout& sl = h->A.sys;
   LevelRT& L0 = h->lev[0];
   if (m1 > L0.cfg.m) return F3R_ERR_ARG;
   const double t0 = now_ms();
-  SolveStats ss;
-  h->history.clear();
+  SolveStats gs;
+  std::vector<SysStat> ss((size_t)ns);
+  h->history.assign((size_t)ns, std::vector<double>());
   h->graph_launches = 0;
   h->probe = h->p.probe_kernel;
   h->probe_ms = 0;
   h->probe_n = 0;
   h->ev_used = 0;
   if (h->probe) use_graph = false;
+  const int64_t per_f2 = baseline ? 0 : r_calls_per_f2(h->p);
+  int64_t m_per_outer = 1;
+  if (!baseline)
+    for (int d = 1; d < h->p.nlev; d++) m_per_outer *= h->p.lev[d].m;
   if (!(h->p.flags & F3R_USE_X0)) HIPCHK(hipMemsetAsync(x, 0, (size_t)n * sizeof(double), h->st));
   if (h->rich >= 0 && !(h->p.flags & F3R_PERSIST_WEIGHTS)) {
     h->cntr = 1;
-    HIPCHK(hipMemcpyAsync(h->lev[h->rich].cntr_dev, &h->cntr, sizeof(int64_t), hipMemcpyHostToDevice,
-                          h->st));
+    // synchronous: the host copy of the counter changes as calls are enqueued
+    HIPCHK(hipStreamSynchronize(h->st));
+    HIPCHK(hipMemcpy(h->lev[h->rich].cntr_dev, &h->cntr, sizeof(int64_t), hipMemcpyHostToDevice));
   }
-  HIPCHK(hipMemsetAsync(L0.I, 0, (size_t)level_ints(L0.cfg.m) * sizeof(int), h->st));
-  for (size_t d = 1; d < h->lev.size(); d++)
-    if (h->lev[d].I)
-      HIPCHK(hipMemsetAsync(h->lev[d].I + I_FALLBACKS, 0, 2 * sizeof(int), h->st));
-  HIPCHK(dot64_to_host(h->st, n, b, b, h->partials, h->hpin + 4));
+  // every level's flags and counters of every system start clear
+  HIPCHK(hipMemsetAsync(h->Iall, 0, (size_t)ns * (size_t)h->dI * sizeof(int), h->st));
+  HIPCHK(dot64_to_host(h->st, sl, n, b, b, h->partials, h->hpin));
   HIPCHK(hipStreamSynchronize(h->st));
-  const double bnorm = std::sqrt(h->hpin[4]);
-  f3r_status status = F3R_NOT_CONVERGED;
-  if (bnorm == 0.0) {
-    HIPCHK(hipMemsetAsync(x, 0, (size_t)n * sizeof(double), h->st));
-    HIPCHK(hipStreamSynchronize(h->st));
-    ss.relres = 0.0;
-    status = F3R_OK;
-  } else if (!std::isfinite(bnorm)) {
-    status = F3R_ERR_ARG;
-  } else {
-    const double inv_bnorm = 1.0 / bnorm;
-    HIPCHK(residual64(h->st, h->A, h->a64, x, b, (double*)L0.V, h->partials));
-    HIPCHK(residual_finalize(h->st, h->partials, nb, L0.S, L0.I, L0.L, inv_bnorm, h->hpin));
-    HIPCHK(hipStreamSynchronize(h->st));
-    ss.relres = h->hpin[0];
-    if (ss.relres < tol) status = F3R_OK;
-    while (status == F3R_NOT_CONVERGED && ss.outer < max_outer) {
-      const int len = std::min(m1, max_outer - ss.outer);
-      int it = 0;
-      bool bad = false;
-      for (int j = 0; j < len; j++) {
-        if (baseline) {
-          baseline_prec(h);
-          ss.m_calls += 1;
-        } else {
-          f2_call(h, ss, use_graph);
-        }
-        void* zj = vec_at(L0.Z, T64, j, n);
-        Basis bj;
-        bj.raw = vec_at(L0.V, T64, j, n);
-        bj.type = T64;
-        bj.scale = L0.S + L0.L.scale + j;
-        Ctx c0{h, h->st, nullptr};
-        probe_begin(c0, F3R_PROBE_SPMV_L0);
-        HIPCHK(spmv_dots(h->st, h->A, h->a64, T64, zj, T64, &bj, L0.I + I_FB + j,
-                         vec_at(L0.V, T64, j + 1, n), T64, L0.V, vec_at(L0.V, T64, 1, n), j + 1,
-                         h->partials, L0.I + I_STOP));
-        probe_end(c0, F3R_PROBE_SPMV_L0);
-        double* hcol = L0.S + L0.L.H + (int64_t)j * (L0.cfg.m + 1);
-        HIPCHK(finalize_sums(h->st, T64, h->partials, nb, j + 1, L0.S + L0.L.scale, hcol,
-                             L0.I + I_STOP));
-        HIPCHK(axpy_norm(h->st, n, vec_at(L0.V, T64, j + 1, n), T64, L0.V, vec_at(L0.V, T64, 1, n),
-                         j + 1, hcol, L0.S + L0.L.scale, h->partials, L0.I + I_STOP));
-        HIPCHK(givens(h->st, T64, h->partials, nb, L0.S, L0.I, L0.L, j, 0, inv_bnorm, h->hpin,
-                      nullptr));
-        HIPCHK(hipStreamSynchronize(h->st));
-        probe_collect(h);
-        it++;
-        ss.outer++;
-        ss.est = h->hpin[0];
-        h->history.push_back(ss.est);
-        const int flags = (int)h->hpin[1];
-        if (flags & 2) {
-          bad = true;
-          break;
-        }
-        if (ss.est < tol || (flags & 1)) break;
-      }
-      if (bad) {
-        status = F3R_ERR_BREAKDOWN;
-        break;
-      }
-      HIPCHK(backsolve(h->st, T64, L0.S, L0.I, L0.L));
-      LevelBasis lb;
-      lb.v0 = L0.V;
-      lb.vb = vec_at(L0.V, T64, 1, n);
-      lb.type = T64;
-      lb.scales = L0.S + L0.L.scale;
-      HIPCHK(combine(h->st, n, L0.Z, T64, T64, L0.S + L0.L.y, L0.I + I_MEFF, x, nullptr, nullptr, 1,
-                     &lb, L0.I + I_FB, nullptr));
-      HIPCHK(residual64(h->st, h->A, h->a64, x, b, (double*)L0.V, h->partials));
-      HIPCHK(residual_finalize(h->st, h->partials, nb, L0.S, L0.I, L0.L, inv_bnorm, h->hpin));
-      HIPCHK(hipStreamSynchronize(h->st));
-      ss.relres = h->hpin[0];
-      if (!std::isfinite(ss.relres)) {
-        status = F3R_ERR_BREAKDOWN;
-        break;
-      }
-      if (ss.relres < tol) {
-        status = F3R_OK;
-        break;
-      }
-      ss.restarts++;
-      if (it == 0) break;
+  std::vector<double> ibn((size_t)ns, 0.0);
+  for (int s = 0; s < ns; s++) {
+    SysStat& q = ss[(size_t)s];
+    const double bnorm = std::sqrt(h->hpin[4 * s]);
+    if (bnorm == 0.0) {
+      const int64_t r0 = h->sys_row0[(size_t)s];
+      HIPCHK(hipMemsetAsync(x + r0, 0, (size_t)h->sys_n[(size_t)s] * sizeof(double), h->st));
+      q.status = F3R_OK;
+      q.hold = true;
+    } else if (!std::isfinite(bnorm)) {
+      q.status = F3R_ERR_ARG;
+      q.hold = true;
+    } else {
+      ibn[(size_t)s] = 1.0 / bnorm;
     }
+  }
+  HIPCHK(hipMemcpy(h->ibn, ibn.data(), ibn.size() * sizeof(double), hipMemcpyHostToDevice));
+  upload_holds(h, ss);
+  auto any_open = [&]() {
+    for (const SysStat& q : ss)
+      if (!q.hold) return true;
+    return false;
+  };
+  if (any_open()) {
+    HIPCHK(residual64(h->st, h->A, h->a64, x, b, (double*)L0.V, h->partials));
+    HIPCHK(residual_finalize(h->st, sl, h->partials, nb, L0.S, L0.I, L0.L, h->ibn, h->hpin));
+    HIPCHK(hipStreamSynchronize(h->st));
+    for (int s = 0; s < ns; s++) {
+      SysStat& q = ss[(size_t)s];
+      if (q.hold) continue;
+      q.relres = h->hpin[4 * s];
+      if (q.relres < tol) {
+        q.status = F3R_OK;
+        q.hold = true;
+      }
+    }
+    upload_holds(h, ss);
+  }
+  while (any_open()) {
+    int omax = 0;
+    for (SysStat& q : ss) {
+      q.run = !q.hold;
+      if (q.run) omax = std::max(omax, q.outer);
+    }
+    const int len = std::min(m1, max_outer - omax);
+    int it = 0;
+    for (int j = 0; j < len; j++) {
+      int64_t upd = 0;
+      if (baseline)
+        baseline_prec(h);
+      else
+        upd = f2_call(h, gs, use_graph);
+      void* zj = vec_at(L0.Z, T64, j, n);
+      Basis bj;
+      bj.raw = vec_at(L0.V, T64, j, n);
+      bj.type = T64;
+      bj.scale = L0.S + L0.L.scale + j;
+      Ctx c0{h, h->st, nullptr};
+      probe_begin(c0, F3R_PROBE_SPMV_L0);
+      HIPCHK(spmv_dots(h->st, h->A, h->a64, T64, zj, T64, &bj, L0.I + I_FB + j,
+                       vec_at(L0.V, T64, j + 1, n), T64, L0.V, vec_at(L0.V, T64, 1, n), j + 1,
+                       h->partials, L0.I + I_STOP));
+      probe_end(c0, F3R_PROBE_SPMV_L0);
+      double* hcol = L0.S + L0.L.H + (int64_t)j * (L0.cfg.m + 1);
+      HIPCHK(finalize_sums(h->st, sl, T64, h->partials, nb, j + 1, L0.S + L0.L.scale, hcol,
+                           L0.I + I_STOP));
+      HIPCHK(axpy_norm(h->st, sl, n, vec_at(L0.V, T64, j + 1, n), T64, L0.V, vec_at(L0.V, T64, 1, n),
+                       j + 1, hcol, L0.S + L0.L.scale, h->partials, L0.I + I_STOP));
+      HIPCHK(givens(h->st, sl, T64, h->partials, nb, L0.S, L0.I, L0.L, j, 0, h->ibn, h->hpin, nullptr,
+                    tol));
+      HIPCHK(hipStreamSynchronize(h->st));
+      probe_collect(h);
+      it++;
+      bool more = false;
+      for (int s = 0; s < ns; s++) {
+        SysStat& q = ss[(size_t)s];
+        if (!q.run) continue;
+        q.outer++;
+        q.r_calls += per_f2;
+        q.upd_calls += upd;
+        q.m_calls += baseline ? 1 : m_per_outer;
+        q.est = h->hpin[4 * s];
+        h->history[(size_t)s].push_back(q.est);
+        const int flags = (int)h->hpin[4 * s + 1];
+        if (flags & 2) {
+          q.status = F3R_ERR_BREAKDOWN;
+          q.run = false;
+          q.hold = true;  // x is left as it is (no update from a broken cycle)
+        } else if (q.est < tol || (flags & 1)) {
+          q.run = false;
+        }
+        more = more || q.run;
+      }
+      if (!more) break;
+    }
+    upload_holds(h, ss);
+    HIPCHK(backsolve(h->st, sl, T64, L0.S, L0.I, L0.L));
+    LevelBasis lb;
+    lb.v0 = L0.V;
+    lb.vb = vec_at(L0.V, T64, 1, n);
+    lb.type = T64;
+    lb.scales = L0.S + L0.L.scale;
+    HIPCHK(combine(h->st, sl, n, L0.Z, T64, T64, L0.S + L0.L.y, L0.I + I_MEFF, x, nullptr, nullptr, 1,
+                   &lb, L0.I + I_FB, nullptr, L0.I + I_HOLD));
+    HIPCHK(residual64(h->st, h->A, h->a64, x, b, (double*)L0.V, h->partials));
+    HIPCHK(residual_finalize(h->st, sl, h->partials, nb, L0.S, L0.I, L0.L, h->ibn, h->hpin));
+    HIPCHK(hipStreamSynchronize(h->st));
+    for (int s = 0; s < ns; s++) {
+      SysStat& q = ss[(size_t)s];
+      if (q.hold) continue;
+      q.relres = h->hpin[4 * s];
+      if (!std::isfinite(q.relres)) {
+        q.status = F3R_ERR_BREAKDOWN;
+        q.hold = true;
+      } else if (q.relres < tol) {
+        q.status = F3R_OK;
+        q.hold = true;
+      } else {
+        q.restarts++;
+        if (q.outer >= max_outer || it == 0) q.hold = true;  // not converged
+      }
+    }
+    upload_holds(h, ss);
   }
   const double t1 = now_ms();
-  if (info) {
-    std::memset(info, 0, sizeof(*info));
-    info->status = status;
-    info->outer_iters = ss.outer;
-    info->restarts = ss.restarts;
+  probe_collect(h);
+  f3r_status worst = F3R_OK;
+  auto severity = [](f3r_status st) { return st == F3R_OK ? 0 : st == F3R_NOT_CONVERGED ? 1 : 2 - st; };
+  for (const SysStat& q : ss)
+    if (severity(q.status) > severity(worst)) worst = q.status;
+  if (infos) {
+    // per-system counters of every level
+    std::vector<int> iall((size_t)ns * (size_t)h->dI);
+    HIPCHK(hipMemcpy(iall.data(), h->Iall, iall.size() * sizeof(int), hipMemcpyDeviceToHost));
     const f3r_params& p = h->p;
-    if (baseline) {
-      info->m_calls = ss.m_calls;
-      info->spmv[0] = ss.outer;
-    } else {
-      int64_t per = 1;  // calls of level d per outermost iteration
-      info->spmv[0] = ss.outer;
-      for (int d = 1; d < p.nlev; d++) {
-        if (p.lev[d].kind == F3R_FGMRES) {
-          info->spmv[d] = (int64_t)ss.outer * per * p.lev[d].m;
-        } else {
-          info->spmv[d] = ss.r_calls * (p.lev[d].m - 1) + ss.upd_calls * p.lev[d].m;
+    for (int s = 0; s < ns; s++) {
+      const SysStat& q = ss[(size_t)s];
+      f3r_info* info = infos + s;
+      std::memset(info, 0, sizeof(*info));
+      info->status = q.status;
+      info->outer_iters = q.outer;
+      info->restarts = q.restarts;
+      info->m_calls = q.m_calls;
+      info->spmv[0] = q.outer;
+      if (!baseline) {
+        int64_t per = 1;  // calls of level d per outermost iteration
+        for (int d = 1; d < p.nlev; d++) {
+          if (p.lev[d].kind == F3R_FGMRES)
+            info->spmv[d] = (int64_t)q.outer * per * p.lev[d].m;
+          else
+            info->spmv[d] = q.r_calls * (p.lev[d].m - 1) + q.upd_calls * p.lev[d].m;
+          per *= p.lev[d].m;
         }
-        per *= p.lev[d].m;
+        info->r_calls = q.r_calls;
       }
-      info->m_calls = (int64_t)ss.outer * per;
-      info->r_calls = ss.r_calls;
+      int64_t fbk = 0, brk = 0;
+      for (size_t d = 0; d < h->lev.size(); d++) {
+        if (!h->lev[d].I) continue;
+        const int* I = iall.data() + (size_t)s * (size_t)h->dI + (size_t)(h->lev[d].I - h->Iall);
+        fbk += I[I_FALLBACKS];
+        brk += I[I_BREAKDOWNS];
+      }
+      info->fallbacks = fbk;
+      info->breakdowns = brk;
+      info->relres_est = q.est;
+      info->relres_true = q.relres;
+      info->setup_ms = h->setup_ms;
+      info->solve_ms = t1 - t0;
+      info->graph_launches = h->graph_launches;
+      info->idx_bits = h->A.idx16 ? 16 : 32;
+      info->sell_c = 64;
+      info->probe_ms = h->probe_ms;
+      info->probe_launches = h->probe_n;
+      info->padded_nnz = h->padded;
+      for (int f = 0; f < 3; f++) {
+        info->rows_per_lane[f] = h->kr[f] / 10;
+        info->entry_chunk[f] = h->kr[f] % 10;
+      }
+      info->tune_ms = h->tune_ms;
     }
-    // device counters
-    int64_t fbk = 0, brk = 0;
-    for (size_t d = 0; d < h->lev.size(); d++) {
-      if (!h->lev[d].I) continue;
-      int v[2];
-      HIPCHK(hipMemcpy(v, h->lev[d].I + I_FALLBACKS, 2 * sizeof(int), hipMemcpyDeviceToHost));
-      fbk += v[0];
-      brk += v[1];
-    }
-    info->fallbacks = fbk;
-    info->breakdowns = brk;
-    info->relres_est = ss.est;
-    info->relres_true = ss.relres;
-    info->setup_ms = h->setup_ms;
-    info->solve_ms = t1 - t0;
-    info->graph_launches = h->graph_launches;
-    info->idx_bits = h->A.idx16 ? 16 : 32;
-    info->sell_c = 64;
-    probe_collect(h);
-    info->probe_ms = h->probe_ms;
-    info->probe_launches = h->probe_n;
-    info->padded_nnz = h->padded;
-    for (int f = 0; f < 3; f++) {
-      info->rows_per_lane[f] = h->kr[f] / 10;
-      info->entry_chunk[f] = h->kr[f] % 10;
-    }
-    info->tune_ms = h->tune_ms;
   }
-  return status;
+  return worst;
 }
 
 template <class F> f3r_status guarded(f3r_handle* h, f3r_info* info, F&& f) {
@@ -844,7 +975,14 @@ void f3r_destroy(f3r_handle* h) {
   delete h;
 }
 
-f3r_status f3r_setup(const f3r_csr* A, const f3r_params* p, void* hip_stream, f3r_handle** out) {
+}  // extern "C"
+
+namespace {
+// Set-up of one matrix holding nsys >= 1 systems on its diagonal; row0 (nsys
+// + 1 entries) and nrows describe the systems (see SysLayout).
+f3r_status setup_impl(const f3r_csr* A, const f3r_params* p, void* hip_stream, int nsys,
+                      const std::vector<int64_t>& row0, const std::vector<int64_t>& nrows,
+                      bool stacked, f3r_handle** out) {
   if (!out) return F3R_ERR_ARG;
   *out = nullptr;
   if (!A || !A->row_ptr || !A->col_idx || !A->val || A->n <= 0 || A->nnz < A->n) return F3R_ERR_ARG;
@@ -880,6 +1018,37 @@ f3r_status f3r_setup(const f3r_csr* A, const f3r_params* p, void* hip_stream, f3
     h->m_shared = m.m_shared;
     h->s = m.s;
     h->padded = m.padded;
+    h->nsys = nsys;
+    h->sys_row0 = row0;
+    h->sys_n = nrows;
+    if (stacked) {
+      // 1024-row block -> system, and each system's first block
+      const int64_t nblk = n / kSysAlign;
+      std::vector<int> blk((size_t)nblk), b0((size_t)nsys + 1);
+      for (int sy = 0; sy < nsys; sy++) {
+        b0[(size_t)sy] = (int)(row0[(size_t)sy] / kSysAlign);
+        for (int64_t k = row0[(size_t)sy] / kSysAlign; k < row0[(size_t)sy + 1] / kSysAlign; k++)
+          blk[(size_t)k] = sy;
+      }
+      b0[(size_t)nsys] = (int)nblk;
+      int* dblk = (int*)h->dalloc(blk.size() * sizeof(int));
+      int* db0 = (int*)h->dalloc(b0.size() * sizeof(int));
+      // synchronous: the host vectors end with this block
+      HIPCHK(hipStreamSynchronize(h->st));
+      HIPCHK(hipMemcpy(dblk, blk.data(), blk.size() * sizeof(int), hipMemcpyHostToDevice));
+      HIPCHK(hipMemcpy(db0, b0.data(), b0.size() * sizeof(int), hipMemcpyHostToDevice));
+      h->A.sys.blk = dblk;
+      h->A.sys.b0 = db0;
+      h->A.sys.nsys = nsys;
+      h->row0_dev = (int64_t*)h->dalloc(row0.size() * sizeof(int64_t));
+      h->nrows_dev = (int64_t*)h->dalloc(nrows.size() * sizeof(int64_t));
+      h->ptrs_dev = (double**)h->dalloc((size_t)nsys * sizeof(double*));
+      h->bcat = (double*)h->dalloc((size_t)n * sizeof(double));
+      h->xcat = (double*)h->dalloc((size_t)n * sizeof(double));
+      HIPCHK(hipMemcpy(h->row0_dev, row0.data(), row0.size() * sizeof(int64_t), hipMemcpyHostToDevice));
+      HIPCHK(hipMemcpy(h->nrows_dev, nrows.data(), nrows.size() * sizeof(int64_t),
+                       hipMemcpyHostToDevice));
+    }
     // workspaces
     int maxdots = p->lev[0].m + 2;
     maxdots = std::max(maxdots, 66);
@@ -889,8 +1058,9 @@ f3r_status f3r_setup(const f3r_csr* A, const f3r_params* p, void* hip_stream, f3
     h->one = (double*)h->dalloc(sizeof(double));
     const double one = 1.0;
     HIPCHK(hipMemcpyAsync(h->one, &one, sizeof(double), hipMemcpyHostToDevice, h->st));
-    HIPCHK(hipHostMalloc((void**)&h->hpin, 64 * sizeof(double), hipHostMallocDefault));
-    std::memset(h->hpin, 0, 64 * sizeof(double));
+    HIPCHK(hipHostMalloc((void**)&h->hpin, (4 * (size_t)h->nsys + 16) * sizeof(double),
+                         hipHostMallocDefault));
+    std::memset(h->hpin, 0, (4 * (size_t)h->nsys + 16) * sizeof(double));
     alloc_levels(h);
     autotune(h);
     HIPCHK(hipStreamSynchronize(h->st));
@@ -903,6 +1073,17 @@ f3r_status f3r_setup(const f3r_csr* A, const f3r_params* p, void* hip_stream, f3
   }
   *out = h;
   return F3R_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+f3r_status f3r_setup(const f3r_csr* A, const f3r_params* p, void* hip_stream, f3r_handle** out) {
+  if (!out) return F3R_ERR_ARG;
+  *out = nullptr;
+  if (!A || A->n <= 0) return F3R_ERR_ARG;
+  return setup_impl(A, p, hip_stream, 1, {0, A->n}, {A->n}, false, out);
 }
 
 f3r_status f3r_solve(f3r_handle* h, const double* b, double* x, double tol,
@@ -956,9 +1137,11 @@ f3r_status f3r_fgmres_solve(f3r_handle* h, const double* b, double* x, double to
 f3r_status f3r_get_history(const f3r_handle* h, int32_t level, double* buf, int64_t cap,
                            int64_t* len) {
   if (!h || level != 0 || cap < 0 || (cap > 0 && !buf)) return F3R_ERR_ARG;
-  const int64_t k = std::min<int64_t>(cap, (int64_t)h->history.size());
-  for (int64_t i = 0; i < k; i++) buf[i] = h->history[(size_t)i];
-  if (len) *len = (int64_t)h->history.size();
+  const std::vector<double> none;
+  const std::vector<double>& hs = h->history.empty() ? none : h->history[0];
+  const int64_t k = std::min<int64_t>(cap, (int64_t)hs.size());
+  for (int64_t i = 0; i < k; i++) buf[i] = hs[(size_t)i];
+  if (len) *len = (int64_t)hs.size();
   return F3R_OK;
 }
 
@@ -1056,7 +1239,7 @@ f3r_status f3r_debug_apply_level(f3r_handle* h, int32_t level, const double* v, 
     }
     RSched rs = make_sched(h, ncalls, 0);
     if (h->rich >= 0 && h->cntr == 1)
-      HIPCHK(set_omega(h->st, h->lev[h->rich].omega, h->lev[h->rich].cfg.m, omega_init_q(h)));
+      HIPCHK(set_omega(h->st, h->A.sys, h->lev[h->rich].omega, h->lev[h->rich].cfg.m, omega_init_q(h)));
     Ctx c{h, h->st, &rs};
     // the level receives its input in the parent's vector precision
     const int tin = h->p.lev[level - 1].prec_v;
@@ -1118,3 +1301,93 @@ f3r_status f3r_debug_level_values(f3r_handle* h, int32_t prec, double* vals_host
 }
 
 }  // extern "C"
+
+// ===========================================================================
+// stacked systems (the lockstep mode of the batched entry points)
+// ===========================================================================
+namespace f3r {
+
+f3r_status stacked_setup(int32_t count, const f3r_csr* A, const f3r_params* p, void* hip_stream,
+                         f3r_handle** out) {
+  if (!out || count < 1 || !A) return F3R_ERR_ARG;
+  *out = nullptr;
+  std::vector<int64_t> row0((size_t)count + 1), nrows((size_t)count);
+  int64_t rows = 0, nnz = 0;
+  for (int s = 0; s < count; s++) {
+    const f3r_csr& a = A[s];
+    if (!a.row_ptr || !a.col_idx || !a.val || a.n <= 0 || a.nnz < a.n) return F3R_ERR_ARG;
+    if (a.row_ptr[0] != 0 || a.row_ptr[a.n] != a.nnz) return F3R_ERR_MATRIX;
+    row0[(size_t)s] = rows;
+    nrows[(size_t)s] = a.n;
+    const int64_t padded = (a.n + kSysAlign - 1) / kSysAlign * kSysAlign;
+    rows += padded;
+    nnz += a.nnz + (padded - a.n);
+  }
+  row0[(size_t)count] = rows;
+  if (rows >= ((int64_t)1 << 31) - 64 || nnz >= ((int64_t)1 << 31)) return F3R_ERR_ARG;
+  // one CSR matrix with the systems on its diagonal; each system is padded
+  // with identity rows to a multiple of 1024 rows (b = 0 there, so those
+  // rows stay zero in every vector and add nothing to any sum)
+  std::vector<int32_t> rp((size_t)rows + 1), ci((size_t)nnz);
+  std::vector<double> va((size_t)nnz);
+  int64_t k = 0;
+  for (int s = 0; s < count; s++) {
+    const f3r_csr& a = A[s];
+    const int64_t r0 = row0[(size_t)s];
+    for (int64_t i = 0; i < a.n; i++) {
+      rp[(size_t)(r0 + i)] = (int32_t)k;
+      if (a.row_ptr[i + 1] < a.row_ptr[i]) return F3R_ERR_MATRIX;
+      for (int64_t e = a.row_ptr[i]; e < a.row_ptr[i + 1]; e++) {
+        const int64_t c = a.col_idx[e];
+        if (c < 0 || c >= a.n) return F3R_ERR_MATRIX;
+        ci[(size_t)k] = (int32_t)(r0 + c);
+        va[(size_t)k] = a.val[e];
+        k++;
+      }
+    }
+    for (int64_t i = a.n; i < row0[(size_t)s + 1] - r0; i++) {
+      rp[(size_t)(r0 + i)] = (int32_t)k;
+      ci[(size_t)k] = (int32_t)(r0 + i);
+      va[(size_t)k] = 1.0;
+      k++;
+    }
+  }
+  rp[(size_t)rows] = (int32_t)k;
+  const f3r_csr cat{rows, nnz, rp.data(), ci.data(), va.data()};
+  return setup_impl(&cat, p, hip_stream, count, row0, nrows, true, out);
+}
+
+f3r_status stacked_solve(f3r_handle* h, const double* const* b, double* const* x, double tol,
+                         f3r_info* infos) {
+  if (!h || !b || !x || !(tol > 0.0) || !h->ptrs_dev) return F3R_ERR_ARG;
+  for (int s = 0; s < h->nsys; s++)
+    if (!b[s] || !x[s]) return F3R_ERR_ARG;
+  f3r_status st = guarded(h, nullptr, [&]() -> f3r_status {
+    HIPCHK(hipSetDevice(h->device));
+    const StackIo io{h->A.sys, h->row0_dev, h->nrows_dev, h->ptrs_dev, h->n};
+    HIPCHK(hipMemcpyAsync(h->ptrs_dev, b, (size_t)h->nsys * sizeof(double*), hipMemcpyHostToDevice,
+                          h->st));
+    HIPCHK(stack_gather(h->st, io, h->bcat));
+    HIPCHK(hipMemcpyAsync(h->ptrs_dev, x, (size_t)h->nsys * sizeof(double*), hipMemcpyHostToDevice,
+                          h->st));
+    if (h->p.flags & F3R_USE_X0) HIPCHK(stack_gather(h->st, io, h->xcat));
+    const f3r_status r = outer_solve(h, h->bcat, h->xcat, tol, h->p.lev[0].m, h->p.max_outer,
+                                     h->p.nlev < 2, !(h->p.flags & F3R_NO_GRAPH), infos);
+    HIPCHK(stack_scatter(h->st, io, h->xcat));
+    HIPCHK(hipStreamSynchronize(h->st));
+    return r;
+  });
+  return st;
+}
+
+f3r_status stacked_history(const f3r_handle* h, int32_t sys, double* buf, int64_t cap, int64_t* len) {
+  if (!h || sys < 0 || sys >= h->nsys || cap < 0 || (cap > 0 && !buf)) return F3R_ERR_ARG;
+  const std::vector<double> none;
+  const std::vector<double>& hs = (size_t)sys < h->history.size() ? h->history[(size_t)sys] : none;
+  const int64_t k = std::min<int64_t>(cap, (int64_t)hs.size());
+  for (int64_t i = 0; i < k; i++) buf[i] = hs[(size_t)i];
+  if (len) *len = (int64_t)hs.size();
+  return F3R_OK;
+}
+
+}  // namespace f3r

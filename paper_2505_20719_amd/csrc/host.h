@@ -68,4 +68,15 @@ struct MatrixDev {
 f3r_status build_matrix(hipStream_t st, const f3r_csr* A, const f3r_params* p, const bool need[4],
                         DevAllocs& al, MatrixDev& m);
 
+// Several systems solved in lockstep by the per-kernel path: one handle whose
+// matrix holds the systems on its diagonal (each padded with identity rows
+// to a multiple of 1024), every kernel covering all systems, reductions and
+// level state per system.  b, x: host arrays of device pointers.
+f3r_status stacked_setup(int32_t count, const f3r_csr* A, const f3r_params* p, void* hip_stream,
+                         f3r_handle** out);
+f3r_status stacked_solve(f3r_handle* h, const double* const* b, double* const* x, double tol,
+                         f3r_info* infos);
+f3r_status stacked_history(const f3r_handle* h, int32_t sys, double* buf, int64_t cap,
+                           int64_t* len);
+
 }  // namespace f3r

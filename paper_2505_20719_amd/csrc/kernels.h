@@ -21,6 +21,22 @@ inline int q_of(int t) { return t == T64 ? T64 : T32; }
 // idx holds int16 offsets col - row when every offset fits, else int32
 // columns.  kd[r] is the position of the diagonal inside row r; kdr[s] packs
 // the smallest (low 16 bits) and largest (high 16 bits) kd of slice s.
+// Several independent systems can share one descriptor as the diagonal
+// blocks of one matrix: system s owns the rows of the 1024-row blocks
+// [b0[s], b0[s+1]) (its rows padded with identity rows to a multiple of
+// 1024), and its device state (level scalars, flags, weights) sits at
+// s * dS doubles and s * dI ints from system 0's.  Every kernel offsets the
+// state pointers it is given by the system of its rows; reductions are
+// summed per system.  One system: blk = b0 = nullptr.
+constexpr int kSysAlign = 1024;  // rows of one reduction block; systems start at multiples
+
+struct SysLayout {
+  const int* blk = nullptr;  // system of each 1024-row block
+  const int* b0 = nullptr;   // first 1024-row block of each system, nsys + 1 entries
+  int nsys = 1;
+  int64_t dS = 0, dI = 0;
+};
+
 struct SellDesc {
   int64_t n = 0, ns = 0;
   const uint32_t* off = nullptr;
@@ -28,6 +44,7 @@ struct SellDesc {
   int idx16 = 0;
   const uint16_t* kd = nullptr;
   const uint32_t* kdr = nullptr;
+  SysLayout sys;
 };
 
 __host__ __device__ inline int64_t n_slices(int64_t n) { return (n + 63) / 64; }
@@ -61,14 +78,14 @@ hipError_t spmv_dots(hipStream_t st, const SellDesc& A, const void* av, int ta,
 
 // dst[l] = round_q(sum_b partials[l nb + b] * (scales ? scales[l] : 1)),
 // one block per l; dst entries are doubles holding q values.
-hipError_t finalize_sums(hipStream_t st, int q, const void* partials, int64_t nb,
-                         int count, const double* scales, double* dst,
+hipError_t finalize_sums(hipStream_t st, const SysLayout& sl, int q, const void* partials,
+                         int64_t nb, int count, const double* scales, double* dst,
                          const int* stop);
 
 // w_i <- round(w_i - sum_l round(h_l * round(raw_l,i * scale_l))) and partial
 // sums of w_i^2 at partials[b].
-hipError_t axpy_norm(hipStream_t st, int64_t n, void* w, int tw, const void* v0,
-                     const void* vb, int nv, const double* h,
+hipError_t axpy_norm(hipStream_t st, const SysLayout& sl, int64_t n, void* w, int tw,
+                     const void* v0, const void* vb, int nv, const double* h,
                      const double* scales, void* partials, const int* stop);
 
 // Layout of the device scalars of one FGMRES level (doubles).
@@ -92,7 +109,9 @@ struct LevelLayout {
   }
 };
 // ints of one FGMRES level
-enum { I_MEFF = 0, I_STOP = 1, I_CUR = 2, I_BAD = 3, I_FALLBACKS = 4, I_BREAKDOWNS = 5, I_FB = 8 };
+// I_HOLD (outermost level): the system has finished and its rows are skipped
+enum { I_MEFF = 0, I_STOP = 1, I_CUR = 2, I_BAD = 3, I_FALLBACKS = 4, I_BREAKDOWNS = 5, I_HOLD = 6,
+       I_FB = 8 };
 inline int level_ints(int m) { return I_FB + m + 8; }
 
 struct ChildInit {  // state of a child FGMRES level reset by its parent
@@ -105,12 +124,16 @@ struct ChildInit {  // state of a child FGMRES level reset by its parent
 // Givens step j of a level whose arithmetic is q (one block):
 // h_{j+1,j} = sqrt(sum partials); rotations; g; scale_{j+1} = 1/h_{j+1,j};
 // breakdown/stop handling; when solve_y, back-substitution R y = g.
-// host_out (pinned host, outermost only): [0] = |g_{j+1}| / ||b||, [1] flags.
-hipError_t givens(hipStream_t st, int q, const void* partials, int64_t nb,
+// host_out (pinned host, outermost only; 4 words per system): [0] =
+// |g_{j+1}| / ||b|| with inv_bnorm[s] = 1 / ||b_s||, [1] flags; with tol > 0
+// a system whose estimate is below tol stops.  One block per system.
+hipError_t givens(hipStream_t st, const SysLayout& sl, int q, const void* partials, int64_t nb,
                   double* S, int* I, const LevelLayout& L, int j, int solve_y,
-                  double inv_bnorm, double* host_out, const ChildInit* child);
+                  const double* inv_bnorm, double* host_out, const ChildInit* child,
+                  double tol = 0.0);
 
-hipError_t backsolve(hipStream_t st, int q, double* S, int* I, const LevelLayout& L);
+hipError_t backsolve(hipStream_t st, const SysLayout& sl, int q, double* S, int* I,
+                     const LevelLayout& L);
 
 // The basis of one FGMRES level: V_0 = v0, V_j = vb + (j-1) n, each held
 // lazily normalised by scales[j].
@@ -126,34 +149,37 @@ struct LevelBasis {
 // in fp64; with accumulate: out_i += u_i; otherwise out_i = u_i (type tv).
 // When `cur` is set the output vector is out + (*cur) n.  fb: per-column
 // flags; a flagged column uses the basis vector V_j instead of Z_j.
-hipError_t combine(hipStream_t st, int64_t n, const void* Z, int tz, int tv,
-                   const double* y, const int* meff, void* out, const double* s,
+// Rows of systems whose pstop flag is set are left alone.
+hipError_t combine(hipStream_t st, const SysLayout& sl, int64_t n, const void* Z, int tz,
+                   int tv, const double* y, const int* meff, void* out, const double* s,
                    const int* cur, int accumulate, const LevelBasis* alt,
-                   const int* fb, int* out_fb);
+                   const int* fb, int* out_fb, const int* pstop);
 
 // Entry of an FGMRES level: out = round_to(to, basis value) and partial
 // sums of out^2 (arithmetic q_of(to)); then the level state is reset with
 // beta = ||out||.
-hipError_t entry_cast(hipStream_t st, int64_t n, const Basis& in, void* out, int to,
-                      void* partials, const int* parent_stop);
-hipError_t entry_finalize(hipStream_t st, int q, const void* partials, int64_t nb,
-                          const ChildInit& lev, const ChildInit* child, const int* parent_stop);
+hipError_t entry_cast(hipStream_t st, const SysLayout& sl, int64_t n, const Basis& in,
+                      void* out, int to, void* partials, const int* parent_stop);
+hipError_t entry_finalize(hipStream_t st, const SysLayout& sl, int q, const void* partials,
+                          int64_t nb, const ChildInit& lev, const ChildInit* child,
+                          const int* parent_stop);
 // state of an aliased child for its first call: scale_0 and beta of the
 // level's own V_0, stop flag copied
-hipError_t child_init0(hipStream_t st, double* S, int* I, const LevelLayout& L,
-                       const ChildInit& child);
+hipError_t child_init0(hipStream_t st, const SysLayout& sl, double* S, int* I,
+                       const LevelLayout& L, const ChildInit& child);
 
 // outermost: r = b - A x (fp64) into r, partial sums of r^2
 hipError_t residual64(hipStream_t st, const SellDesc& A, const double* a64,
                       const double* x, const double* b, double* r, void* partials);
-// beta = ||r||; S.scale[0], S.g, I (meff, stop, cur, bad) reset; host_out[0] =
-// beta * inv_bnorm, host_out[2] = beta
-hipError_t residual_finalize(hipStream_t st, const void* partials, int64_t nb,
-                             double* S, int* I, const LevelLayout& L, double inv_bnorm,
-                             double* host_out);
-// partial sums of x_i y_i (fp64), then sum into host_out[slot]
-hipError_t dot64_to_host(hipStream_t st, int64_t n, const double* x, const double* y,
-                         void* partials, double* host_out);
+// per system: beta = ||r||; S.scale[0], S.g, I (meff, stop, cur, bad) reset;
+// host_out[4 s] = beta * inv_bnorm[s], host_out[4 s + 2] = beta.  A held
+// system (I[I_HOLD]) stays stopped.
+hipError_t residual_finalize(hipStream_t st, const SysLayout& sl, const void* partials,
+                             int64_t nb, double* S, int* I, const LevelLayout& L,
+                             const double* inv_bnorm, double* host_out);
+// partial sums of x_i y_i (fp64), then the sum of system s into host_out[4 s]
+hipError_t dot64_to_host(hipStream_t st, const SysLayout& sl, int64_t n, const double* x,
+                         const double* y, void* partials, double* host_out);
 
 // ---- primary preconditioner M = G W (two SpMVs) and Richardson ------------
 // t = round(u_i + sum_{k < kd} w_k u_c): W = I - L/alpha; `mv` (type tm) are
@@ -187,17 +213,33 @@ hipError_t rich_tdots(hipStream_t st, const SellDesc& A, const void* av, int ta,
                       const int* stop);
 // omega' = num / den; running mean of Eq. (5) with l = c_ntr / c, where the
 // device counter holds c_ntr + 1 during the call
-hipError_t rich_omega(hipStream_t st, int q, const void* partials, int64_t nb,
-                      double* omega_k, double* wcur, const int64_t* cntr, int c,
+hipError_t rich_omega(hipStream_t st, const SysLayout& sl, int q, const void* partials,
+                      int64_t nb, double* omega_k, double* wcur, const int64_t* cntr, int c,
                       const int* stop);
 // z = round(zprev + w y) (zprev may be null), w = *wcur
-hipError_t rich_zupdate(hipStream_t st, int64_t n, const void* zprev, const void* y,
-                        int tr, const double* wcur, void* z, int* fbflag,
+hipError_t rich_zupdate(hipStream_t st, const SysLayout& sl, int64_t n, const void* zprev,
+                        const void* y, int tr, const double* wcur, void* z, int* fbflag,
                         const int* stop);
+
+// ---- stacked systems: caller vectors <-> the stacked vector ---------------
+struct StackIo {
+  SysLayout sl;
+  const int64_t* row0 = nullptr;   // first row of each system (device)
+  const int64_t* nrows = nullptr;  // rows of each system (device)
+  double* const* ptrs = nullptr;   // the caller's vector of each system (device array)
+  int64_t n = 0;                   // stacked rows
+};
+// cat_i = ptrs[s][i - row0[s]] on the rows of system s, 0 on its padding
+hipError_t stack_gather(hipStream_t st, const StackIo& io, double* cat);
+// ptrs[s][i - row0[s]] = cat_i
+hipError_t stack_scatter(hipStream_t st, const StackIo& io, const double* cat);
 
 // ---- small utilities -------------------------------------------------------
 hipError_t convert(hipStream_t st, int64_t n, const void* in, int ti, void* out, int to);
 hipError_t fill_nan(hipStream_t st, void* p, int t, int64_t count, int* flag);
-hipError_t set_omega(hipStream_t st, double* omega, int m, double v);
+hipError_t set_omega(hipStream_t st, const SysLayout& sl, double* omega, int m, double v);
+// I[I_HOLD] = I[I_STOP] = 1 for the systems s with mask[s] != 0 (mask:
+// device, nsys ints; I: the outermost level's flags)
+hipError_t sys_hold(hipStream_t st, const SysLayout& sl, int* I, const int* mask);
 
 }  // namespace f3r

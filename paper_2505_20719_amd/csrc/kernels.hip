@@ -17,6 +17,8 @@
 
 namespace f3r {
 
+static_assert(kRowsPerBlock == kSysAlign, "systems are aligned to reduction blocks");
+
 template <class F> static hipError_t with_type(int t, F&& f) {
   switch (t) {
     case T64: return f((double*)nullptr);
@@ -70,10 +72,14 @@ __global__ __launch_bounds__(kBlock) void k_spmv_dots(SellDesc A, const TA* __re
                                                       const TY* __restrict__ vb, int nv,
                                                       Q* __restrict__ part, int64_t nb,
                                                       const int* stop) {
-  if (stop && *stop) return;
   __shared__ Q lds[kBlock / kWave][kDotChunk];
   const int64_t lb = logical_block(nb);
   if (lb >= nb) return;
+  const int sy = sys_of(A.sys, lb * kRowsPerBlock);
+  stop = sys_ptr(stop, sy, A.sys.dI);
+  if (stop && *stop) return;
+  fb = sys_ptr(fb, sy, A.sys.dI);
+  alt.at_sys(sy, A.sys);
   const int wave = threadIdx.x / kWave, lane = threadIdx.x & (kWave - 1);
   RowSlot s[kR];
   make_slots(A, lb * 4 + wave, lane, s);
@@ -176,11 +182,16 @@ hipError_t spmv_dots(hipStream_t st, const SellDesc& A, const void* av, int ta, 
 template <class Q>
 __global__ __launch_bounds__(kFinBlock) void k_finalize(const Q* __restrict__ part, int64_t nb,
                                                         const double* scales, double* dst,
-                                                        const int* stop) {
+                                                        const int* stop, SysLayout sl) {
   __shared__ Q lds[kFinBlock / kWave];
-  const int l = blockIdx.x;
+  const int l = blockIdx.x, sy = blockIdx.y;
+  int64_t lo, hi;
+  sys_range(sl, sy, nb, lo, hi);
+  scales = sys_ptr(scales, sy, sl.dS);
+  dst = sys_ptr(dst, sy, sl.dS);
+  stop = sys_ptr(stop, sy, sl.dI);
   // partial loads first; the stop flag is read while they are in flight
-  Q s = thread_sum(part + (int64_t)l * nb, nb);
+  Q s = thread_sum(part + (int64_t)l * nb + lo, hi - lo);
   s = fin_block_sum(s, lds);
   if (threadIdx.x == 0 && !(stop && *stop)) {
     if (scales) s = s * (Q)scales[l];
@@ -188,15 +199,16 @@ __global__ __launch_bounds__(kFinBlock) void k_finalize(const Q* __restrict__ pa
   }
 }
 
-hipError_t finalize_sums(hipStream_t st, int q, const void* partials, int64_t nb, int count,
-                         const double* scales, double* dst, const int* stop) {
+hipError_t finalize_sums(hipStream_t st, const SysLayout& sl, int q, const void* partials, int64_t nb,
+                         int count, const double* scales, double* dst, const int* stop) {
   if (count <= 0) return hipSuccess;
+  const dim3 g((unsigned)count, (unsigned)sl.nsys);
   if (q == T64)
-    hipLaunchKernelGGL(k_finalize<double>, dim3(count), dim3(kFinBlock), 0, st,
-                       (const double*)partials, nb, scales, dst, stop);
+    hipLaunchKernelGGL(k_finalize<double>, g, dim3(kFinBlock), 0, st, (const double*)partials, nb,
+                       scales, dst, stop, sl);
   else
-    hipLaunchKernelGGL(k_finalize<float>, dim3(count), dim3(kFinBlock), 0, st,
-                       (const float*)partials, nb, scales, dst, stop);
+    hipLaunchKernelGGL(k_finalize<float>, g, dim3(kFinBlock), 0, st, (const float*)partials, nb,
+                       scales, dst, stop, sl);
   return hipGetLastError();
 }
 
@@ -206,17 +218,21 @@ hipError_t finalize_sums(hipStream_t st, int q, const void* partials, int64_t nb
 constexpr int kMaxM = 1024;
 
 template <class TY, class Q>
-__global__ __launch_bounds__(kBlock) void k_axpy_norm(int64_t n, TY* __restrict__ w,
+__global__ __launch_bounds__(kBlock) void k_axpy_norm(SysLayout sl, int64_t n, TY* __restrict__ w,
                                                       const TY* __restrict__ v0,
                                                       const TY* __restrict__ vb, int nv,
                                                       const double* __restrict__ h,
                                                       const double* __restrict__ scales,
                                                       Q* __restrict__ part, int64_t nb,
                                                       const int* stop) {
-  if (stop && *stop) return;
   __shared__ Q lds[kBlock / kWave];
   const int64_t lb = logical_block(nb);
   if (lb >= nb) return;
+  const int sy = sys_of(sl, lb * kRowsPerBlock);
+  stop = sys_ptr(stop, sy, sl.dI);
+  if (stop && *stop) return;
+  h = sys_ptr(h, sy, sl.dS);
+  scales = sys_ptr(scales, sy, sl.dS);
   int64_t row[kR];
   bool ok[kR];
   Q acc[kR];
@@ -260,15 +276,15 @@ __global__ __launch_bounds__(kBlock) void k_axpy_norm(int64_t n, TY* __restrict_
   if (threadIdx.x == 0) part[lb] = tot;
 }
 
-hipError_t axpy_norm(hipStream_t st, int64_t n, void* w, int tw, const void* v0, const void* vb,
-                     int nv, const double* h, const double* scales, void* partials,
+hipError_t axpy_norm(hipStream_t st, const SysLayout& sl, int64_t n, void* w, int tw, const void* v0,
+                     const void* vb, int nv, const double* h, const double* scales, void* partials,
                      const int* stop) {
   if (nv > kMaxM) return hipErrorInvalidValue;
   const int64_t nb = n_blocks(n);
   return with_type(tw, [&](auto pw) {
     using TY = TYPE_OF(pw);
     using Q = wider_t<TY, TY>;
-    hipLaunchKernelGGL((k_axpy_norm<TY, Q>), grid_for(n), dim3(kBlock), 0, st, n, (TY*)w,
+    hipLaunchKernelGGL((k_axpy_norm<TY, Q>), grid_for(n), dim3(kBlock), 0, st, sl, n, (TY*)w,
                        (const TY*)v0, (const TY*)vb, nv, h, scales, (Q*)partials, nb, stop);
     return hipGetLastError();
   });
@@ -291,6 +307,13 @@ template <class Q> __device__ void back_substitute(double* S, const int* I, cons
   }
 }
 
+// the child state of system sy
+__device__ __forceinline__ ChildInit child_of(ChildInit c, const SysLayout& sl, int sy) {
+  c.S = sys_ptr(c.S, sy, sl.dS);
+  c.I = sys_ptr(c.I, sy, sl.dI);
+  return c;
+}
+
 __device__ void init_child(const ChildInit& c, double scale0, double beta, int stop) {
   c.S[c.scale] = scale0;
   c.S[c.g] = beta;
@@ -305,7 +328,7 @@ __device__ void init_child(const ChildInit& c, double scale0, double beta, int s
 // orthogonalised w (thread 0 only).
 template <class Q>
 __device__ void givens_core(Q s, double* S, int* I, const LevelLayout& L, int j, int solve_y,
-                            double inv_bnorm, double* host_out, const ChildInit& child) {
+                            double inv_bnorm, double* host_out, const ChildInit& child, double tol) {
   const int ld = L.m + 1;
   double* H = S + L.H;
   double* Hraw = S + L.Hraw;
@@ -349,12 +372,15 @@ __device__ void givens_core(Q s, double* S, int* I, const LevelLayout& L, int j,
       S[L.cbeta] = (double)(hn * inv);
     }
   }
-  I[I_STOP] = stop;
-  I[I_CUR] = j + 1;
   if (host_out) {
-    host_out[0] = fabs(g[j + 1]) * inv_bnorm;
+    const double est = fabs(g[j + 1]) * inv_bnorm;
+    // outermost level: a system that reached the tolerance stops its rows
+    if (tol > 0.0 && est < tol) stop = 1;
+    host_out[0] = est;
     host_out[1] = (double)(stop | (I[I_BAD] << 1));
   }
+  I[I_STOP] = stop;
+  I[I_CUR] = j + 1;
   if (child.S) init_child(child, S[L.scale + j + 1], S[L.cbeta], stop);
   if (solve_y || stop) back_substitute<Q>(S, I, L);
 }
@@ -362,37 +388,49 @@ __device__ void givens_core(Q s, double* S, int* I, const LevelLayout& L, int j,
 template <class Q>
 __global__ __launch_bounds__(kFinBlock) void k_givens(const Q* __restrict__ part, int64_t nb,
                                                       double* S, int* I, LevelLayout L, int j,
-                                                      int solve_y, double inv_bnorm,
-                                                      double* host_out, ChildInit child) {
+                                                      int solve_y, const double* inv_bnorm,
+                                                      double* host_out, ChildInit child,
+                                                      SysLayout sl, double tol) {
   __shared__ Q lds[kFinBlock / kWave];
-  Q s = thread_sum(part, nb);
+  const int sy = blockIdx.x;
+  int64_t lo, hi;
+  sys_range(sl, sy, nb, lo, hi);
+  Q s = thread_sum(part + lo, hi - lo);
   s = fin_block_sum(s, lds);
+  S = sys_ptr(S, sy, sl.dS);
+  I = sys_ptr(I, sy, sl.dI);
   if (threadIdx.x != 0 || I[I_STOP]) return;
-  givens_core<Q>(s, S, I, L, j, solve_y, inv_bnorm, host_out, child);
+  const double ibn = inv_bnorm ? inv_bnorm[sy] : 0.0;
+  givens_core<Q>(s, S, I, L, j, solve_y, ibn, host_out ? host_out + 4 * sy : nullptr,
+                 child.S ? child_of(child, sl, sy) : child, tol);
 }
 
-hipError_t givens(hipStream_t st, int q, const void* partials, int64_t nb, double* S, int* I,
-                  const LevelLayout& L, int j, int solve_y, double inv_bnorm, double* host_out,
-                  const ChildInit* child) {
+hipError_t givens(hipStream_t st, const SysLayout& sl, int q, const void* partials, int64_t nb,
+                  double* S, int* I, const LevelLayout& L, int j, int solve_y,
+                  const double* inv_bnorm, double* host_out, const ChildInit* child, double tol) {
   ChildInit c = child ? *child : ChildInit{};
+  const dim3 g((unsigned)sl.nsys);
   if (q == T64)
-    hipLaunchKernelGGL(k_givens<double>, dim3(1), dim3(kFinBlock), 0, st, (const double*)partials,
-                       nb, S, I, L, j, solve_y, inv_bnorm, host_out, c);
+    hipLaunchKernelGGL(k_givens<double>, g, dim3(kFinBlock), 0, st, (const double*)partials, nb, S,
+                       I, L, j, solve_y, inv_bnorm, host_out, c, sl, tol);
   else
-    hipLaunchKernelGGL(k_givens<float>, dim3(1), dim3(kFinBlock), 0, st, (const float*)partials, nb,
-                       S, I, L, j, solve_y, inv_bnorm, host_out, c);
+    hipLaunchKernelGGL(k_givens<float>, g, dim3(kFinBlock), 0, st, (const float*)partials, nb, S, I,
+                       L, j, solve_y, inv_bnorm, host_out, c, sl, tol);
   return hipGetLastError();
 }
 
-template <class Q> __global__ void k_backsolve(double* S, int* I, LevelLayout L) {
-  if (threadIdx.x == 0) back_substitute<Q>(S, I, L);
+template <class Q> __global__ void k_backsolve(double* S, int* I, LevelLayout L, SysLayout sl) {
+  const int sy = blockIdx.x;
+  if (threadIdx.x == 0) back_substitute<Q>(sys_ptr(S, sy, sl.dS), sys_ptr(I, sy, sl.dI), L);
 }
 
-hipError_t backsolve(hipStream_t st, int q, double* S, int* I, const LevelLayout& L) {
+hipError_t backsolve(hipStream_t st, const SysLayout& sl, int q, double* S, int* I,
+                     const LevelLayout& L) {
+  const dim3 g((unsigned)sl.nsys);
   if (q == T64)
-    hipLaunchKernelGGL(k_backsolve<double>, dim3(1), dim3(64), 0, st, S, I, L);
+    hipLaunchKernelGGL(k_backsolve<double>, g, dim3(64), 0, st, S, I, L, sl);
   else
-    hipLaunchKernelGGL(k_backsolve<float>, dim3(1), dim3(64), 0, st, S, I, L);
+    hipLaunchKernelGGL(k_backsolve<float>, g, dim3(64), 0, st, S, I, L, sl);
   return hipGetLastError();
 }
 
@@ -400,15 +438,25 @@ hipError_t backsolve(hipStream_t st, int q, double* S, int* I, const LevelLayout
 // level output: sum_j y_j z_j
 // ---------------------------------------------------------------------------
 template <class TZ, class TV, class Q>
-__global__ __launch_bounds__(kBlock) void k_combine(int64_t n, const TZ* __restrict__ Z,
+__global__ __launch_bounds__(kBlock) void k_combine(SysLayout sl, int64_t n, const TZ* __restrict__ Z,
                                                     const double* y, const int* meffp,
                                                     void* out, const double* s, const int* cur,
                                                     int accumulate, LdLevelBasis<TV, Q> alt,
-                                                    const int* fb, int* out_fb, int64_t nb) {
+                                                    const int* fb, int* out_fb, const int* pstop,
+                                                    int64_t nb) {
   __shared__ Q ys[kMaxM];
   __shared__ int fbs[kMaxM];
   const int64_t lb = logical_block(nb);
   if (lb >= nb) return;
+  const int sy = sys_of(sl, lb * kRowsPerBlock);
+  pstop = sys_ptr(pstop, sy, sl.dI);
+  if (pstop && *pstop) return;
+  y = sys_ptr(y, sy, sl.dS);
+  meffp = sys_ptr(meffp, sy, sl.dI);
+  cur = sys_ptr(cur, sy, sl.dI);
+  fb = sys_ptr(fb, sy, sl.dI);
+  out_fb = sys_ptr(out_fb, sy, sl.dI);
+  alt.scales = sys_ptr(alt.scales, sy, sl.dS);
   const int meff = *meffp;
   for (int t = threadIdx.x; t < meff; t += kBlock) {
     ys[t] = (Q)y[t];
@@ -459,9 +507,10 @@ __global__ __launch_bounds__(kBlock) void k_combine(int64_t n, const TZ* __restr
   }
 }
 
-hipError_t combine(hipStream_t st, int64_t n, const void* Z, int tz, int tv, const double* y,
-                   const int* meff, void* out, const double* s, const int* cur, int accumulate,
-                   const LevelBasis* alt, const int* fb, int* out_fb) {
+hipError_t combine(hipStream_t st, const SysLayout& sl, int64_t n, const void* Z, int tz, int tv,
+                   const double* y, const int* meff, void* out, const double* s, const int* cur,
+                   int accumulate, const LevelBasis* alt, const int* fb, int* out_fb,
+                   const int* pstop) {
   const int64_t nb = n_blocks(n);
   return with_type(tz, [&](auto pz) {
     using TZ = TYPE_OF(pz);
@@ -476,8 +525,9 @@ hipError_t combine(hipStream_t st, int64_t n, const void* Z, int tz, int tv, con
         ld.scales = alt->scales;
         ld.n = n;
       }
-      hipLaunchKernelGGL((k_combine<TZ, TV, Q>), grid_for(n), dim3(kBlock), 0, st, n, (const TZ*)Z,
-                         y, meff, out, s, cur, accumulate, ld, alt ? fb : nullptr, out_fb, nb);
+      hipLaunchKernelGGL((k_combine<TZ, TV, Q>), grid_for(n), dim3(kBlock), 0, st, sl, n,
+                         (const TZ*)Z, y, meff, out, s, cur, accumulate, ld, alt ? fb : nullptr,
+                         out_fb, pstop, nb);
       return hipGetLastError();
     });
   });
@@ -487,13 +537,16 @@ hipError_t combine(hipStream_t st, int64_t n, const void* Z, int tz, int tv, con
 // level entry (cast + norm) and outermost residual
 // ---------------------------------------------------------------------------
 template <class LD, class TO, class Q>
-__global__ __launch_bounds__(kBlock) void k_entry(int64_t n, LD ld, TO* __restrict__ out,
+__global__ __launch_bounds__(kBlock) void k_entry(SysLayout sl, int64_t n, LD ld, TO* __restrict__ out,
                                                   Q* __restrict__ part, int64_t nb,
                                                   const int* pstop) {
-  if (pstop && *pstop) return;
   __shared__ Q lds[kBlock / kWave];
   const int64_t lb = logical_block(nb);
   if (lb >= nb) return;
+  const int sy = sys_of(sl, lb * kRowsPerBlock);
+  pstop = sys_ptr(pstop, sy, sl.dI);
+  if (pstop && *pstop) return;
+  ld.at_sys(sy, sl);
   ld.init();
   Q sq = 0;
 #pragma unroll
@@ -510,8 +563,8 @@ __global__ __launch_bounds__(kBlock) void k_entry(int64_t n, LD ld, TO* __restri
   if (threadIdx.x == 0) part[lb] = s;
 }
 
-hipError_t entry_cast(hipStream_t st, int64_t n, const Basis& in, void* out, int to,
-                      void* partials, const int* parent_stop) {
+hipError_t entry_cast(hipStream_t st, const SysLayout& sl, int64_t n, const Basis& in, void* out,
+                      int to, void* partials, const int* parent_stop) {
   const int64_t nb = n_blocks(n);
   return with_type(to, [&](auto po) -> hipError_t {
     using TO = TYPE_OF(po);
@@ -520,15 +573,15 @@ hipError_t entry_cast(hipStream_t st, int64_t n, const Basis& in, void* out, int
       if (in.type != T64) return hipErrorInvalidValue;
       LdSBasis<TO, double> ld{(const double*)in.raw, in.scale, in.s, in.cur, in.stride, 0.0};
       hipLaunchKernelGGL((k_entry<LdSBasis<TO, double>, TO, Q>), grid_for(n), dim3(kBlock), 0, st,
-                         n, ld, (TO*)out, (Q*)partials, nb, parent_stop);
+                         sl, n, ld, (TO*)out, (Q*)partials, nb, parent_stop);
       return hipGetLastError();
     }
     return with_type(in.type, [&](auto pi) -> hipError_t {
       using TIN = TYPE_OF(pi);
       using QQ = wider_t<TIN, TO>;
       LdBasis<TIN, TO, QQ> ld{(const TIN*)in.raw, in.scale, in.cur, in.stride, 0.0};
-      hipLaunchKernelGGL((k_entry<LdBasis<TIN, TO, QQ>, TO, Q>), grid_for(n), dim3(kBlock), 0, st, n,
-                         ld, (TO*)out, (Q*)partials, nb, parent_stop);
+      hipLaunchKernelGGL((k_entry<LdBasis<TIN, TO, QQ>, TO, Q>), grid_for(n), dim3(kBlock), 0, st,
+                         sl, n, ld, (TO*)out, (Q*)partials, nb, parent_stop);
       return hipGetLastError();
     });
   });
@@ -537,8 +590,14 @@ hipError_t entry_cast(hipStream_t st, int64_t n, const Basis& in, void* out, int
 template <class Q>
 __global__ __launch_bounds__(kFinBlock) void k_entry_fin(const Q* __restrict__ part, int64_t nb,
                                                          ChildInit c, ChildInit child,
-                                                         const int* pstop) {
+                                                         const int* pstop, SysLayout sl) {
   __shared__ Q lds[kFinBlock / kWave];
+  const int sy = blockIdx.x;
+  int64_t lo, hi;
+  sys_range(sl, sy, nb, lo, hi);
+  c = child_of(c, sl, sy);
+  if (child.S) child = child_of(child, sl, sy);
+  pstop = sys_ptr(pstop, sy, sl.dI);
   if (pstop && *pstop) {
     if (threadIdx.x == 0) {
       init_child(c, 0.0, 0.0, 1);
@@ -546,7 +605,7 @@ __global__ __launch_bounds__(kFinBlock) void k_entry_fin(const Q* __restrict__ p
     }
     return;
   }
-  Q s = thread_sum(part, nb);
+  Q s = thread_sum(part + lo, hi - lo);
   s = fin_block_sum(s, lds);
   if (threadIdx.x == 0) {
     const Q beta = sqrt(s);
@@ -558,25 +617,30 @@ __global__ __launch_bounds__(kFinBlock) void k_entry_fin(const Q* __restrict__ p
   }
 }
 
-hipError_t entry_finalize(hipStream_t st, int q, const void* partials, int64_t nb,
-                          const ChildInit& lev, const ChildInit* child, const int* parent_stop) {
+hipError_t entry_finalize(hipStream_t st, const SysLayout& sl, int q, const void* partials,
+                          int64_t nb, const ChildInit& lev, const ChildInit* child,
+                          const int* parent_stop) {
   const ChildInit ch = child ? *child : ChildInit{};
+  const dim3 g((unsigned)sl.nsys);
   if (q == T64)
-    hipLaunchKernelGGL(k_entry_fin<double>, dim3(1), dim3(kFinBlock), 0, st, (const double*)partials,
-                       nb, lev, ch, parent_stop);
+    hipLaunchKernelGGL(k_entry_fin<double>, g, dim3(kFinBlock), 0, st, (const double*)partials, nb,
+                       lev, ch, parent_stop, sl);
   else
-    hipLaunchKernelGGL(k_entry_fin<float>, dim3(1), dim3(kFinBlock), 0, st, (const float*)partials,
-                       nb, lev, ch, parent_stop);
+    hipLaunchKernelGGL(k_entry_fin<float>, g, dim3(kFinBlock), 0, st, (const float*)partials, nb, lev,
+                       ch, parent_stop, sl);
   return hipGetLastError();
 }
 
-__global__ void k_child_init0(double* S, int* I, LevelLayout L, ChildInit child) {
-  if (threadIdx.x == 0) init_child(child, S[L.scale], S[L.g], I[I_STOP]);
+__global__ void k_child_init0(double* S, int* I, LevelLayout L, ChildInit child, SysLayout sl) {
+  const int sy = blockIdx.x;
+  S = sys_ptr(S, sy, sl.dS);
+  I = sys_ptr(I, sy, sl.dI);
+  if (threadIdx.x == 0) init_child(child_of(child, sl, sy), S[L.scale], S[L.g], I[I_STOP]);
 }
 
-hipError_t child_init0(hipStream_t st, double* S, int* I, const LevelLayout& L,
+hipError_t child_init0(hipStream_t st, const SysLayout& sl, double* S, int* I, const LevelLayout& L,
                        const ChildInit& child) {
-  hipLaunchKernelGGL(k_child_init0, dim3(1), dim3(64), 0, st, S, I, L, child);
+  hipLaunchKernelGGL(k_child_init0, dim3((unsigned)sl.nsys), dim3(64), 0, st, S, I, L, child, sl);
   return hipGetLastError();
 }
 
@@ -628,30 +692,39 @@ hipError_t residual64(hipStream_t st, const SellDesc& A, const double* a64, cons
 
 __global__ __launch_bounds__(kFinBlock) void k_residual_fin(const double* __restrict__ part, int64_t nb,
                                                             double* S, int* I, LevelLayout L,
-                                                            double inv_bnorm, double* host_out) {
+                                                            const double* inv_bnorm,
+                                                            double* host_out, SysLayout sl) {
   __shared__ double lds[kFinBlock / kWave];
-  double s = thread_sum(part, nb);
+  const int sy = blockIdx.x;
+  int64_t lo, hi;
+  sys_range(sl, sy, nb, lo, hi);
+  double s = thread_sum(part + lo, hi - lo);
   s = fin_block_sum(s, lds);
+  S = sys_ptr(S, sy, sl.dS);
+  I = sys_ptr(I, sy, sl.dI);
   if (threadIdx.x == 0) {
     const double beta = sqrt(s);
     S[L.scale] = beta > 0 ? 1.0 / beta : 0.0;
     S[L.g] = beta;
     for (int i = 1; i <= L.m; i++) S[L.g + i] = 0.0;
     I[I_MEFF] = 0;
-    I[I_STOP] = beta > 0 ? 0 : 1;
+    // a held system (already finished) keeps every kernel of its rows off
+    I[I_STOP] = beta > 0 && !I[I_HOLD] ? 0 : 1;
     I[I_CUR] = 0;
     I[I_BAD] = isfinite(beta) ? 0 : 1;
     for (int i = 0; i < L.m; i++) I[I_FB + i] = 0;
-    host_out[0] = beta * inv_bnorm;
-    host_out[1] = 0.0;
-    host_out[2] = beta;
+    double* ho = host_out + 4 * sy;
+    ho[0] = beta * inv_bnorm[sy];
+    ho[1] = 0.0;
+    ho[2] = beta;
   }
 }
 
-hipError_t residual_finalize(hipStream_t st, const void* partials, int64_t nb, double* S, int* I,
-                             const LevelLayout& L, double inv_bnorm, double* host_out) {
-  hipLaunchKernelGGL(k_residual_fin, dim3(1), dim3(kFinBlock), 0, st, (const double*)partials, nb, S,
-                     I, L, inv_bnorm, host_out);
+hipError_t residual_finalize(hipStream_t st, const SysLayout& sl, const void* partials, int64_t nb,
+                             double* S, int* I, const LevelLayout& L, const double* inv_bnorm,
+                             double* host_out) {
+  hipLaunchKernelGGL(k_residual_fin, dim3((unsigned)sl.nsys), dim3(kFinBlock), 0, st,
+                     (const double*)partials, nb, S, I, L, inv_bnorm, host_out, sl);
   return hipGetLastError();
 }
 
@@ -672,18 +745,22 @@ __global__ __launch_bounds__(kBlock) void k_dot64(int64_t n, const double* __res
 }
 
 __global__ __launch_bounds__(kFinBlock) void k_sum_to(const double* __restrict__ part, int64_t nb,
-                                                      double* out) {
+                                                      double* out, SysLayout sl) {
   __shared__ double lds[kFinBlock / kWave];
-  double s = thread_sum(part, nb);
+  const int sy = blockIdx.x;
+  int64_t lo, hi;
+  sys_range(sl, sy, nb, lo, hi);
+  double s = thread_sum(part + lo, hi - lo);
   s = fin_block_sum(s, lds);
-  if (threadIdx.x == 0) out[0] = s;
+  if (threadIdx.x == 0) out[4 * sy] = s;
 }
 
-hipError_t dot64_to_host(hipStream_t st, int64_t n, const double* x, const double* y,
-                         void* partials, double* host_out) {
+hipError_t dot64_to_host(hipStream_t st, const SysLayout& sl, int64_t n, const double* x,
+                         const double* y, void* partials, double* host_out) {
   const int64_t nb = n_blocks(n);
   hipLaunchKernelGGL(k_dot64, grid_for(n), dim3(kBlock), 0, st, n, x, y, (double*)partials, nb);
-  hipLaunchKernelGGL(k_sum_to, dim3(1), dim3(kFinBlock), 0, st, (const double*)partials, nb, host_out);
+  hipLaunchKernelGGL(k_sum_to, dim3((unsigned)sl.nsys), dim3(kFinBlock), 0, st, (const double*)partials,
+                     nb, host_out, sl);
   return hipGetLastError();
 }
 
@@ -695,13 +772,16 @@ __global__ __launch_bounds__(kBlock) void k_mw(SellDesc A, const TM* __restrict_
                                                LD ld, TT* __restrict__ t, const int* stop,
                                                int64_t* cntr, int64_t nb) {
   if (cntr && blockIdx.x == 0 && threadIdx.x == 0) *cntr += 1;
-  if (stop && *stop) return;
   const int64_t lb = logical_block(nb);
   if (lb >= nb) return;
+  const int sy = sys_of(A.sys, lb * (kBlock * KR));
+  stop = sys_ptr(stop, sy, A.sys.dI);
+  if (stop && *stop) return;
   const int wave = threadIdx.x / kWave, lane = threadIdx.x & (kWave - 1);
   const int64_t gw = lb * 4 + wave;
   RowSlot s[KR];
   make_slots(A, gw, lane, s);
+  ld.at_sys(sy, A.sys);
   ld.init();
   int lo[KR], hi[KR], kb[KR], ke[KR];
   Q acc[KR];
@@ -729,6 +809,7 @@ __global__ __launch_bounds__(kBlock) void k_mw(SellDesc A, const TM* __restrict_
 template <class TT, class Q> struct EpiStore {
   TT* out;
   int* fb;
+  __device__ __forceinline__ void at_sys(int sy, const SysLayout& sl) { fb = sys_ptr(fb, sy, sl.dI); }
   __device__ __forceinline__ void init() {}
   __device__ __forceinline__ void prefetch(int, int64_t) {}
   __device__ __forceinline__ void operator()(int, int64_t r, TT y) const {
@@ -741,6 +822,10 @@ template <class TT, class Q> struct EpiZ1 {
   const double* wp;
   int* fb;
   Q w;
+  __device__ __forceinline__ void at_sys(int sy, const SysLayout& sl) {
+    wp = sys_ptr(wp, sy, sl.dS);
+    fb = sys_ptr(fb, sy, sl.dI);
+  }
   __device__ __forceinline__ void init() { w = (Q)(*wp); }
   __device__ __forceinline__ void prefetch(int, int64_t) {}
   __device__ __forceinline__ void operator()(int, int64_t r, TT y) const {
@@ -756,6 +841,10 @@ template <class TT, class Q> struct EpiZK {
   int* fb;
   Q w;
   Q zv[4];  // one per row of the lane (at most four)
+  __device__ __forceinline__ void at_sys(int sy, const SysLayout& sl) {
+    wp = sys_ptr(wp, sy, sl.dS);
+    fb = sys_ptr(fb, sy, sl.dI);
+  }
   __device__ __forceinline__ void init() { w = (Q)(*wp); }
   __device__ __forceinline__ void prefetch(int k, int64_t r) { zv[k] = widen<Q>(zp[r]); }
   __device__ __forceinline__ void operator()(int k, int64_t r, TT y) const {
@@ -770,6 +859,10 @@ struct EpiS64 {
   int* fb;
   const int* cur;
   int64_t n;
+  __device__ __forceinline__ void at_sys(int sy, const SysLayout& sl) {
+    fb = sys_ptr(fb, sy, sl.dI);
+    cur = sys_ptr(cur, sy, sl.dI);
+  }
   __device__ __forceinline__ void init() {
     if (cur) {
       out += (int64_t)(*cur) * n;
@@ -788,13 +881,16 @@ template <int KR, int U, class TI, class TM, class TT, class Q, class EPI>
 __global__ __launch_bounds__(kBlock) void k_mg(SellDesc A, const TM* __restrict__ mv, int neg, Q gd,
                                                const TT* __restrict__ t, EPI epi, const int* stop,
                                                int64_t nb) {
-  if (stop && *stop) return;
   const int64_t lb = logical_block(nb);
   if (lb >= nb) return;
+  const int sy = sys_of(A.sys, lb * (kBlock * KR));
+  stop = sys_ptr(stop, sy, A.sys.dI);
+  if (stop && *stop) return;
   const int wave = threadIdx.x / kWave, lane = threadIdx.x & (kWave - 1);
   const int64_t gw = lb * 4 + wave;
   RowSlot s[KR];
   make_slots(A, gw, lane, s);
+  epi.at_sys(sy, A.sys);
   epi.init();
   int lo[KR], hi[KR], kb[KR], ke[KR];
   Q acc[KR];
@@ -923,12 +1019,15 @@ template <int KR, int U, class TI, class TA, class TR, class Q, class LD>
 __global__ __launch_bounds__(kBlock) void k_rres(SellDesc A, const TA* __restrict__ av, LD ld,
                                                  const TR* __restrict__ z, TR* __restrict__ r,
                                                  const int* stop, int64_t nb) {
-  if (stop && *stop) return;
   const int64_t lb = logical_block(nb);
   if (lb >= nb) return;
+  const int sy = sys_of(A.sys, lb * (kBlock * KR));
+  stop = sys_ptr(stop, sy, A.sys.dI);
+  if (stop && *stop) return;
   const int wave = threadIdx.x / kWave, lane = threadIdx.x & (kWave - 1);
   RowSlot s[KR];
   make_slots(A, lb * 4 + wave, lane, s);
+  ld.at_sys(sy, A.sys);
   ld.init();
   int kb[KR], ke[KR], kc[KR];
   Q acc[KR];
@@ -985,13 +1084,16 @@ __global__ __launch_bounds__(kBlock) void k_rtdots(SellDesc A, const TA* __restr
                                                    const TR* __restrict__ y, LD rld,
                                                    Q* __restrict__ part, int64_t nb,
                                                    const int* stop) {
-  if (stop && *stop) return;
   __shared__ Q lds[kBlock / kWave];
   const int64_t lb = logical_block(nb);
   if (lb >= nb) return;
+  const int sy = sys_of(A.sys, lb * kRowsPerBlock);
+  stop = sys_ptr(stop, sy, A.sys.dI);
+  if (stop && *stop) return;
   const int wave = threadIdx.x / kWave, lane = threadIdx.x & (kWave - 1);
   RowSlot s[kR];
   make_slots(A, lb * 4 + wave, lane, s);
+  rld.at_sys(sy, A.sys);
   rld.init();
   int kb[kR], ke[kR], kc[kR];
   Q acc[kR];
@@ -1060,11 +1162,18 @@ hipError_t rich_tdots(hipStream_t st, const SellDesc& A, const void* av, int ta,
 template <class Q>
 __global__ __launch_bounds__(kFinBlock) void k_romega(const Q* __restrict__ part, int64_t nb,
                                                       double* om, double* wcur,
-                                                      const int64_t* cntr, int c, const int* stop) {
+                                                      const int64_t* cntr, int c, const int* stop,
+                                                      SysLayout sl) {
+  const int sy = blockIdx.x;
+  stop = sys_ptr(stop, sy, sl.dI);
   if (stop && *stop) return;
+  om = sys_ptr(om, sy, sl.dS);
+  wcur = sys_ptr(wcur, sy, sl.dS);
+  int64_t lo, hi;
+  sys_range(sl, sy, nb, lo, hi);
   __shared__ Q lds[kFinBlock / kWave];
-  const Q num = fin_block_sum(thread_sum(part, nb), lds);
-  const Q den = fin_block_sum(thread_sum(part + nb, nb), lds);
+  const Q num = fin_block_sum(thread_sum(part + lo, hi - lo), lds);
+  const Q den = fin_block_sum(thread_sum(part + nb + lo, hi - lo), lds);
   if (threadIdx.x == 0) {
     const int64_t l = (*cntr - 1) / c;  // Eq. (5): l = c_ntr / c
     const Q wp = num / den;
@@ -1081,26 +1190,31 @@ __global__ __launch_bounds__(kFinBlock) void k_romega(const Q* __restrict__ part
   }
 }
 
-hipError_t rich_omega(hipStream_t st, int q, const void* partials, int64_t nb, double* omega_k,
-                      double* wcur, const int64_t* cntr, int c, const int* stop) {
+hipError_t rich_omega(hipStream_t st, const SysLayout& sl, int q, const void* partials, int64_t nb,
+                      double* omega_k, double* wcur, const int64_t* cntr, int c, const int* stop) {
   if (c <= 0) return hipErrorInvalidValue;
+  const dim3 g((unsigned)sl.nsys);
   if (q == T64)
-    hipLaunchKernelGGL(k_romega<double>, dim3(1), dim3(kFinBlock), 0, st, (const double*)partials, nb,
-                       omega_k, wcur, cntr, c, stop);
+    hipLaunchKernelGGL(k_romega<double>, g, dim3(kFinBlock), 0, st, (const double*)partials, nb,
+                       omega_k, wcur, cntr, c, stop, sl);
   else
-    hipLaunchKernelGGL(k_romega<float>, dim3(1), dim3(kFinBlock), 0, st, (const float*)partials, nb,
-                       omega_k, wcur, cntr, c, stop);
+    hipLaunchKernelGGL(k_romega<float>, g, dim3(kFinBlock), 0, st, (const float*)partials, nb,
+                       omega_k, wcur, cntr, c, stop, sl);
   return hipGetLastError();
 }
 
 template <class TR, class Q>
-__global__ __launch_bounds__(kBlock) void k_zupd(int64_t n, const TR* __restrict__ zp,
+__global__ __launch_bounds__(kBlock) void k_zupd(SysLayout sl, int64_t n, const TR* __restrict__ zp,
                                                  const TR* __restrict__ y, const double* wcur,
                                                  TR* __restrict__ z, int* fb, const int* stop,
                                                  int64_t nb) {
-  if (stop && *stop) return;
   const int64_t lb = logical_block(nb);
   if (lb >= nb) return;
+  const int sy = sys_of(sl, lb * kRowsPerBlock);
+  stop = sys_ptr(stop, sy, sl.dI);
+  if (stop && *stop) return;
+  wcur = sys_ptr(wcur, sy, sl.dS);
+  fb = sys_ptr(fb, sy, sl.dI);
   const Q w = (Q)(*wcur);
 #pragma unroll
   for (int r = 0; r < kR; r++) {
@@ -1113,13 +1227,13 @@ __global__ __launch_bounds__(kBlock) void k_zupd(int64_t n, const TR* __restrict
   }
 }
 
-hipError_t rich_zupdate(hipStream_t st, int64_t n, const void* zprev, const void* y, int tr,
+hipError_t rich_zupdate(hipStream_t st, const SysLayout& sl, int64_t n, const void* zprev, const void* y, int tr,
                         const double* wcur, void* z, int* fbflag, const int* stop) {
   const int64_t nb = n_blocks(n);
   return with_type(tr, [&](auto pr) {
     using TR = TYPE_OF(pr);
     using Q = wider_t<TR, TR>;
-    hipLaunchKernelGGL((k_zupd<TR, Q>), grid_for(n), dim3(kBlock), 0, st, n, (const TR*)zprev,
+    hipLaunchKernelGGL((k_zupd<TR, Q>), grid_for(n), dim3(kBlock), 0, st, sl, n, (const TR*)zprev,
                        (const TR*)y, wcur, (TR*)z, fbflag, stop, nb);
     return hipGetLastError();
   });
@@ -1161,12 +1275,55 @@ hipError_t fill_nan(hipStream_t st, void* p, int t, int64_t count, int* flag) {
   });
 }
 
-__global__ void k_set(double* p, int m, double v) {
+__global__ void k_set(double* p, int m, double v, SysLayout sl) {
+  p = sys_ptr(p, (int)blockIdx.x, sl.dS);
   if ((int)threadIdx.x < m) p[threadIdx.x] = v;
 }
 
-hipError_t set_omega(hipStream_t st, double* omega, int m, double v) {
-  hipLaunchKernelGGL(k_set, dim3(1), dim3(64), 0, st, omega, m, v);
+hipError_t set_omega(hipStream_t st, const SysLayout& sl, double* omega, int m, double v) {
+  hipLaunchKernelGGL(k_set, dim3((unsigned)sl.nsys), dim3(64), 0, st, omega, m, v, sl);
+  return hipGetLastError();
+}
+
+// holds every system s with mask[s]: I[I_HOLD] = I[I_STOP] = 1 (the host's
+// per-system decision that a system has finished)
+__global__ void k_sys_hold(int* I, const int* mask, SysLayout sl) {
+  const int sy = blockIdx.x * blockDim.x + threadIdx.x;
+  if (sy < sl.nsys && mask[sy]) {
+    int* Is = sys_ptr(I, sy, sl.dI);
+    Is[I_HOLD] = 1;
+    Is[I_STOP] = 1;
+  }
+}
+
+hipError_t sys_hold(hipStream_t st, const SysLayout& sl, int* I, const int* mask) {
+  hipLaunchKernelGGL(k_sys_hold, dim3((unsigned)((sl.nsys + 255) / 256)), dim3(256), 0, st, I, mask, sl);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// stacked systems
+// ---------------------------------------------------------------------------
+__global__ void k_stack(StackIo io, double* cat, int to_cat) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= io.n) return;
+  const int sy = sys_of(io.sl, i);
+  const int64_t local = i - io.row0[sy];
+  const bool own = local < io.nrows[sy];
+  if (to_cat)
+    cat[i] = own ? io.ptrs[sy][local] : 0.0;
+  else if (own)
+    io.ptrs[sy][local] = cat[i];
+}
+
+hipError_t stack_gather(hipStream_t st, const StackIo& io, double* cat) {
+  hipLaunchKernelGGL(k_stack, dim3((unsigned)((io.n + 255) / 256)), dim3(256), 0, st, io, cat, 1);
+  return hipGetLastError();
+}
+
+hipError_t stack_scatter(hipStream_t st, const StackIo& io, const double* cat) {
+  hipLaunchKernelGGL(k_stack, dim3((unsigned)((io.n + 255) / 256)), dim3(256), 0, st, io,
+                     const_cast<double*>(cat), 0);
   return hipGetLastError();
 }
 

@@ -9,6 +9,21 @@
 
 namespace f3r {
 
+// ---- several systems in one descriptor --------------------------------------
+// system of the rows starting at row0 (a block never spans two systems)
+__device__ __forceinline__ int sys_of(const SysLayout& s, int64_t row0) {
+  return s.blk ? s.blk[row0 >> 10] : 0;
+}
+template <class T> __device__ __forceinline__ T* sys_ptr(T* p, int sy, int64_t d) {
+  return p ? p + (int64_t)sy * d : p;
+}
+// partial-sum range [lo, hi) of system sy among nb block partials
+__device__ __forceinline__ void sys_range(const SysLayout& s, int sy, int64_t nb, int64_t& lo,
+                                          int64_t& hi) {
+  lo = s.b0 ? s.b0[sy] : 0;
+  hi = s.b0 ? s.b0[sy + 1] : nb;
+}
+
 template <class T> struct is_dbl : std::is_same<T, double> {};
 template <class A, class B, class C = float> using wider_t =
     typename std::conditional<is_dbl<A>::value || is_dbl<B>::value || is_dbl<C>::value, double, float>::type;
@@ -103,6 +118,7 @@ constexpr int kUnroll = 4;
 // ---------------------------------------------------------------------------
 template <class TT, class Q> struct LdVec {
   const TT* p;
+  __device__ __forceinline__ void at_sys(int, const SysLayout&) {}
   __device__ __forceinline__ void init() {}
   __device__ __forceinline__ Q operator()(int64_t c) const { return widen<Q>(p[c]); }
 };
@@ -118,6 +134,11 @@ template <class TIN, class TT, class Q> struct LdBasis {
   const int* cur;
   int64_t stride;
   double sc;
+  // the scale and basis index of system sy
+  __device__ __forceinline__ void at_sys(int sy, const SysLayout& sl) {
+    scp = sys_ptr(scp, sy, sl.dS);
+    cur = sys_ptr(cur, sy, sl.dI);
+  }
   __device__ __forceinline__ void init() {
     int64_t j = cur ? *cur : 0;
     p += j * stride;
@@ -138,6 +159,10 @@ template <class TT, class Q> struct LdSBasis {
   const int* cur;
   int64_t stride;
   double sc;
+  __device__ __forceinline__ void at_sys(int sy, const SysLayout& sl) {
+    scp = sys_ptr(scp, sy, sl.dS);
+    cur = sys_ptr(cur, sy, sl.dI);
+  }
   __device__ __forceinline__ void init() {
     int64_t j = cur ? *cur : 0;
     p += j * stride;

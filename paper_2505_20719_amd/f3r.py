@@ -18,7 +18,7 @@ LIB_PATH = os.path.join(HERE, "libf3r.so")
 FP64, FP32, FP16, BF16 = 0, 1, 2, 3
 FGMRES, RICHARDSON = 0, 1
 VARIANT_FP16, VARIANT_FP32, VARIANT_FP64, VARIANT_FGMRES64, VARIANT_BF16 = 0, 1, 2, 3, 4
-USE_X0, PERSIST_WEIGHTS, NO_GRAPH = 1, 2, 4
+USE_X0, PERSIST_WEIGHTS, NO_GRAPH, BATCH_LOCKSTEP = 1, 2, 4, 8
 (PROBE_NONE, PROBE_M_LOWER, PROBE_M_UPPER, PROBE_R_RESIDUAL, PROBE_SPMV_L2, PROBE_SPMV_L1,
  PROBE_SPMV_L0) = range(7)
 MAX_LEVELS = 8
@@ -251,12 +251,14 @@ class Solver:
 
 class BatchSolver:
     """f3r_setup_batched / f3r_solve_batched: many independent systems solved
-    by one persistent launch."""
+    by one persistent launch, or in lockstep by the per-kernel path."""
 
-    def __init__(self, matrices, params: Params | None = None):
+    def __init__(self, matrices, params: Params | None = None, lockstep: bool = False):
         """matrices: sequence of (row_ptr, col_idx, val) host arrays."""
         self.L = lib()
         self.params = params if params is not None else params_default()
+        if lockstep:
+            self.params.flags |= BATCH_LOCKSTEP
         self._keep = []
         csrs = (Csr * len(matrices))()
         self.sizes = []

@@ -53,11 +53,13 @@ def kappa(A):
     return np.linalg.cond(A.to_scipy().toarray())
 
 
+@pytest.mark.parametrize("lockstep", [False, True])
 @pytest.mark.parametrize("variant", [0, 4])
-def test_batch_matches_oracle_per_system(variant):
+def test_batch_matches_oracle_per_system(variant, lockstep):
     mats, rhss = small_batch()
-    print(f"[case] batch variant={variant} sizes={[A.n for A in mats]}", flush=True)
-    bs = P().BatchSolver([(A.row_ptr, A.col_idx, A.val) for A in mats], P().params_default(variant))
+    print(f"[case] batch variant={variant} lockstep={lockstep} sizes={[A.n for A in mats]}", flush=True)
+    bs = P().BatchSolver([(A.row_ptr, A.col_idx, A.val) for A in mats], P().params_default(variant),
+                         lockstep=lockstep)
     xs, infos, st = bs.solve([dev(b) for _, b in rhss])
     assert st == 0, [i.status for i in infos]
     ov = O.FP16_F3R if variant == 0 else O.BF16_F3R
@@ -77,12 +79,13 @@ def test_batch_matches_oracle_per_system(variant):
     bs.close()
 
 
-def test_batch_agrees_with_per_kernel_path_and_is_deterministic():
+@pytest.mark.parametrize("lockstep", [False, True])
+def test_batch_agrees_with_per_kernel_path_and_is_deterministic(lockstep):
     mats, rhss = small_batch(count=5, lo=30, hi=64, tag="batchcmp")
     mats.append(W.poisson2d(64))
     rhss.append(W.rhs(mats[-1], "poisson2d_64"))
-    print(f"[case] batch vs per-kernel sizes={[A.n for A in mats]}", flush=True)
-    bs = P().BatchSolver([(A.row_ptr, A.col_idx, A.val) for A in mats])
+    print(f"[case] batch vs per-kernel lockstep={lockstep} sizes={[A.n for A in mats]}", flush=True)
+    bs = P().BatchSolver([(A.row_ptr, A.col_idx, A.val) for A in mats], lockstep=lockstep)
     bt = [dev(b) for _, b in rhss]
     x1, i1, s1 = bs.solve(bt)
     x2, i2, s2 = bs.solve(bt)
@@ -102,10 +105,12 @@ def test_batch_agrees_with_per_kernel_path_and_is_deterministic():
     bs.close()
 
 
-def test_batch_edge_cases():
+@pytest.mark.parametrize("lockstep", [False, True])
+def test_batch_edge_cases(lockstep):
     PP = P()
     mats, rhss = small_batch(count=3, lo=32, hi=40, tag="batchedge")
-    bs = PP.BatchSolver([(A.row_ptr, A.col_idx, A.val) for A in mats])
+    print(f"[case] batch edge cases lockstep={lockstep}", flush=True)
+    bs = PP.BatchSolver([(A.row_ptr, A.col_idx, A.val) for A in mats], lockstep=lockstep)
     # a zero right-hand side gives x = 0 at once; without F3R_USE_X0 the old
     # contents of x never leak into a solution
     bt = [dev(rhss[0][1]), torch.zeros(mats[1].n, dtype=torch.float64, device="cuda"), dev(rhss[2][1])]
@@ -118,18 +123,40 @@ def test_batch_edge_cases():
     # a cap of one outermost iteration: not converged, x is the last iterate
     p = PP.params_default(PP.VARIANT_FP16)
     p.max_outer = 1
-    bs1 = PP.BatchSolver([(A.row_ptr, A.col_idx, A.val) for A in mats], p)
+    bs1 = PP.BatchSolver([(A.row_ptr, A.col_idx, A.val) for A in mats], p, lockstep=lockstep)
     xs1, inf1, st1 = bs1.solve([dev(b) for _, b in rhss])
     assert st1 == PP.NOT_CONVERGED and all(i.status == PP.NOT_CONVERGED and i.outer_iters == 1 for i in inf1)
     for A, (_, b), x, i in zip(mats, rhss, xs1, inf1):
         assert np.isclose(relres(A, b, host(x)), i.relres_true, rtol=1e-6)
-    # parameters outside the batched nest are rejected
-    for bad in (PP.VARIANT_FP32, PP.VARIANT_FP64, PP.VARIANT_FGMRES64):
+    if not lockstep:
+        # parameters outside the persistent kernel's nest are rejected
+        for bad in (PP.VARIANT_FP32, PP.VARIANT_FP64, PP.VARIANT_FGMRES64):
+            with pytest.raises(PP.F3RError):
+                PP.BatchSolver([(A.row_ptr, A.col_idx, A.val) for A in mats], PP.params_default(bad))
+        q = PP.params_default(PP.VARIANT_FP16)
+        q.lev[2].m = 17
         with pytest.raises(PP.F3RError):
-            PP.BatchSolver([(A.row_ptr, A.col_idx, A.val) for A in mats], PP.params_default(bad))
-    q = PP.params_default(PP.VARIANT_FP16)
-    q.lev[2].m = 17
-    with pytest.raises(PP.F3RError):
-        PP.BatchSolver([(A.row_ptr, A.col_idx, A.val) for A in mats], q)
+            PP.BatchSolver([(A.row_ptr, A.col_idx, A.val) for A in mats], q)
     bs.close()
     bs1.close()
+
+
+@pytest.mark.parametrize("variant", [1, 2])
+def test_lockstep_batch_other_nests(variant):
+    # the lockstep mode runs any nest of the per-kernel path: fp32- and
+    # fp64-F3R per system against the oracle
+    mats, rhss = small_batch(count=4, lo=24, hi=40, tag="batchnest")
+    print(f"[case] lockstep batch variant={variant}", flush=True)
+    bs = P().BatchSolver([(A.row_ptr, A.col_idx, A.val) for A in mats], P().params_default(variant),
+                         lockstep=True)
+    xs, infos, st = bs.solve([dev(b) for _, b in rhss])
+    assert st == 0
+    ov = {1: O.FP32_F3R, 2: O.FP64_F3R}[variant]
+    for A, (_, b), x, info in zip(mats, rhss, xs, infos):
+        o = O.Oracle(A.row_ptr, A.col_idx, A.val, O.default_params(ov))
+        xo, io = o.solve(b, 1e-10)
+        o.close()
+        rg = relres(A, b, host(x))
+        assert rg < 1e-10 and abs(info.outer_iters - io.outer_iters) <= 1
+        assert np.linalg.norm(host(x) - xo) / np.linalg.norm(xo) <= kappa(A) * (rg + io.relres_true)
+    bs.close()

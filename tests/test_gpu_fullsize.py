@@ -98,12 +98,13 @@ def test_elasticity_bonds_64_solve():
     assert relres(A, b, host(x)) < 1e-10
 
 
-def test_batch256_solve():
+@pytest.mark.parametrize("lockstep", [False, True])
+def test_batch256_solve(lockstep):
     sizes = W.batch_sizes(256, 32, 256)
     mats = [W.varcoef2d(int(s), tag=f"batch/{i}") for i, s in enumerate(sizes)]
     rhss = [W.rhs(A, f"batch/{i}") for i, A in enumerate(mats)]
-    print(f"[case] batch of 256, {sum(A.n for A in mats)} unknowns", flush=True)
-    bs = P().BatchSolver([(A.row_ptr, A.col_idx, A.val) for A in mats])
+    print(f"[case] batch of 256, {sum(A.n for A in mats)} unknowns, lockstep={lockstep}", flush=True)
+    bs = P().BatchSolver([(A.row_ptr, A.col_idx, A.val) for A in mats], lockstep=lockstep)
     xs, infos, st = bs.solve([dev(b) for _, b in rhss])
     bs.close()
     assert st == 0
