@@ -104,7 +104,10 @@ typedef struct {
                                     candidate shapes at set-up; 1, 2 or 4 =
                                     that many rows per lane.  Results do not
                                     depend on it. */
-  int32_t reserved[5];
+  int32_t entry_chunk;           /* with rows_per_lane != 0: entries per load
+                                    chunk (0 = 8, 4, 4 for 1, 2, 4 rows; 3 is
+                                    allowed with 2 or 4 rows and narrow vectors) */
+  int32_t reserved[4];
 } f3r_params;
 
 typedef struct {

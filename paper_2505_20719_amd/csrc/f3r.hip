@@ -168,6 +168,13 @@ f3r_status check_params(const f3r_params* p) {
   if (p->m_identity != 0) return F3R_ERR_ARG;  // M = I is not provided
   if (p->rows_per_lane != 0 && p->rows_per_lane != 1 && p->rows_per_lane != 2 && p->rows_per_lane != 4)
     return F3R_ERR_ARG;
+  if (p->entry_chunk != 0) {
+    const int code = 10 * p->rows_per_lane + p->entry_chunk;
+    const int plast = p->lev[p->nlev - 1].prec_v;
+    const bool narrow_v = plast == F3R_FP16 || plast == F3R_BF16;
+    if (!(code == 18 || code == 24 || code == 44 || ((code == 23 || code == 43) && narrow_v)))
+      return F3R_ERR_ARG;
+  }
   return F3R_OK;
 }
 
@@ -455,7 +462,7 @@ void enqueue_fgmres(Ctx& c, int d, const Basis& vin, const void* alias_raw, cons
 void autotune(f3r_handle* h) {
   const int fixed = h->p.rows_per_lane;
   if (fixed) {
-    const int code = fixed == 1 ? 18 : fixed == 2 ? 24 : 44;
+    const int code = h->p.entry_chunk ? 10 * fixed + h->p.entry_chunk : fixed == 1 ? 18 : fixed == 2 ? 24 : 44;
     h->kr[0] = h->kr[1] = h->kr[2] = code;
     return;
   }
@@ -648,9 +655,20 @@ struct SysStat {
   bool run = false;    // iterating in the current cycle
 };
 
-void upload_holds(f3r_handle* h, const std::vector<SysStat>& ss) {
-  std::vector<int> m((size_t)h->nsys);
-  for (int s = 0; s < h->nsys; s++) m[(size_t)s] = ss[(size_t)s].hold ? 1 : 0;
+// Marks on the device the systems held since the last call (held[] is the
+// host's copy of what the device already knows).  Nothing is enqueued when
+// no system changed.
+void upload_holds(f3r_handle* h, const std::vector<SysStat>& ss, std::vector<int>& held) {
+  bool changed = false;
+  std::vector<int> m((size_t)h->nsys, 0);
+  for (int s = 0; s < h->nsys; s++) {
+    if (ss[(size_t)s].hold && !held[(size_t)s]) {
+      m[(size_t)s] = 1;
+      held[(size_t)s] = 1;
+      changed = true;
+    }
+  }
+  if (!changed) return;
   // ordered after the stream's earlier work, complete before m goes away
   HIPCHK(hipStreamSynchronize(h->st));
   HIPCHK(hipMemcpy(h->mask, m.data(), m.size() * sizeof(int), hipMemcpyHostToDevice));
@@ -674,6 +692,7 @@ f3r_status outer_solve(f3r_handle* h, const double* b, double* x, double tol, in
   const double t0 = now_ms();
   SolveStats gs;
   std::vector<SysStat> ss((size_t)ns);
+  std::vector<int> held((size_t)ns, 0);  // holds the device knows of
   h->history.assign((size_t)ns, std::vector<double>());
   h->graph_launches = 0;
   h->probe = h->p.probe_kernel;
@@ -713,7 +732,7 @@ f3r_status outer_solve(f3r_handle* h, const double* b, double* x, double tol, in
     }
   }
   HIPCHK(hipMemcpy(h->ibn, ibn.data(), ibn.size() * sizeof(double), hipMemcpyHostToDevice));
-  upload_holds(h, ss);
+  upload_holds(h, ss, held);
   auto any_open = [&]() {
     for (const SysStat& q : ss)
       if (!q.hold) return true;
@@ -732,7 +751,7 @@ f3r_status outer_solve(f3r_handle* h, const double* b, double* x, double tol, in
         q.hold = true;
       }
     }
-    upload_holds(h, ss);
+    upload_holds(h, ss, held);
   }
   while (any_open()) {
     int omax = 0;
@@ -791,7 +810,7 @@ f3r_status outer_solve(f3r_handle* h, const double* b, double* x, double tol, in
       }
       if (!more) break;
     }
-    upload_holds(h, ss);
+    upload_holds(h, ss, held);
     HIPCHK(backsolve(h->st, sl, T64, L0.S, L0.I, L0.L));
     LevelBasis lb;
     lb.v0 = L0.V;
@@ -818,7 +837,7 @@ f3r_status outer_solve(f3r_handle* h, const double* b, double* x, double tol, in
         if (q.outer >= max_outer || it == 0) q.hold = true;  // not converged
       }
     }
-    upload_holds(h, ss);
+    if (any_open()) upload_holds(h, ss, held);
   }
   const double t1 = now_ms();
   probe_collect(h);
@@ -1211,13 +1230,15 @@ f3r_status f3r_debug_apply_m(f3r_handle* h, int32_t prec, const double* r, doubl
     void* t = h->tmp64b;
     double* outb = (double*)h->partials;  // n values fit: partials hold >= 66 n / 256 doubles
     (void)outb;
-    // the sweep shapes of the solve (picked at set-up)
-    hipError_t e = m_apply_w(h->st, h->A, mv, tm, neg, in, t, prec, nullptr, nullptr, h->kr[0]);
+    // the sweep shapes of the solve (picked at set-up); chunks of three exist
+    // for narrow vectors only
+    auto shape = [&](int code) { return code % 10 == 3 && tsz(prec) != 2 ? code + 1 : code; };
+    hipError_t e = m_apply_w(h->st, h->A, mv, tm, neg, in, t, prec, nullptr, nullptr, shape(h->kr[0]));
     if (e == hipErrorInvalidValue) return F3R_ERR_ARG;
     HIPCHK(e);
     // y (type prec) into tmp64 (the input is dead now)
     HIPCHK(m_apply_g(h->st, h->A, mv, tm, neg, gd, t, prec, 0, nullptr, nullptr, h->tmp64, prec,
-                     nullptr, nullptr, nullptr, nullptr, h->kr[1]));
+                     nullptr, nullptr, nullptr, nullptr, shape(h->kr[1])));
     HIPCHK(convert(h->st, n, h->tmp64, prec, y, T64));
     HIPCHK(hipStreamSynchronize(h->st));
     return F3R_OK;

@@ -36,7 +36,8 @@ class Params(C.Structure):
                 ("m_identity", C.c_int32), ("c", C.c_int32), ("alpha", C.c_double),
                 ("omega_init", C.c_double), ("max_outer", C.c_int32), ("flags", C.c_uint32),
                 ("poison_call", C.c_int32), ("probe_kernel", C.c_int32),
-                ("rows_per_lane", C.c_int32), ("reserved", C.c_int32 * 5)]
+                ("rows_per_lane", C.c_int32), ("entry_chunk", C.c_int32),
+                ("reserved", C.c_int32 * 4)]
 
 
 class Csr(C.Structure):

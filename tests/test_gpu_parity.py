@@ -91,11 +91,11 @@ def test_m_apply_bit_exact(name):
     r16 = O.round_to(O.F16, r)
     ref16 = o.apply_m(r16, O.F16, O.F32)
     assert np.array_equal(host(g.debug_apply_m(O.F16, dev(r16))), ref16)
-    for kr in (1, 2, 4):  # every sweep shape the set-up tuner can pick
+    for kr, ch in ((1, 8), (2, 4), (4, 4), (2, 3), (4, 3)):  # every shape the tuner can pick
         prm = P().params_default(0)
-        prm.rows_per_lane = kr
+        prm.rows_per_lane, prm.entry_chunk = kr, ch
         gk = P().Solver(A.row_ptr, A.col_idx, A.val, prm)
-        assert np.array_equal(host(gk.debug_apply_m(O.F16, dev(r16))), ref16), kr
+        assert np.array_equal(host(gk.debug_apply_m(O.F16, dev(r16))), ref16), (kr, ch)
         gk.close()
     r32 = O.round_to(O.F32, r)
     assert np.array_equal(host(g.debug_apply_m(O.F32, dev(r32))), o.apply_m(r32, O.F32, O.F32))
@@ -269,10 +269,10 @@ def test_autotuned_shapes_change_time_not_results():
     A = MATS["poisson3d_30"]()
     xs, b = W.rhs(A, "poisson3d_30")
     ref = None
-    for kr in (0, 1, 2, 4):
+    for kr, ch in ((0, 0), (1, 0), (2, 0), (4, 0), (2, 3), (4, 3)):
         prm = PP.params_default(0)
-        prm.rows_per_lane = kr
-        print(f"[case] poisson3d_30 rows_per_lane={kr}", flush=True)
+        prm.rows_per_lane, prm.entry_chunk = kr, ch
+        print(f"[case] poisson3d_30 rows_per_lane={kr} chunk={ch}", flush=True)
         g = PP.Solver(A.row_ptr, A.col_idx, A.val, prm)
         x, info = g.solve(dev(b))
         assert info.status == 0
@@ -281,6 +281,8 @@ def test_autotuned_shapes_change_time_not_results():
         assert all(c in (3, 4, 8) for c in info.entry_chunk)
         if kr:
             assert shapes == [kr] * 3 and info.tune_ms == 0.0
+            if ch:
+                assert list(info.entry_chunk) == [ch] * 3
         else:
             assert info.tune_ms > 0.0
         if ref is None:
@@ -288,7 +290,8 @@ def test_autotuned_shapes_change_time_not_results():
         else:
             assert torch.equal(x, ref[0]) and np.array_equal(g.history(), ref[1])
         g.close()
-    bad = PP.params_default(0)
-    bad.rows_per_lane = 3
-    with pytest.raises(PP.F3RError):
-        PP.Solver(A.row_ptr, A.col_idx, A.val, bad)
+    for kr, ch in ((3, 0), (1, 3), (2, 8)):
+        bad = PP.params_default(0)
+        bad.rows_per_lane, bad.entry_chunk = kr, ch
+        with pytest.raises(PP.F3RError):
+            PP.Solver(A.row_ptr, A.col_idx, A.val, bad)
