@@ -141,6 +141,9 @@ typedef struct {
   int32_t rows_per_lane[3]; /* shapes in use: W sweep, G sweep, Richardson residual */
   int32_t entry_chunk[3];   /* entries per load chunk of the same three sweeps */
   double tune_ms;        /* set-up time spent timing the candidate shapes */
+  double probe_empty_ms; /* with probe_kernel: average event-bracketed time of an
+                            empty kernel launched right after each probed launch
+                            (the cost an event pair adds to a launch there) */
 } f3r_info;
 
 typedef struct f3r_handle f3r_handle;

@@ -111,6 +111,7 @@ struct f3r_handle {
   std::vector<hipEvent_t> ev;
   size_t ev_used = 0;
   double probe_ms = 0;
+  double probe_empty_ms = 0;
   int64_t probe_n = 0;
   double setup_ms = 0;
   // shapes (10 x rows per lane + entry chunk) of the W sweep, the G sweep
@@ -262,18 +263,27 @@ struct Ctx {
 
 // HIP events around the launches of the probed kernel (direct launches on
 // the solve's stream only)
+// Probe: every launch of the probed kernel sits between two events, and right
+// after it an empty kernel sits between two more, so the cost an event pair
+// adds to a launch in the same queue position is measured alongside (groups
+// of four events: probed start/end, empty start/end).
+void probe_drain(f3r_handle* h) {
+  for (size_t i = 0; i + 3 < h->ev_used; i += 4) {
+    float ms = 0, me = 0;
+    HIPCHK(hipEventElapsedTime(&ms, h->ev[i], h->ev[i + 1]));
+    HIPCHK(hipEventElapsedTime(&me, h->ev[i + 2], h->ev[i + 3]));
+    h->probe_ms += ms;
+    h->probe_empty_ms += me;
+    h->probe_n++;
+  }
+  h->ev_used = 0;
+}
 void probe_begin(Ctx& c, int id) {
   f3r_handle* h = c.h;
   if (h->probe != id || c.st != h->st) return;
-  if (h->ev_used + 2 > h->ev.size()) {
+  if (h->ev_used + 4 > h->ev.size()) {
     HIPCHK(hipStreamSynchronize(h->st));
-    for (size_t i = 0; i + 1 < h->ev_used; i += 2) {
-      float ms = 0;
-      HIPCHK(hipEventElapsedTime(&ms, h->ev[i], h->ev[i + 1]));
-      h->probe_ms += ms;
-      h->probe_n++;
-    }
-    h->ev_used = 0;
+    probe_drain(h);
     while (h->ev.size() < 512) {
       hipEvent_t e;
       HIPCHK(hipEventCreate(&e));
@@ -286,18 +296,15 @@ void probe_end(Ctx& c, int id) {
   f3r_handle* h = c.h;
   if (h->probe != id || c.st != h->st) return;
   HIPCHK(hipEventRecord(h->ev[h->ev_used + 1], h->st));
-  h->ev_used += 2;
+  HIPCHK(hipEventRecord(h->ev[h->ev_used + 2], h->st));
+  HIPCHK(empty_launch(h->st));
+  HIPCHK(hipEventRecord(h->ev[h->ev_used + 3], h->st));
+  h->ev_used += 4;
 }
 void probe_collect(f3r_handle* h) {
   if (!h->probe || h->ev_used == 0) return;
   HIPCHK(hipStreamSynchronize(h->st));
-  for (size_t i = 0; i + 1 < h->ev_used; i += 2) {
-    float ms = 0;
-    HIPCHK(hipEventElapsedTime(&ms, h->ev[i], h->ev[i + 1]));
-    h->probe_ms += ms;
-    h->probe_n++;
-  }
-  h->ev_used = 0;
+  probe_drain(h);
 }
 
 struct OutSpec {
@@ -699,6 +706,7 @@ f3r_status outer_solve(f3r_handle* h, const double* b, double* x, double tol, in
   h->probe_ms = 0;
   h->probe_n = 0;
   h->ev_used = 0;
+  h->probe_empty_ms = 0;
   if (h->probe) use_graph = false;
   const int64_t per_f2 = baseline ? 0 : r_calls_per_f2(h->p);
   int64_t m_per_outer = 1;
@@ -887,6 +895,7 @@ f3r_status outer_solve(f3r_handle* h, const double* b, double* x, double tol, in
       info->idx_bits = h->A.idx16 ? 16 : 32;
       info->sell_c = 64;
       info->probe_ms = h->probe_ms;
+      info->probe_empty_ms = h->probe_n ? h->probe_empty_ms / (double)h->probe_n : 0.0;
       info->probe_launches = h->probe_n;
       info->padded_nnz = h->padded;
       for (int f = 0; f < 3; f++) {

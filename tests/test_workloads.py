@@ -68,6 +68,28 @@ def test_table2_sizes_follow_the_27_point_closed_form():
         assert (3 * nx - 2) * (3 * ny - 2) * (3 * nz - 2) == int(nnz)
     A = W.hpcg(4, 8, 2)  # small instance of the same generator
     assert A.nnz == (3 * 4 - 2) * (3 * 8 - 2) * (3 * 2 - 2)
+    B = W.hpgmp(4, 8, 2)
+    assert B.nnz == A.nnz and np.array_equal(B.col_idx, A.col_idx)
+
+
+def test_hpgmp_changes_only_the_z_couplings():
+    # Sec. 5: the HPCG operator with the forward/backward z couplings set to
+    # -1 + beta and -1 - beta (beta = 0.5)
+    nx, ny, nz = 4, 3, 5
+    A, B = W.hpcg(nx, ny, nz).to_scipy().toarray(), W.hpgmp(nx, ny, nz).to_scipy().toarray()
+    D = B - A
+    plane = nx * ny
+    rows, cols = np.nonzero(D)
+    assert np.all(np.abs(cols - rows) == plane)
+    assert np.allclose(D[rows, cols], np.where(cols > rows, 0.5, -0.5))
+    assert len(rows) == 2 * plane * (nz - 1)
+    assert not np.allclose(B, B.T)
+
+
+def test_paper_rhs_is_uniform_on_unit_interval():
+    A = W.poisson2d(16)
+    b = W.paper_rhs(A, "t")
+    assert b.shape == (A.n,) and b.min() >= 0.0 and b.max() < 1.0
 
 
 def test_elasticity_is_spd_small():

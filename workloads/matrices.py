@@ -102,6 +102,30 @@ def hpcg(nx: int, ny: int, nz: int) -> CSR:
     return _stencil_csr((nz, ny, nx), offs, coef, f"hpcg_{nx}_{ny}_{nz}")
 
 
+def hpgmp(nx: int, ny: int, nz: int, beta: float = 0.5) -> CSR:
+    """HPGMP-like operator (Sec. 5): the HPCG 27-point operator with the
+    couplings to the forward and backward neighbours along z replaced by
+    -1 + beta and -1 - beta (nonsymmetric; beta = 0.5 as in the paper's
+    runs).  nnz = (3nx-2)(3ny-2)(3nz-2)."""
+    offs = list(itertools.product((-1, 0, 1), repeat=3))
+
+    def coef(o):
+        if o == (0, 0, 0):
+            return 26.0
+        if o == (1, 0, 0):
+            return -1.0 + beta
+        if o == (-1, 0, 0):
+            return -1.0 - beta
+        return -1.0
+
+    return _stencil_csr((nz, ny, nx), offs, [coef(o) for o in offs], f"hpgmp_{nx}_{ny}_{nz}")
+
+
+def paper_rhs(A: CSR, tag: str) -> np.ndarray:
+    """Right-hand side of the paper's runs (Sec. 5): uniform on [0, 1)."""
+    return rng.uniform01(rng.substream(f"rhs-paper/{tag}"), A.n)
+
+
 # ---------------------------------------------------------------------------
 # cfg3: Q1 convection-diffusion, lognormal diffusion, Peclet 50
 # ---------------------------------------------------------------------------
@@ -279,7 +303,10 @@ def build(name: str, scale: int | None = None) -> CSR:
         return convdiff_q1(scale or 100)
     if name.startswith("elasticity"):
         return elasticity_bonds(scale or 64)
-    if name.startswith("hpcg"):
-        s = scale or 16
-        return hpcg(s, s, s)
+    if name.startswith("hpcg") or name.startswith("hpgmp"):
+        gen = hpcg if name.startswith("hpcg") else hpgmp
+        if scale:
+            return gen(scale, scale, scale)
+        x, y, z = (1 << int(t) for t in name.split("_")[1:4])
+        return gen(x, y, z)
     raise KeyError(name)
