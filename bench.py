@@ -351,15 +351,10 @@ def main():
         ov = P.params_default(P.VARIANT_FP16)
         ov.probe_kernel = pid
         _, ip = s16.solve(bt, tol=tol, override=ov)
-        ev_ms = ip.probe_ms / max(ip.probe_launches, 1)
-        # the event pair around each launch adds the time it takes around an
-        # empty kernel on the same stream, measured in the same solve
-        avg_ms = max(ev_ms - ip.probe_empty_ms, 1e-6)
-        kern[key] = {"total_ms": ip.probe_ms, "launches": ip.probe_launches, "event_avg_us": ev_ms * 1e3,
-                     "empty_kernel_us": ip.probe_empty_ms * 1e3, "avg_us": avg_ms * 1e3,
+        avg_ms = ip.probe_ms / max(ip.probe_launches, 1)
+        kern[key] = {"total_ms": ip.probe_ms, "launches": ip.probe_launches, "avg_us": avg_ms * 1e3,
                      "gbs": ab[key] / (avg_ms * 1e-3) / 1e9}
-        log(f"[bench] probe {key}: {ip.probe_launches} launches, event avg {ev_ms * 1e3:.2f} us, "
-            f"empty kernel {ip.probe_empty_ms * 1e3:.2f} us -> {avg_ms * 1e3:.2f} us, "
+        log(f"[bench] probe {key}: {ip.probe_launches} launches, avg {avg_ms * 1e3:.2f} us, "
             f"{kern[key]['gbs']:.0f} GB/s (algorithmic {ab[key] / 1e6:.1f} MB/launch)")
     dom = max(kern, key=lambda k: kern[k]["launches"] * kern[k]["avg_us"])
     achieved = kern[dom]["gbs"]

@@ -96,9 +96,11 @@ typedef struct {
   int32_t max_outer;             /* outermost iterations allowed in total */
   uint32_t flags;                /* F3R_USE_X0 | F3R_PERSIST_WEIGHTS | ... */
   int32_t poison_call;           /* >0: test hook, NaN in that R call's output */
-  int32_t probe_kernel;          /* F3R_PROBE_*: time every launch of that kernel
-                                    with HIP events on the solve's stream; the
-                                    solve then launches without hipGraphs */
+  int32_t probe_kernel;          /* F3R_PROBE_*: time that kernel with HIP events
+                                    on the solve's stream (each call repeated 4
+                                    times between one event pair; the kernel
+                                    rewrites the same output); the solve then
+                                    launches without hipGraphs */
   int32_t rows_per_lane;         /* shape of the M sweeps and of the Richardson
                                     residual: 0 = picked by timing the
                                     candidate shapes at set-up; 1, 2 or 4 =
@@ -136,14 +138,12 @@ typedef struct {
   int32_t idx_bits;      /* 16 or 32: column index width of the device format */
   int32_t sell_c;        /* rows per slice of the device format */
   double probe_ms;       /* summed duration of the probed kernel's launches */
-  int64_t probe_launches; /* launches of the probed kernel */
+  int64_t probe_launches; /* launches of the probed kernel (each probed call is
+                             made 4 times in a row between one event pair) */
   int64_t padded_nnz;    /* stored entries of the device format incl. padding */
   int32_t rows_per_lane[3]; /* shapes in use: W sweep, G sweep, Richardson residual */
   int32_t entry_chunk[3];   /* entries per load chunk of the same three sweeps */
   double tune_ms;        /* set-up time spent timing the candidate shapes */
-  double probe_empty_ms; /* with probe_kernel: average event-bracketed time of an
-                            empty kernel launched right after each probed launch
-                            (the cost an event pair adds to a launch there) */
 } f3r_info;
 
 typedef struct f3r_handle f3r_handle;

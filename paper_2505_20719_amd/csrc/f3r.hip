@@ -111,7 +111,6 @@ struct f3r_handle {
   std::vector<hipEvent_t> ev;
   size_t ev_used = 0;
   double probe_ms = 0;
-  double probe_empty_ms = 0;
   int64_t probe_n = 0;
   double setup_ms = 0;
   // shapes (10 x rows per lane + entry chunk) of the W sweep, the G sweep
@@ -263,25 +262,26 @@ struct Ctx {
 
 // HIP events around the launches of the probed kernel (direct launches on
 // the solve's stream only)
-// Probe: every launch of the probed kernel sits between two events, and right
-// after it an empty kernel sits between two more, so the cost an event pair
-// adds to a launch in the same queue position is measured alongside (groups
-// of four events: probed start/end, empty start/end).
+// Probe: each launch of the probed kernel is made kProbeReps times in a row
+// (every probed kernel rewrites the same output from the same inputs) between
+// one pair of events, so the cost of the event pair is spread over the
+// repeats; probe_ms / probe_launches is the time of one launch.
+constexpr int kProbeReps = 4;
+
 void probe_drain(f3r_handle* h) {
-  for (size_t i = 0; i + 3 < h->ev_used; i += 4) {
-    float ms = 0, me = 0;
+  for (size_t i = 0; i + 1 < h->ev_used; i += 2) {
+    float ms = 0;
     HIPCHK(hipEventElapsedTime(&ms, h->ev[i], h->ev[i + 1]));
-    HIPCHK(hipEventElapsedTime(&me, h->ev[i + 2], h->ev[i + 3]));
     h->probe_ms += ms;
-    h->probe_empty_ms += me;
-    h->probe_n++;
+    h->probe_n += kProbeReps;
   }
   h->ev_used = 0;
 }
-void probe_begin(Ctx& c, int id) {
+// returns how many times the caller makes the launch
+int probe_begin(Ctx& c, int id) {
   f3r_handle* h = c.h;
-  if (h->probe != id || c.st != h->st) return;
-  if (h->ev_used + 4 > h->ev.size()) {
+  if (h->probe != id || c.st != h->st) return 1;
+  if (h->ev_used + 2 > h->ev.size()) {
     HIPCHK(hipStreamSynchronize(h->st));
     probe_drain(h);
     while (h->ev.size() < 512) {
@@ -291,15 +291,13 @@ void probe_begin(Ctx& c, int id) {
     }
   }
   HIPCHK(hipEventRecord(h->ev[h->ev_used], h->st));
+  return kProbeReps;
 }
 void probe_end(Ctx& c, int id) {
   f3r_handle* h = c.h;
   if (h->probe != id || c.st != h->st) return;
   HIPCHK(hipEventRecord(h->ev[h->ev_used + 1], h->st));
-  HIPCHK(hipEventRecord(h->ev[h->ev_used + 2], h->st));
-  HIPCHK(empty_launch(h->st));
-  HIPCHK(hipEventRecord(h->ev[h->ev_used + 3], h->st));
-  h->ev_used += 4;
+  h->ev_used += 2;
 }
 void probe_collect(f3r_handle* h) {
   if (!h->probe || h->ev_used == 0) return;
@@ -350,20 +348,23 @@ void enqueue_rich(Ctx& c, int d, const Basis& vin, const int* stop, void* out, i
     if (k == 0) {
       rsrc = vin;
     } else {
-      probe_begin(c, F3R_PROBE_R_RESIDUAL);
-      HIPCHK(rich_residual(c.st, h->A, av, R.pa, vin, zprev, R.rr, tr, stop, h->kr[2]));
+      const int nr = probe_begin(c, F3R_PROBE_R_RESIDUAL);
+      for (int r = 0; r < nr; r++)
+        HIPCHK(rich_residual(c.st, h->A, av, R.pa, vin, zprev, R.rr, tr, stop, h->kr[2]));
       probe_end(c, F3R_PROBE_R_RESIDUAL);
       rsrc.raw = R.rr;
       rsrc.type = tr;
     }
-    probe_begin(c, F3R_PROBE_M_LOWER);
-    HIPCHK(m_apply_w(c.st, h->A, mv, tm, neg, rsrc, R.rt, tr, stop, k == 0 ? R.cntr_dev : nullptr,
-                     h->kr[0]));
+    const int nw = probe_begin(c, F3R_PROBE_M_LOWER);
+    for (int r = 0; r < nw; r++)  // the call counter advances once
+      HIPCHK(m_apply_w(c.st, h->A, mv, tm, neg, rsrc, R.rt, tr, stop,
+                       k == 0 && r == 0 ? R.cntr_dev : nullptr, h->kr[0]));
     probe_end(c, F3R_PROBE_M_LOWER);
     if (!upd) {
-      probe_begin(c, F3R_PROBE_M_UPPER);
-      HIPCHK(m_apply_g(c.st, h->A, mv, tm, neg, gd, R.rt, tr, k == 0 ? 1 : 2, R.omega + k, zprev, zk,
-                       tr, nullptr, zfb, stop, nullptr, h->kr[1]));
+      const int ng = probe_begin(c, F3R_PROBE_M_UPPER);
+      for (int r = 0; r < ng; r++)
+        HIPCHK(m_apply_g(c.st, h->A, mv, tm, neg, gd, R.rt, tr, k == 0 ? 1 : 2, R.omega + k, zprev, zk,
+                         tr, nullptr, zfb, stop, nullptr, h->kr[1]));
       probe_end(c, F3R_PROBE_M_UPPER);
     } else {
       HIPCHK(m_apply_g(c.st, h->A, mv, tm, neg, gd, R.rt, tr, 0, nullptr, nullptr, R.ry, tr, nullptr,
@@ -443,9 +444,10 @@ void enqueue_fgmres(Ctx& c, int d, const Basis& vin, const void* alias_raw, cons
     }
     const int pid = d == 1 ? F3R_PROBE_SPMV_L1 : d == 2 ? F3R_PROBE_SPMV_L2 : -1;
     double* hcol = L.S + L.L.H + (int64_t)j * (m + 1);
-    probe_begin(c, pid);
-    HIPCHK(spmv_dots(c.st, h->A, h->ah[L.pa], L.pa, zj, L.zt, &bj, fbj, vec_at(L.V, L.pv, j + 1, n),
-                     L.pv, v0, vb, j + 1, h->partials, stop));
+    const int ns_ = probe_begin(c, pid);
+    for (int r = 0; r < ns_; r++)
+      HIPCHK(spmv_dots(c.st, h->A, h->ah[L.pa], L.pa, zj, L.zt, &bj, fbj, vec_at(L.V, L.pv, j + 1, n),
+                       L.pv, v0, vb, j + 1, h->partials, stop));
     probe_end(c, pid);
     HIPCHK(finalize_sums(c.st, h->A.sys, L.q, h->partials, nb, j + 1, L.S + L.L.scale, hcol, stop));
     HIPCHK(axpy_norm(c.st, h->A.sys, n, vec_at(L.V, L.pv, j + 1, n), L.pv, v0, vb, j + 1, hcol,
@@ -706,7 +708,6 @@ f3r_status outer_solve(f3r_handle* h, const double* b, double* x, double tol, in
   h->probe_ms = 0;
   h->probe_n = 0;
   h->ev_used = 0;
-  h->probe_empty_ms = 0;
   if (h->probe) use_graph = false;
   const int64_t per_f2 = baseline ? 0 : r_calls_per_f2(h->p);
   int64_t m_per_outer = 1;
@@ -781,10 +782,11 @@ f3r_status outer_solve(f3r_handle* h, const double* b, double* x, double tol, in
       bj.type = T64;
       bj.scale = L0.S + L0.L.scale + j;
       Ctx c0{h, h->st, nullptr};
-      probe_begin(c0, F3R_PROBE_SPMV_L0);
-      HIPCHK(spmv_dots(h->st, h->A, h->a64, T64, zj, T64, &bj, L0.I + I_FB + j,
-                       vec_at(L0.V, T64, j + 1, n), T64, L0.V, vec_at(L0.V, T64, 1, n), j + 1,
-                       h->partials, L0.I + I_STOP));
+      const int n0 = probe_begin(c0, F3R_PROBE_SPMV_L0);
+      for (int r = 0; r < n0; r++)
+        HIPCHK(spmv_dots(h->st, h->A, h->a64, T64, zj, T64, &bj, L0.I + I_FB + j,
+                         vec_at(L0.V, T64, j + 1, n), T64, L0.V, vec_at(L0.V, T64, 1, n), j + 1,
+                         h->partials, L0.I + I_STOP));
       probe_end(c0, F3R_PROBE_SPMV_L0);
       double* hcol = L0.S + L0.L.H + (int64_t)j * (L0.cfg.m + 1);
       HIPCHK(finalize_sums(h->st, sl, T64, h->partials, nb, j + 1, L0.S + L0.L.scale, hcol,
@@ -895,7 +897,6 @@ f3r_status outer_solve(f3r_handle* h, const double* b, double* x, double tol, in
       info->idx_bits = h->A.idx16 ? 16 : 32;
       info->sell_c = 64;
       info->probe_ms = h->probe_ms;
-      info->probe_empty_ms = h->probe_n ? h->probe_empty_ms / (double)h->probe_n : 0.0;
       info->probe_launches = h->probe_n;
       info->padded_nnz = h->padded;
       for (int f = 0; f < 3; f++) {

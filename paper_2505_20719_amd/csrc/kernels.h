@@ -238,8 +238,6 @@ hipError_t stack_scatter(hipStream_t st, const StackIo& io, const double* cat);
 hipError_t convert(hipStream_t st, int64_t n, const void* in, int ti, void* out, int to);
 hipError_t fill_nan(hipStream_t st, void* p, int t, int64_t count, int* flag);
 hipError_t set_omega(hipStream_t st, const SysLayout& sl, double* omega, int m, double v);
-// one launch of an empty kernel (reference for event-pair timing)
-hipError_t empty_launch(hipStream_t st);
 // I[I_HOLD] = I[I_STOP] = 1 for the systems s with mask[s] != 0 (mask:
 // device, nsys ints; I: the outermost level's flags)
 hipError_t sys_hold(hipStream_t st, const SysLayout& sl, int* I, const int* mask);

@@ -1327,13 +1327,4 @@ hipError_t stack_scatter(hipStream_t st, const StackIo& io, const double* cat) {
   return hipGetLastError();
 }
 
-// an empty kernel: the reference for the cost of timing one launch with a
-// pair of events
-__global__ void k_empty() {}
-
-hipError_t empty_launch(hipStream_t st) {
-  hipLaunchKernelGGL(k_empty, dim3(1), dim3(64), 0, st);
-  return hipGetLastError();
-}
-
 }  // namespace f3r

@@ -53,8 +53,7 @@ class Info(C.Structure):
                 ("relres_true", C.c_double), ("setup_ms", C.c_double), ("solve_ms", C.c_double),
                 ("graph_launches", C.c_int64), ("idx_bits", C.c_int32), ("sell_c", C.c_int32),
                 ("probe_ms", C.c_double), ("probe_launches", C.c_int64), ("padded_nnz", C.c_int64),
-                ("rows_per_lane", C.c_int32 * 3), ("entry_chunk", C.c_int32 * 3), ("tune_ms", C.c_double),
-                ("probe_empty_ms", C.c_double)]
+                ("rows_per_lane", C.c_int32 * 3), ("entry_chunk", C.c_int32 * 3), ("tune_ms", C.c_double)]
 
     def as_dict(self):
         arrays = ("spmv", "rows_per_lane", "entry_chunk")

@@ -295,3 +295,22 @@ def test_autotuned_shapes_change_time_not_results():
         bad.rows_per_lane, bad.entry_chunk = kr, ch
         with pytest.raises(PP.F3RError):
             PP.Solver(A.row_ptr, A.col_idx, A.val, bad)
+
+
+def test_kernel_probe_leaves_the_solve_unchanged():
+    # the probe repeats the probed launch between one pair of events; every
+    # probed kernel rewrites the same output, so the solve is bitwise the same
+    PP = P()
+    A = MATS["poisson3d_30"]()
+    xs, b = W.rhs(A, "poisson3d_30")
+    g = PP.Solver(A.row_ptr, A.col_idx, A.val)
+    x0, i0 = g.solve(dev(b))
+    for pid in (PP.PROBE_M_LOWER, PP.PROBE_M_UPPER, PP.PROBE_R_RESIDUAL, PP.PROBE_SPMV_L2,
+                PP.PROBE_SPMV_L1, PP.PROBE_SPMV_L0):
+        print(f"[case] probe {pid}", flush=True)
+        ov = PP.params_default(0)
+        ov.probe_kernel = pid
+        x1, i1 = g.solve(dev(b), override=ov)
+        assert torch.equal(x0, x1) and i1.outer_iters == i0.outer_iters
+        assert i1.probe_launches > 0 and i1.probe_launches % 4 == 0 and i1.probe_ms > 0
+    g.close()
