@@ -340,6 +340,21 @@ def main():
             s.close()
         if "fp64" in extra:
             result_cfg["speedup_fp16_vs_fp64_f3r"] = round(result_cfg["f3r_fp64_s"] / mean_s, 3)
+        # the other comparison solvers: CG (symmetric matrices) and BiCGStab,
+        # fp64, with the same S M (S v) preconditioner, M in fp64
+        Asp = A.to_scipy()
+        methods = [("bicgstab", P.BICGSTAB)]
+        if abs(Asp - Asp.T).max() == 0.0:
+            methods.insert(0, ("cg", P.CG))
+        for key, method in methods:
+            (xk, ik), tk, totk = timed_solves(
+                lambda: s16.krylov_solve(bt, method, P.FP64, tol=tol, max_iter=20000), reps, 1)
+            assert ik.status == 0, ik.as_dict()
+            result_cfg[f"{key}_s"] = round(totk / reps, 6)
+            result_cfg[f"{key}_iters"] = ik.outer_iters
+            result_cfg[f"{key}_err_vs_xstar"] = err_of(xk.cpu().numpy())
+            result_cfg[f"speedup_vs_{key}"] = round(totk / reps / mean_s, 3)
+            log(f"[bench] fp64 {key}: {totk / reps * 1e3:.2f} ms/solve, iters={ik.outer_iters}")
 
     # live per-kernel timing of the hot kernels inside one solve (HIP events
     # on the solve's stream, direct launches)

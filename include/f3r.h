@@ -182,6 +182,20 @@ f3r_status f3r_fgmres_solve(f3r_handle* h, const double* b, double* x,
                             double tol, int32_t m, int32_t max_iter,
                             f3r_info* info);
 
+/* The other comparison solvers of Sec. 5: preconditioned CG (method F3R_CG,
+   for symmetric positive definite A) or right-preconditioned BiCGStab
+   (F3R_BICGSTAB), every vector and operation in fp64, preconditioned by
+   S M (S v) with M's factors stored in prec_m (F3R_FP64, or a precision the
+   handle holds: its prec_m, and any level precision when alpha = 1).
+   Convergence is tested on the recursive residual and confirmed with the
+   fp64 true residual (the iteration continues from it otherwise); max_iter
+   bounds the iterations.  info->outer_iters counts iterations, m_calls the
+   applications of M.  Same conventions as f3r_solve. */
+#define F3R_CG 0
+#define F3R_BICGSTAB 1
+f3r_status f3r_krylov_solve(f3r_handle* h, int32_t method, int32_t prec_m, const double* b,
+                            double* x, double tol, int32_t max_iter, f3r_info* info);
+
 /* Relative residual estimate after every outermost iteration of the last
    solve (level 0 only).  Copies min(cap, available) values to buf (host),
    *len = available.  Errors: F3R_ERR_ARG. */

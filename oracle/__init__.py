@@ -18,6 +18,7 @@ LIB_PATH = os.path.join(HERE, "liboracle.so")
 F64, F32, F16, BF16 = 0, 1, 2, 3
 FGMRES, RICH = 0, 1
 OK, NOT_CONVERGED = 0, 1
+CG, BICGSTAB = 0, 1  # comparison solvers of Sec. 5
 ERR_ARG, ERR_MATRIX, ERR_RANGE, ERR_NOMEM, ERR_BREAKDOWN = -1, -2, -3, -4, -6
 MAX_LEV = 8
 
@@ -85,6 +86,8 @@ def lib():
         "or_destroy": (None, [H]),
         "or_solve": (C.c_int32, [H, _dp, _dp, C.c_double, C.POINTER(Info)]),
         "or_fgmres_solve": (C.c_int32, [H, _dp, _dp, C.c_double, C.c_int32,
+                                        C.c_int32, C.POINTER(Info)]),
+        "or_krylov_solve": (C.c_int32, [H, C.c_int32, C.c_int32, _dp, _dp, C.c_double,
                                         C.c_int32, C.POINTER(Info)]),
         "or_n": (C.c_int64, [H]),
         "or_get_scaling": (None, [H, _dp]),
@@ -206,6 +209,15 @@ class Oracle:
         x = np.zeros(self.n)
         info = Info()
         self.L.or_fgmres_solve(self.h, b, x, tol, m, max_iter, C.byref(info))
+        return x, info
+
+    def krylov_solve(self, b, method=CG, m64=True, tol=1e-10, max_iter=10000, x0=None):
+        """Preconditioned CG (method CG) or BiCGStab (BICGSTAB), fp64, with
+        S M (S v) as preconditioner; M's factors in fp64 or in pM."""
+        b = np.ascontiguousarray(b, dtype=np.float64)
+        x = np.zeros(self.n) if x0 is None else np.array(x0, dtype=np.float64)
+        info = Info()
+        self.L.or_krylov_solve(self.h, method, int(bool(m64)), b, x, tol, max_iter, C.byref(info))
         return x, info
 
     def scaling(self):

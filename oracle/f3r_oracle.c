@@ -855,6 +855,141 @@ int32_t or_fgmres_solve(or_handle* h, const double* b, double* x, double tol,
 }
 
 /* ------------------------------------------------------------------------ */
+/* comparison solvers of Sec. 5: preconditioned CG (symmetric matrices) and  */
+/* BiCGStab (nonsymmetric), every value fp64, with the preconditioner        */
+/* P(v) = S M (S v) -- the diagonal scaling of Sec. 5 around the primary     */
+/* preconditioner, whose factors are stored in the handle's pM (or fp64).    */
+/* ------------------------------------------------------------------------ */
+
+static void hist_push(or_handle* h, double v) {
+  if (h->hist_len == h->hist_cap) {
+    double* nh = realloc(h->hist, (size_t)(2 * h->hist_cap) * sizeof(double));
+    if (nh) {
+      h->hist = nh;
+      h->hist_cap *= 2;
+    }
+  }
+  if (h->hist_len < h->hist_cap) h->hist[h->hist_len++] = v;
+}
+
+/* z = S M (S r), fp64 arithmetic, M factors in fp64 (m64) or in pM */
+static void apply_p64(or_handle* h, int m64, const double* r, double* z, double* tmp) {
+  for (int64_t i = 0; i < h->n; i++) tmp[i] = h->s[i] * r[i];
+  apply_m_impl(h, OR_F64, OR_F64, m64, tmp, z);
+  for (int64_t i = 0; i < h->n; i++) z[i] = h->s[i] * z[i];
+}
+
+static double relres_of(or_handle* h, const double* b, const double* x, double* r, double bn) {
+  csr_mv(h->n, h->rp, h->ci, h->a, OR_F64, OR_F64, x, r);
+  for (int64_t i = 0; i < h->n; i++) r[i] = b[i] - r[i];
+  return nrm2(OR_F64, h->n, r) / bn;
+}
+
+int32_t or_krylov_solve(or_handle* h, int32_t method, int32_t m64, const double* b, double* x,
+                        double tol, int32_t max_iter, or_info* info) {
+  if (!h || !b || !x || !(tol > 0.0) || max_iter < 1 || (method != 0 && method != 1))
+    return OR_ERR_ARG;
+  const int64_t n = h->n;
+  memset(info, 0, sizeof(*info));
+  memset(&h->st, 0, sizeof(h->st));
+  h->hist_len = 0;
+  enum { NW = 10 };
+  double* w[NW];
+  for (int k = 0; k < NW; k++) w[k] = xcalloc((size_t)n, sizeof(double));
+  double *r = w[0], *z = w[1], *p = w[2], *q = w[3], *tmp = w[4];
+  double *rh = w[5], *v = w[6], *t = w[7], *ps = w[8], *sv = w[9];
+  if (!h->p.use_x0) memset(x, 0, (size_t)n * sizeof(double));
+  const double bn = nrm2(OR_F64, n, b);
+  int32_t status = OR_NOT_CONVERGED;
+  int it = 0;
+  double rel = 0.0;
+  if (bn == 0.0) {
+    memset(x, 0, (size_t)n * sizeof(double));
+    status = OR_OK;
+  } else if (method == 0) {
+    /* preconditioned conjugate gradients */
+    rel = relres_of(h, b, x, r, bn);
+    apply_p64(h, m64, r, z, tmp);
+    memcpy(p, z, (size_t)n * sizeof(double));
+    double rz = dot(OR_F64, n, r, z);
+    while (rel >= tol && it < max_iter) {
+      csr_mv(n, h->rp, h->ci, h->a, OR_F64, OR_F64, p, q);
+      const double alpha = rz / dot(OR_F64, n, p, q);
+      for (int64_t i = 0; i < n; i++) {
+        x[i] = x[i] + alpha * p[i];
+        r[i] = r[i] - alpha * q[i];
+      }
+      it++;
+      rel = nrm2(OR_F64, n, r) / bn;
+      hist_push(h, rel);
+      if (!isfinite(rel)) break;
+      if (rel < tol) {
+        /* confirm with the true residual; continue from it otherwise */
+        rel = relres_of(h, b, x, r, bn);
+        if (rel < tol) break;
+      }
+      apply_p64(h, m64, r, z, tmp);
+      const double rz1 = dot(OR_F64, n, r, z);
+      const double beta = rz1 / rz;
+      rz = rz1;
+      for (int64_t i = 0; i < n; i++) p[i] = z[i] + beta * p[i];
+    }
+  } else {
+    /* right-preconditioned BiCGStab; the preconditioned vectors P p and
+       P s are the ones added to x */
+    rel = relres_of(h, b, x, r, bn);
+    memcpy(rh, r, (size_t)n * sizeof(double));
+    double rho = 1.0, alpha = 1.0, omega = 1.0;
+    while (rel >= tol && it < max_iter) {
+      const double rho1 = dot(OR_F64, n, rh, r);
+      const double beta = (rho1 / rho) * (alpha / omega);
+      rho = rho1;
+      for (int64_t i = 0; i < n; i++) p[i] = r[i] + beta * (p[i] - omega * v[i]);
+      apply_p64(h, m64, p, z, tmp); /* z = P p */
+      csr_mv(n, h->rp, h->ci, h->a, OR_F64, OR_F64, z, v);
+      alpha = rho / dot(OR_F64, n, rh, v);
+      for (int64_t i = 0; i < n; i++) sv[i] = r[i] - alpha * v[i];
+      it++;
+      const double srel = nrm2(OR_F64, n, sv) / bn;
+      if (srel < tol) {
+        /* the half step already meets the tolerance */
+        for (int64_t i = 0; i < n; i++) x[i] = x[i] + alpha * z[i];
+        rel = relres_of(h, b, x, r, bn);
+        hist_push(h, rel);
+        if (rel < tol || !isfinite(rel)) break;
+        continue;
+      }
+      apply_p64(h, m64, sv, ps, tmp); /* P s */
+      csr_mv(n, h->rp, h->ci, h->a, OR_F64, OR_F64, ps, t);
+      omega = dot(OR_F64, n, t, sv) / dot(OR_F64, n, t, t);
+      for (int64_t i = 0; i < n; i++) {
+        x[i] = x[i] + alpha * z[i] + omega * ps[i];
+        r[i] = sv[i] - omega * t[i];
+      }
+      rel = nrm2(OR_F64, n, r) / bn;
+      hist_push(h, rel);
+      if (!isfinite(rel)) break;
+      if (rel < tol) {
+        rel = relres_of(h, b, x, r, bn);
+        if (rel < tol) break;
+      }
+    }
+  }
+  if (bn != 0.0) {
+    rel = relres_of(h, b, x, r, bn);
+    if (!isfinite(rel)) status = OR_ERR_BREAKDOWN;
+    else if (rel < tol) status = OR_OK;
+  }
+  for (int k = 0; k < NW; k++) free(w[k]);
+  info->status = status;
+  info->outer_iters = it;
+  info->m_calls = h->st.m_calls;
+  info->relres_true = rel;
+  info->relres_est = h->hist_len ? h->hist[h->hist_len - 1] : rel;
+  return status;
+}
+
+/* ------------------------------------------------------------------------ */
 /* accessors                                                                 */
 /* ------------------------------------------------------------------------ */
 

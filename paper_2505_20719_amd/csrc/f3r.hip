@@ -21,6 +21,7 @@
 #include "f3r.h"
 #include "host.h"
 #include "kernels.h"
+#include "krylov.h"
 #include "setup.h"
 
 using namespace f3r;
@@ -103,6 +104,9 @@ struct f3r_handle {
   double** ptrs_dev = nullptr;
   double* bcat = nullptr;
   double* xcat = nullptr;
+  // comparison solvers: ten work vectors and the scalar slots
+  double* kv = nullptr;
+  double* ks = nullptr;
   std::vector<std::vector<double>> history;  // per system
   // stats of the last solve
   int64_t graph_launches = 0;
@@ -1422,3 +1426,191 @@ f3r_status stacked_history(const f3r_handle* h, int32_t sys, double* buf, int64_
 }
 
 }  // namespace f3r
+
+// ===========================================================================
+// comparison solvers of Sec. 5: preconditioned CG and BiCGStab in fp64
+// ===========================================================================
+namespace {
+
+enum { KS_RZ0 = 0, KS_RZ1 = 1, KS_PQ = 2, KS_RHO0 = 3, KS_RHO1 = 4, KS_ALPHA = 5, KS_OMEGA = 6,
+       KS_RV = 7, KS_TS = 8, KS_TT = 9, KS_NORM = 10, KS_ONE = 11, KS_COUNT = 16 };
+
+f3r_status krylov_impl(f3r_handle* h, int method, int prec, const double* b, double* x, double tol,
+                       int max_iter, f3r_info* info) {
+  const int64_t n = h->n;
+  const int64_t nb = n_blocks(n);
+  const SysLayout one_sys{};
+  // M's values in the requested storage
+  const void* mv = nullptr;
+  int neg = 0;
+  if (h->m_shared) {
+    mv = h->ah[prec];
+    neg = 1;
+  } else {
+    mv = h->mv[prec];
+  }
+  if (!mv) return F3R_ERR_ARG;
+  const double gd = h->gd[prec];
+  if (!h->kv) {
+    h->kv = (double*)h->dalloc((size_t)10 * (size_t)n * sizeof(double));
+    h->ks = (double*)h->dalloc(KS_COUNT * sizeof(double));
+  }
+  double* V[10];
+  for (int k = 0; k < 10; k++) V[k] = h->kv + (size_t)k * (size_t)n;
+  double *r = V[0], *z = V[1], *p = V[2], *q = V[3], *tmp = V[4], *rh = V[5], *v = V[6], *t = V[7],
+         *ps = V[8], *sv = V[9];
+  double* ks = h->ks;
+  const double t0 = now_ms();
+  int64_t m_calls = 0;
+  auto prec_apply = [&](const double* in_v, double* out_v) {  // out = S M (S in)
+    Basis in;
+    in.raw = in_v;
+    in.type = T64;
+    in.scale = h->one;
+    in.s = h->s;
+    HIPCHK(m_apply_w(h->st, h->A, mv, prec, neg, in, tmp, T64, nullptr, nullptr));
+    HIPCHK(m_apply_g(h->st, h->A, mv, prec, neg, gd, tmp, T64, 3, nullptr, nullptr, out_v, T64, h->s,
+                     nullptr, nullptr, nullptr));
+    m_calls++;
+  };
+  auto sum_to = [&](int slot) {  // partials -> device slot
+    HIPCHK(finalize_sums(h->st, one_sys, T64, h->partials, nb, 1, nullptr, ks + slot, nullptr));
+  };
+  auto dot_to = [&](const double* a, const double* c, int slot) {
+    HIPCHK(dot64_partials(h->st, n, a, c, h->partials));
+    sum_to(slot);
+  };
+  auto host_norm = [&]() {  // sqrt of slot KS_NORM on the host
+    HIPCHK(hipMemcpyAsync(h->hpin, ks + KS_NORM, sizeof(double), hipMemcpyDeviceToHost, h->st));
+    HIPCHK(hipStreamSynchronize(h->st));
+    return std::sqrt(h->hpin[0]);
+  };
+  auto true_residual = [&]() {  // r = b - A x, its norm on the host
+    HIPCHK(residual64(h->st, h->A, h->a64, x, b, r, h->partials));
+    sum_to(KS_NORM);
+    return host_norm();
+  };
+  h->history.assign(1, std::vector<double>());
+  std::vector<double>& hist = h->history[0];
+  if (!(h->p.flags & F3R_USE_X0)) HIPCHK(hipMemsetAsync(x, 0, (size_t)n * sizeof(double), h->st));
+  dot_to(b, b, KS_NORM);
+  const double bn = host_norm();
+  f3r_status status = F3R_NOT_CONVERGED;
+  int it = 0;
+  double rel = 0.0, est = 0.0;
+  if (bn == 0.0) {
+    HIPCHK(hipMemsetAsync(x, 0, (size_t)n * sizeof(double), h->st));
+    status = F3R_OK;
+  } else if (!std::isfinite(bn)) {
+    status = F3R_ERR_ARG;
+  } else if (method == F3R_CG) {
+    rel = true_residual() / bn;
+    prec_apply(r, z);
+    HIPCHK(hipMemcpyAsync(p, z, (size_t)n * sizeof(double), hipMemcpyDeviceToDevice, h->st));
+    int cur = KS_RZ0, nxt = KS_RZ1;
+    dot_to(r, z, cur);
+    while (rel >= tol && it < max_iter) {
+      // q = A p and (p, q)
+      HIPCHK(spmv_dots(h->st, h->A, h->a64, T64, p, T64, nullptr, nullptr, q, T64, p, nullptr, 1,
+                       h->partials, nullptr));
+      sum_to(KS_PQ);
+      HIPCHK(cg_update_xr(h->st, n, x, r, p, q, ks + cur, ks + KS_PQ, h->partials));
+      sum_to(KS_NORM);
+      it++;
+      est = rel = host_norm() / bn;
+      hist.push_back(rel);
+      if (!std::isfinite(rel)) break;
+      if (rel < tol) {
+        rel = true_residual() / bn;  // confirmed, or continue from the true residual
+        if (rel < tol) break;
+      }
+      prec_apply(r, z);
+      dot_to(r, z, nxt);
+      HIPCHK(cg_update_p(h->st, n, p, z, ks + nxt, ks + cur));
+      std::swap(cur, nxt);
+    }
+  } else {
+    rel = true_residual() / bn;
+    HIPCHK(hipMemcpyAsync(rh, r, (size_t)n * sizeof(double), hipMemcpyDeviceToDevice, h->st));
+    HIPCHK(hipMemsetAsync(p, 0, (size_t)n * sizeof(double), h->st));
+    HIPCHK(hipMemsetAsync(v, 0, (size_t)n * sizeof(double), h->st));
+    const double ones[3] = {1.0, 1.0, 1.0};  // rho, alpha, omega start at 1
+    HIPCHK(hipMemcpy(ks + KS_RHO0, ones, sizeof(double), hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(ks + KS_ALPHA, ones + 1, 2 * sizeof(double), hipMemcpyHostToDevice));
+    int cur = KS_RHO0, nxt = KS_RHO1;
+    while (rel >= tol && it < max_iter) {
+      dot_to(rh, r, nxt);
+      HIPCHK(bicg_update_p(h->st, n, p, r, v, ks + nxt, ks + cur, ks + KS_ALPHA, ks + KS_OMEGA));
+      std::swap(cur, nxt);  // rho = rho_new
+      prec_apply(p, z);
+      // v = A z and (rh, v)
+      HIPCHK(spmv_dots(h->st, h->A, h->a64, T64, z, T64, nullptr, nullptr, v, T64, rh, nullptr, 1,
+                       h->partials, nullptr));
+      sum_to(KS_RV);
+      HIPCHK(bicg_update_s(h->st, n, sv, r, v, ks + cur, ks + KS_RV, ks + KS_ALPHA, h->partials));
+      sum_to(KS_NORM);
+      it++;
+      const double srel = host_norm() / bn;
+      if (srel < tol) {  // the half step meets the tolerance
+        HIPCHK(axpy_dev(h->st, n, x, z, ks + KS_ALPHA));
+        est = rel = true_residual() / bn;
+        hist.push_back(rel);
+        if (rel < tol || !std::isfinite(rel)) break;
+        continue;
+      }
+      prec_apply(sv, ps);
+      // t = A ps and (t, s); then (t, t)
+      HIPCHK(spmv_dots(h->st, h->A, h->a64, T64, ps, T64, nullptr, nullptr, t, T64, sv, nullptr, 1,
+                       h->partials, nullptr));
+      sum_to(KS_TS);
+      dot_to(t, t, KS_TT);
+      HIPCHK(bicg_update_xr(h->st, n, x, r, sv, t, z, ps, ks + KS_ALPHA, ks + KS_TS, ks + KS_TT,
+                            ks + KS_OMEGA, h->partials));
+      sum_to(KS_NORM);
+      est = rel = host_norm() / bn;
+      hist.push_back(rel);
+      if (!std::isfinite(rel)) break;
+      if (rel < tol) {
+        rel = true_residual() / bn;
+        if (rel < tol) break;
+      }
+    }
+  }
+  if (bn != 0.0 && std::isfinite(bn)) {
+    rel = true_residual() / bn;
+    if (!std::isfinite(rel))
+      status = F3R_ERR_BREAKDOWN;
+    else if (rel < tol)
+      status = F3R_OK;
+  }
+  const double t1 = now_ms();
+  if (info) {
+    std::memset(info, 0, sizeof(*info));
+    info->status = status;
+    info->outer_iters = it;
+    info->m_calls = m_calls;
+    info->spmv[0] = method == F3R_CG ? it : 2 * (int64_t)it;
+    info->relres_est = est;
+    info->relres_true = rel;
+    info->setup_ms = h->setup_ms;
+    info->solve_ms = t1 - t0;
+    info->idx_bits = h->A.idx16 ? 16 : 32;
+    info->sell_c = 64;
+    info->padded_nnz = h->padded;
+  }
+  return status;
+}
+
+}  // namespace
+
+extern "C" f3r_status f3r_krylov_solve(f3r_handle* h, int32_t method, int32_t prec_m,
+                                       const double* b, double* x, double tol, int32_t max_iter,
+                                       f3r_info* info) {
+  if (!h || !b || !x || !(tol > 0.0) || max_iter < 1 || !prec_ok(prec_m)) return F3R_ERR_ARG;
+  if (method != F3R_CG && method != F3R_BICGSTAB) return F3R_ERR_ARG;
+  if (h->nsys != 1) return F3R_ERR_ARG;
+  return guarded(h, info, [&]() {
+    HIPCHK(hipSetDevice(h->device));
+    return krylov_impl(h, method, prec_m, b, x, tol, max_iter, info);
+  });
+}

@@ -24,6 +24,7 @@ USE_X0, PERSIST_WEIGHTS, NO_GRAPH, BATCH_LOCKSTEP = 1, 2, 4, 8
 MAX_LEVELS = 8
 
 OK, NOT_CONVERGED = 0, 1
+CG, BICGSTAB = 0, 1  # comparison solvers of Sec. 5
 ERR_ARG, ERR_MATRIX, ERR_RANGE, ERR_NOMEM, ERR_DEVICE, ERR_BREAKDOWN = -1, -2, -3, -4, -5, -6
 
 
@@ -78,6 +79,8 @@ EXPORTS = {
                               C.POINTER(Info)]),
     "f3r_fgmres_solve": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_double, C.c_int32,
                                      C.c_int32, C.POINTER(Info)]),
+    "f3r_krylov_solve": (C.c_int32, [C.c_void_p, C.c_int32, C.c_int32, C.c_void_p, C.c_void_p,
+                                     C.c_double, C.c_int32, C.POINTER(Info)]),
     "f3r_get_history": (C.c_int32, [C.c_void_p, C.c_int32, C.c_void_p, C.c_int64,
                                     C.POINTER(C.c_int64)]),
     "f3r_get_weights": (C.c_int32, [C.c_void_p, C.c_int32, C.c_void_p, C.POINTER(C.c_int64)]),
@@ -195,6 +198,19 @@ class Solver:
         st = self.L.f3r_fgmres_solve(self.h, _dptr(b), _dptr(x), tol, m, max_iter, C.byref(info))
         if st < 0 and raise_on_error:
             raise F3RError(st, "f3r_fgmres_solve")
+        return x, info
+
+    def krylov_solve(self, b, method=CG, prec_m=FP64, x=None, tol=1e-10, max_iter=10000,
+                     raise_on_error=True):
+        """Preconditioned CG or BiCGStab in fp64 with S M (S v), M stored in prec_m."""
+        import torch
+        if x is None:
+            x = torch.zeros(self.n, dtype=torch.float64, device=b.device)
+        info = Info()
+        st = self.L.f3r_krylov_solve(self.h, method, prec_m, _dptr(b), _dptr(x), tol, max_iter,
+                                     C.byref(info))
+        if st < 0 and raise_on_error:
+            raise F3RError(st, "f3r_krylov_solve")
         return x, info
 
     def history(self, level=0):
