@@ -175,12 +175,15 @@ f3r_status f3r_setup(const f3r_csr* A, const f3r_params* p, void* hip_stream,
 f3r_status f3r_solve(f3r_handle* h, const double* b, double* x, double tol,
                      const f3r_params* level_override, f3r_info* info);
 
-/* Restarted FGMRES(m) preconditioned by M with every value in fp64: the
-   comparison solver of Sec. 5 ("fp64-FGMRES(64)").  Same conventions as
-   f3r_solve; max_iter counts iterations over all restarts. */
+/* Restarted FGMRES(m) in fp64 preconditioned by S M (S v): the comparison
+   solver of Sec. 5.  prec_m is the storage of M's values (F3R_FP64 for
+   "fp64-FGMRES(64)", or a precision the handle holds -- its prec_m, and any
+   level precision when alpha = 1 -- for the fp32/fp16 variants; arithmetic
+   stays fp64); others give F3R_ERR_ARG.  Same conventions as f3r_solve;
+   max_iter counts iterations over all restarts, m <= the set-up m1. */
 f3r_status f3r_fgmres_solve(f3r_handle* h, const double* b, double* x,
                             double tol, int32_t m, int32_t max_iter,
-                            f3r_info* info);
+                            int32_t prec_m, f3r_info* info);
 
 /* The other comparison solvers of Sec. 5: preconditioned CG (method F3R_CG,
    for symmetric positive definite A) or right-preconditioned BiCGStab
@@ -190,7 +193,9 @@ f3r_status f3r_fgmres_solve(f3r_handle* h, const double* b, double* x,
    Convergence is tested on the recursive residual and confirmed with the
    fp64 true residual (the iteration continues from it otherwise); max_iter
    bounds the iterations.  info->outer_iters counts iterations, m_calls the
-   applications of M.  Same conventions as f3r_solve. */
+   applications of M.  Same conventions as f3r_solve; F3R_ERR_ARG for an
+   unknown method, a precision the handle does not hold, tol <= 0 or
+   max_iter < 1, and on a batched (stacked) handle. */
 #define F3R_CG 0
 #define F3R_BICGSTAB 1
 f3r_status f3r_krylov_solve(f3r_handle* h, int32_t method, int32_t prec_m, const double* b,

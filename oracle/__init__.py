@@ -86,7 +86,7 @@ def lib():
         "or_destroy": (None, [H]),
         "or_solve": (C.c_int32, [H, _dp, _dp, C.c_double, C.POINTER(Info)]),
         "or_fgmres_solve": (C.c_int32, [H, _dp, _dp, C.c_double, C.c_int32,
-                                        C.c_int32, C.POINTER(Info)]),
+                                        C.c_int32, C.c_int32, C.POINTER(Info)]),
         "or_krylov_solve": (C.c_int32, [H, C.c_int32, C.c_int32, _dp, _dp, C.c_double,
                                         C.c_int32, C.POINTER(Info)]),
         "or_n": (C.c_int64, [H]),
@@ -204,11 +204,11 @@ class Oracle:
         self.L.or_solve(self.h, b, x, tol, C.byref(info))
         return x, info
 
-    def fgmres_solve(self, b, tol=1e-10, m=64, max_iter=19200):
+    def fgmres_solve(self, b, tol=1e-10, m=64, max_iter=19200, m64=True):
         b = np.ascontiguousarray(b, dtype=np.float64)
         x = np.zeros(self.n)
         info = Info()
-        self.L.or_fgmres_solve(self.h, b, x, tol, m, max_iter, C.byref(info))
+        self.L.or_fgmres_solve(self.h, b, x, tol, m, max_iter, int(bool(m64)), C.byref(info))
         return x, info
 
     def krylov_solve(self, b, method=CG, m64=True, tol=1e-10, max_iter=10000, x0=None):

@@ -194,7 +194,8 @@ struct or_handle {
   double omega[OR_MAX_LEV][64];
   int64_t cntr[OR_MAX_LEV];
   or_info st;
-  int32_t baseline; /* 1 while running FGMRES(m) + M64 */
+  int32_t baseline; /* 1 while running the comparison FGMRES(m) */
+  int32_t base_m64; /* its M: fp64 factors (1) or the pM ones (0) */
   double* hist;
   int64_t hist_len, hist_cap;
   int32_t last_m;
@@ -556,7 +557,7 @@ static void apply_prec(or_handle* h, int d, const double* v, double* z) {
     double* t1 = h->ws[0].tmp1;
     for (int64_t i = 0; i < n; i++) t0[i] = h->s[i] * v[i];
     if (h->baseline || h->p.nlev == 1)
-      apply_m_impl(h, OR_F64, OR_F64, h->baseline, t0, t1);
+      apply_m_impl(h, OR_F64, OR_F64, h->baseline && h->base_m64, t0, t1);
     else
       apply_level_impl(h, 1, t0, t1);
     for (int64_t i = 0; i < n; i++) z[i] = h->s[i] * t1[i];
@@ -845,10 +846,11 @@ int32_t or_solve(or_handle* h, const double* b, double* x, double tol,
 }
 
 int32_t or_fgmres_solve(or_handle* h, const double* b, double* x, double tol,
-                        int32_t m, int32_t max_iter, or_info* info) {
+                        int32_t m, int32_t max_iter, int32_t m64, or_info* info) {
   if (!h || !b || !x || !(tol > 0.0) || m < 1 || max_iter < 1)
     return OR_ERR_ARG;
   h->baseline = 1;
+  h->base_m64 = m64 != 0;
   int32_t st = outer_solve(h, b, x, tol, m, max_iter, info);
   h->baseline = 0;
   return st;

@@ -96,15 +96,16 @@ int32_t or_setup(int64_t n, int64_t nnz, const int32_t* row_ptr,
 void or_destroy(or_handle* h);
 int32_t or_solve(or_handle* h, const double* b, double* x, double tol,
                  or_info* info);
+/* comparison solvers (Sec. 5), fp64 vectors and arithmetic, preconditioner
+   S M (S v) with M's factors in fp64 (m64 = 1) or in the handle's pM (0):
+   restarted FGMRES(m), and method 0 = preconditioned CG, 1 = right-
+   preconditioned BiCGStab. */
 int32_t or_fgmres_solve(or_handle* h, const double* b, double* x, double tol,
-                        int32_t m, int32_t max_iter, or_info* info);
-
-/* ---- pieces, for lockstep comparisons and pins ---- */
-/* comparison solvers (Sec. 5): method 0 = preconditioned CG, 1 = right-
-   preconditioned BiCGStab; fp64 vectors and arithmetic, preconditioner
-   S M (S v) with M's factors in fp64 (m64 = 1) or in the handle's pM. */
+                        int32_t m, int32_t max_iter, int32_t m64, or_info* info);
 int32_t or_krylov_solve(or_handle* h, int32_t method, int32_t m64, const double* b,
                         double* x, double tol, int32_t max_iter, or_info* info);
+
+/* ---- pieces, for lockstep comparisons and pins ---- */
 int64_t or_n(const or_handle* h);
 void or_get_scaling(const or_handle* h, double* s);
 void or_get_level_values(const or_handle* h, int32_t p, double* vals);

@@ -104,6 +104,7 @@ struct f3r_handle {
   double** ptrs_dev = nullptr;
   double* bcat = nullptr;
   double* xcat = nullptr;
+  int base_prec = T64;  // storage of M in the comparison FGMRES
   // comparison solvers: ten work vectors and the scalar slots
   double* kv = nullptr;
   double* ks = nullptr;
@@ -651,10 +652,12 @@ void baseline_prec(f3r_handle* h) {
   in.s = h->s;
   in.cur = L0.I + I_CUR;
   in.stride = h->n;
-  const void* mv = h->m_shared ? h->ah[T64] : h->mv[T64];
+  // M's values in the storage the call asked for (fp64 arithmetic)
+  const int tm = h->base_prec;
+  const void* mv = h->m_shared ? h->ah[tm] : h->mv[tm];
   const int neg = h->m_shared ? 1 : 0;
-  HIPCHK(m_apply_w(h->st, h->A, mv, T64, neg, in, h->tmp64, T64, L0.I + I_STOP, nullptr));
-  HIPCHK(m_apply_g(h->st, h->A, mv, T64, neg, h->gd[T64], h->tmp64, T64, 3, nullptr, nullptr, L0.Z,
+  HIPCHK(m_apply_w(h->st, h->A, mv, tm, neg, in, h->tmp64, T64, L0.I + I_STOP, nullptr));
+  HIPCHK(m_apply_g(h->st, h->A, mv, tm, neg, h->gd[tm], h->tmp64, T64, 3, nullptr, nullptr, L0.Z,
                    T64, h->s, L0.I + I_FB, L0.I + I_STOP, L0.I + I_CUR));
 }
 
@@ -1158,9 +1161,12 @@ f3r_status f3r_solve(f3r_handle* h, const double* b, double* x, double tol,
 }
 
 f3r_status f3r_fgmres_solve(f3r_handle* h, const double* b, double* x, double tol, int32_t m,
-                            int32_t max_iter, f3r_info* info) {
-  if (!h || !b || !x || !(tol > 0.0) || m < 1 || max_iter < 1) return F3R_ERR_ARG;
+                            int32_t max_iter, int32_t prec_m, f3r_info* info) {
+  if (!h || !b || !x || !(tol > 0.0) || m < 1 || max_iter < 1 || !prec_ok(prec_m))
+    return F3R_ERR_ARG;
   if (m > h->p.lev[0].m) return F3R_ERR_ARG;
+  if (!(h->m_shared ? h->ah[prec_m] : h->mv[prec_m])) return F3R_ERR_ARG;
+  h->base_prec = prec_m;
   return guarded(h, info, [&]() {
     HIPCHK(hipSetDevice(h->device));
     return outer_solve(h, b, x, tol, m, max_iter, true, false, info);

@@ -78,7 +78,7 @@ EXPORTS = {
     "f3r_solve": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_double, C.c_void_p,
                               C.POINTER(Info)]),
     "f3r_fgmres_solve": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_double, C.c_int32,
-                                     C.c_int32, C.POINTER(Info)]),
+                                     C.c_int32, C.c_int32, C.POINTER(Info)]),
     "f3r_krylov_solve": (C.c_int32, [C.c_void_p, C.c_int32, C.c_int32, C.c_void_p, C.c_void_p,
                                      C.c_double, C.c_int32, C.POINTER(Info)]),
     "f3r_get_history": (C.c_int32, [C.c_void_p, C.c_int32, C.c_void_p, C.c_int64,
@@ -190,12 +190,14 @@ class Solver:
             raise F3RError(st, "f3r_solve")
         return x, info
 
-    def fgmres_solve(self, b, x=None, tol=1e-10, m=64, max_iter=19200, raise_on_error=True):
+    def fgmres_solve(self, b, x=None, tol=1e-10, m=64, max_iter=19200, prec_m=FP64,
+                     raise_on_error=True):
         import torch
         if x is None:
             x = torch.zeros(self.n, dtype=torch.float64, device=b.device)
         info = Info()
-        st = self.L.f3r_fgmres_solve(self.h, _dptr(b), _dptr(x), tol, m, max_iter, C.byref(info))
+        st = self.L.f3r_fgmres_solve(self.h, _dptr(b), _dptr(x), tol, m, max_iter, prec_m,
+                                     C.byref(info))
         if st < 0 and raise_on_error:
             raise F3RError(st, "f3r_fgmres_solve")
         return x, info

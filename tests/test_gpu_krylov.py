@@ -3,8 +3,10 @@ BiCGStab, fp64, preconditioner S M (S v)) through the C ABI, against the
 oracle on the same seeded systems.
 
 Bars: both reach the fp64 relative residual (checked here with an
-independent fp64 matvec); iteration counts agree within one (the two sum in
-different orders); solutions differ by at most kappa (res_gpu + res_oracle);
+independent fp64 matvec); the iterates after k = 1 .. 12 steps agree to
+rounding; final iteration counts agree within one for CG and within 10 %
+(plus two) for BiCGStab, whose non-monotone residual amplifies the different
+summation order; solutions differ by at most kappa (res_gpu + res_oracle);
 repeated solves are bitwise equal; at full size the residual and the
 iteration counts of the two preconditioner precisions are checked."""
 import numpy as np
@@ -75,17 +77,39 @@ def test_krylov_matches_oracle(name, make, methods, m64, alpha):
         assert ig.status == P().OK and io.status == O.OK
         rg = relres(A, b, host(xg))
         assert rg < 1e-10 and np.isclose(rg, ig.relres_true, rtol=1e-6), (rg, ig.relres_true)
-        assert abs(ig.outer_iters - io.outer_iters) <= 1, (ig.outer_iters, io.outer_iters)
-        assert abs(ig.m_calls - io.m_calls) <= 2
-        assert np.linalg.norm(host(xg) - xo) / np.linalg.norm(xo) <= kappa * (rg + io.relres_true)
-        h = g.history()
+        h, ho = g.history(), o.history()
+        print(f"  iterations gpu {ig.outer_iters} oracle {io.outer_iters}", flush=True)
         assert len(h) == ig.outer_iters and h[-1] == ig.relres_est
-        # the first few residuals agree closely (same arithmetic, other sum order)
-        ho = o.history()
+        # the first residuals agree closely (same arithmetic, other sum order)
         k = min(5, len(h), len(ho))
         assert np.allclose(h[:k], ho[:k], rtol=1e-9), (h[:k], ho[:k])
+        # CG's counts agree within one; BiCGStab's residual is not monotone
+        # and amplifies rounding differences, so its bar is 10 % (plus two)
+        slack = 1 if method == P().CG else max(2, int(0.1 * io.outer_iters))
+        assert abs(ig.outer_iters - io.outer_iters) <= slack, (ig.outer_iters, io.outer_iters)
+        assert abs(ig.m_calls - io.m_calls) <= 2 * slack
+        assert np.linalg.norm(host(xg) - xo) / np.linalg.norm(xo) <= kappa * (rg + io.relres_true)
         xg2, ig2 = g.krylov_solve(dev(b), method, prec, tol=1e-10)
         assert torch.equal(xg, xg2) and ig2.outer_iters == ig.outer_iters
+    g.close()
+    o.close()
+
+
+@pytest.mark.parametrize("method", [0, 1])
+def test_krylov_iterates_match_oracle_step_by_step(method):
+    # after k iterations (k = 1 .. 12) the GPU iterate equals the oracle's to
+    # rounding: the same recurrences in the same order
+    A = W.convdiff_q1(12) if method == 1 else W.varcoef2d(30, tag="krylovstep")
+    b = W.rhs(A, "krylovstep")[1]
+    g = P().Solver(A.row_ptr, A.col_idx, A.val)
+    o = O.Oracle(A.row_ptr, A.col_idx, A.val, O.default_params(O.FP16_F3R))
+    print(f"[case] krylov step by step method={method}", flush=True)
+    for k in range(1, 13):
+        xg, ig = g.krylov_solve(dev(b), method, tol=1e-30, max_iter=k)
+        xo, io = o.krylov_solve(b, method, tol=1e-30, max_iter=k)
+        assert ig.outer_iters == io.outer_iters == k
+        assert np.linalg.norm(host(xg) - xo) <= 1e-10 * np.linalg.norm(xo), k
+        assert np.isclose(ig.relres_true, io.relres_true, rtol=1e-8)
     g.close()
     o.close()
 
@@ -136,3 +160,33 @@ def test_krylov_fullsize_poisson3d_128():
     for method in (P().CG, P().BICGSTAB):
         assert abs(its[(method, P().FP16)] - its[(method, P().FP64)]) <= 0.1 * its[(method, P().FP64)] + 2
     g.close()
+
+
+@pytest.mark.parametrize("variant", [0, 1])
+def test_fgmres_with_narrow_m_matches_oracle(variant):
+    # the fp32-/fp16-FGMRES(64) comparison solvers: fp64 FGMRES with M's
+    # values stored in the nest's pM
+    A = W.convdiff_q1(20)
+    b = W.rhs(A, "convdiff_q1_20")[1]
+    p = P().params_default(variant)
+    q = O.default_params({0: O.FP16_F3R, 1: O.FP32_F3R}[variant])
+    g = P().Solver(A.row_ptr, A.col_idx, A.val, p)
+    o = O.Oracle(A.row_ptr, A.col_idx, A.val, q)
+    print(f"[case] fgmres narrow M variant={variant} prec={p.prec_m}", flush=True)
+    xg, ig = g.fgmres_solve(dev(b), prec_m=p.prec_m)
+    xo, io = o.fgmres_solve(b, m64=False)
+    assert ig.status == P().OK and io.status == O.OK
+    rg = relres(A, b, host(xg))
+    assert rg < 1e-10 and abs(ig.outer_iters - io.outer_iters) <= 1
+    kappa = np.linalg.cond(A.to_scipy().toarray())
+    assert np.linalg.norm(host(xg) - xo) / np.linalg.norm(xo) <= kappa * (rg + io.relres_true)
+    h, ho = g.history(), o.history()
+    k = min(len(h), len(ho))
+    assert np.allclose(h[:k - 1], ho[:k - 1], rtol=1e-6)
+    # fp64 M gives other iterates
+    x64, i64 = g.fgmres_solve(dev(b))
+    assert not torch.equal(x64, xg)
+    with pytest.raises(P().F3RError):
+        g.fgmres_solve(dev(b), prec_m=P().BF16)
+    g.close()
+    o.close()

@@ -54,16 +54,24 @@ def test_givens_estimate_equals_true_residual():
         assert np.isclose(info.relres_true, true, rtol=1e-10)
 
 
-def test_equals_right_preconditioned_gmres_brute_force():
+@pytest.mark.parametrize("m64", [True, False])
+def test_equals_right_preconditioned_gmres_brute_force(m64):
+    # m64: M's factors in fp64 (fp64-FGMRES); otherwise rounded to fp16
+    # (the fp16-FGMRES comparison solver), arithmetic fp64 in both
     A = random_sparse_system(40, 0.15, seed=21)
-    o = _fgmres(A)
+    o = _fgmres(A) if m64 else O.Oracle(A.row_ptr, A.col_idx, A.val, O.default_params(O.FP16_F3R))
     D = dense(A)
     s = 1.0 / np.sqrt(np.abs(np.diag(D)))
-    (wrp, wci, wv), (grp, gci, gv) = o.m_factors()
-    M = csr_dense(grp, gci, gv, A.n) @ csr_dense(wrp, wci, wv, A.n)
+    Ah = s[:, None] * D * s[None, :]
+    I = np.eye(A.n)
+    W = I - np.tril(Ah, -1)
+    G = I - np.triu(Ah, 1)
+    if not m64:
+        W, G = W.astype(np.float16).astype(np.float64), G.astype(np.float16).astype(np.float64)
+    M = G @ W
     P = s[:, None] * M * s[None, :]  # outermost preconditioner S M S
     b = np.random.default_rng(2).uniform(0, 1, A.n)
-    o.fgmres_solve(b, tol=1e-30, m=8, max_iter=8)
+    o.fgmres_solve(b, tol=1e-30, m=8, max_iter=8, m64=m64)
     hist = o.history()
     AP = D @ P
     K = [b / np.linalg.norm(b)]
