@@ -351,7 +351,7 @@ def main():
         for key, method in methods:
             for pk, prec in (("fp64", P.FP64), ("fp16", P.FP16)):
                 runs.append((f"{pk}_{key}", lambda method=method, prec=prec: s16.krylov_solve(
-                    bt, method, prec, tol=tol, max_iter=20000)))
+                    bt, method, prec, tol=tol, max_iter=19200)))
         for key, fn in runs:
             (xk, ik), tk, totk = timed_solves(fn, reps, 1)
             assert ik.status == 0, (key, ik.as_dict())

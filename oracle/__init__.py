@@ -211,7 +211,7 @@ class Oracle:
         self.L.or_fgmres_solve(self.h, b, x, tol, m, max_iter, int(bool(m64)), C.byref(info))
         return x, info
 
-    def krylov_solve(self, b, method=CG, m64=True, tol=1e-10, max_iter=10000, x0=None):
+    def krylov_solve(self, b, method=CG, m64=True, tol=1e-10, max_iter=19200, x0=None):
         """Preconditioned CG (method CG) or BiCGStab (BICGSTAB), fp64, with
         S M (S v) as preconditioner; M's factors in fp64 or in pM."""
         b = np.ascontiguousarray(b, dtype=np.float64)

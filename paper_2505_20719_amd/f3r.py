@@ -202,7 +202,7 @@ class Solver:
             raise F3RError(st, "f3r_fgmres_solve")
         return x, info
 
-    def krylov_solve(self, b, method=CG, prec_m=FP64, x=None, tol=1e-10, max_iter=10000,
+    def krylov_solve(self, b, method=CG, prec_m=FP64, x=None, tol=1e-10, max_iter=19200,
                      raise_on_error=True):
         """Preconditioned CG or BiCGStab in fp64 with S M (S v), M stored in prec_m."""
         import torch
