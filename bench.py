@@ -238,6 +238,8 @@ def main():
     ap.add_argument("--paper-protocol", action="store_true",
                     help="b uniform on [0,1) and tolerance 1e-8 (the paper's runs, Sec. 5) instead of "
                          "b = A x* and 1e-10")
+    ap.add_argument("--layout", choices=("auto", "sell", "diag"), default="auto",
+                    help="device matrix format (default: picked at set-up by padding)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="first run one plain device copy of MIB MiB (reference for HBM byte counters)")
     args = ap.parse_args()
@@ -277,7 +279,14 @@ def main():
     log(f"[bench] {name} n={A.n} nnz={A.nnz}")
 
     t = time.perf_counter()
-    s16 = P.Solver(A.row_ptr, A.col_idx, A.val, P.params_default(P.VARIANT_FP16))
+    layout = {"auto": P.LAYOUT_AUTO, "sell": P.LAYOUT_SELL, "diag": P.LAYOUT_DIAG}[args.layout]
+
+    def params(variant):
+        p = P.params_default(variant)
+        p.layout = layout
+        return p
+
+    s16 = P.Solver(A.row_ptr, A.col_idx, A.val, params(P.VARIANT_FP16))
     torch.cuda.synchronize()
     setup_s = time.perf_counter() - t
 
@@ -305,7 +314,8 @@ def main():
         "f3r_fp16_m_calls": info16.m_calls,
         "relres_true": info16.relres_true,
         "err_vs_xstar": err_xstar,
-        "device_format": f"SELL-64, {info16.idx_bits}-bit column indices, "
+        "device_format": ("diagonal-aligned " if info16.layout == P.LAYOUT_DIAG else "")
+                         + f"SELL-64, {info16.idx_bits}-bit column indices, "
                          f"{info16.padded_nnz / A.nnz:.4f} padded/stored entries",
         "tuned_shapes": {k: f"{info16.rows_per_lane[i]} rows/lane, chunks of {info16.entry_chunk[i]}"
                          for i, k in enumerate(("m_lower", "m_upper", "r_residual"))},
@@ -329,7 +339,7 @@ def main():
                            "fgmres64_err_vs_xstar": err_of(xf.cpu().numpy()),
                            "speedup_vs_fgmres64": round(fg_s / mean_s, 3)})
         for key in extra:
-            s = P.Solver(A.row_ptr, A.col_idx, A.val, P.params_default(getattr(P, VARIANTS[key])))
+            s = P.Solver(A.row_ptr, A.col_idx, A.val, params(getattr(P, VARIANTS[key])))
             (xv, iv), tv, totv = timed_solves(lambda: s.solve(bt, tol=tol), 2, 1)
             assert iv.status == 0, iv.as_dict()
             result_cfg[f"f3r_{key}_s"] = round(totv / 2, 6)
@@ -384,6 +394,23 @@ def main():
                 "bytes_per_launch": int(ab[dom]), "avg_launch_us": round(kern[dom]["avg_us"], 3)}
     result_cfg["kernels"] = {k: {kk: round(vv, 3) if isinstance(vv, float) else vv for kk, vv in v.items()}
                              for k, v in kern.items()}
+    # standalone level SpMVs, warm (back to back) and cold (a 1 GiB buffer
+    # overwritten before every launch evicts the 256 MB last-level cache)
+    scrub = torch.empty(1 << 27, dtype=torch.float64, device="cuda")
+    si = info16.idx_bits // 8
+    spmv = {}
+    for level, key, sa, sx, sy in ((0, "l0_fp64", 8, 8, 8), (1, "l1_fp32", 4, 4, 4),
+                                   (2, "l2_fp16", 2, 2, 4)):
+        nbytes = A.nnz * (sa + si) + A.n / 16.0 + A.n * (sx + sy)
+        warm = s16.time_spmv(level, reps=20)
+        cold = s16.time_spmv(level, reps=20, scrub=scrub)
+        spmv[key] = {"bytes": int(nbytes), "warm_us": round(warm * 1e3, 3),
+                     "warm_gbs": round(nbytes / (warm * 1e-3) / 1e9, 1),
+                     "cold_us": round(cold * 1e3, 3), "cold_gbs": round(nbytes / (cold * 1e-3) / 1e9, 1)}
+        log(f"[bench] standalone SpMV {key}: {nbytes / 1e6:.1f} MB, warm {warm * 1e3:.2f} us "
+            f"({spmv[key]['warm_gbs']:.0f} GB/s), cold {cold * 1e3:.2f} us ({spmv[key]['cold_gbs']:.0f} GB/s)")
+    del scrub
+    result_cfg["spmv_standalone"] = spmv
 
     cpu = None
     if not args.no_cpu_baseline:

@@ -75,6 +75,13 @@ typedef int32_t f3r_status;
 #define F3R_PROBE_SPMV_L1 5    /* SpMV + Gram-Schmidt dots of level 1 */
 #define F3R_PROBE_SPMV_L0 6    /* SpMV + Gram-Schmidt dots of level 0 */
 
+/* device matrix formats (f3r_params.layout) */
+#define F3R_LAYOUT_AUTO 0      /* DIAG when it stores at most 3 % more entries than SELL */
+#define F3R_LAYOUT_SELL 1      /* slices of 64 rows, each padded to its longest row */
+#define F3R_LAYOUT_DIAG 2      /* slices of 64 rows of one common width with every
+                                  row's diagonal at one common position: no
+                                  per-slice offsets or bounds to load */
+
 #define F3R_MAX_LEVELS 8
 
 typedef struct {
@@ -109,7 +116,9 @@ typedef struct {
   int32_t entry_chunk;           /* with rows_per_lane != 0: entries per load
                                     chunk (0 = 8, 4, 4 for 1, 2, 4 rows; 3 is
                                     allowed with 2 or 4 rows and narrow vectors) */
-  int32_t reserved[4];
+  int32_t layout;                /* F3R_LAYOUT_*: device format of the matrix
+                                    and M; results do not depend on it */
+  int32_t reserved[3];
 } f3r_params;
 
 typedef struct {
@@ -144,6 +153,8 @@ typedef struct {
   int32_t rows_per_lane[3]; /* shapes in use: W sweep, G sweep, Richardson residual */
   int32_t entry_chunk[3];   /* entries per load chunk of the same three sweeps */
   double tune_ms;        /* set-up time spent timing the candidate shapes */
+  int32_t layout;        /* F3R_LAYOUT_SELL or F3R_LAYOUT_DIAG: format in use */
+  int32_t reserved_i;
 } f3r_info;
 
 typedef struct f3r_handle f3r_handle;
@@ -278,6 +289,18 @@ void f3r_batch_destroy(f3r_batch* bt);
    arithmetic, Sec. 4.2). */
 f3r_status f3r_debug_spmv(f3r_handle* h, int32_t level, const double* x,
                           double* y);
+
+/* Measurement of the level SpMV of Sec. 4.2 on its own: `reps` launches of
+   level `level`'s SpMV (an FGMRES level: level 0 is the fp64 matrix with
+   fp64 vectors, deeper levels their Table 1 storage) on the handle's own
+   buffers, each bracketed by its own pair of HIP events on the handle's
+   stream.  With scrub_bytes > 0, a device buffer `scrub` (caller-owned) is
+   overwritten before every launch so that the matrix is read from HBM and not
+   from the caches.  *avg_ms = mean launch time.  Overwrites the level's first
+   Z slot and second V slot (solve state), nothing else.  F3R_ERR_ARG for a
+   Richardson level or bad sizes. */
+f3r_status f3r_time_spmv(f3r_handle* h, int32_t level, int32_t reps, void* scrub,
+                         int64_t scrub_bytes, double* avg_ms);
 
 /* y = M r with vectors stored in prec (the two-SpMV application of
    Sec. 5.2; fp32 arithmetic for narrow prec, fp64 for fp64). prec must be

@@ -292,9 +292,9 @@ template <class TI, class T16> struct Solver {
       for (int r = 0; r < kRB; r++) {
         const int64_t slice = gw * kRB + r;
         lo[r] = 0;
-        hi[r] = s[r].ok ? max((int)(A.kdr[slice] >> 16), 1) : 1;
+        hi[r] = s[r].ok ? max(A.dell_w ? A.dell_kd : (int)(A.kdr[slice] >> 16), 1) : 1;
         kb[r] = 0;
-        ke[r] = s[r].ok ? (int)A.kd[s[r].row] : 0;
+        ke[r] = s[r].ok ? (A.dell_w ? A.dell_kd : (int)A.kd[s[r].row]) : 0;
         acc[r] = 0.f;
       }
 #pragma unroll
@@ -318,8 +318,8 @@ template <class TI, class T16> struct Solver {
 #pragma unroll
       for (int r = 0; r < kRB; r++) {
         const int64_t slice = gw * kRB + r;
-        const int kd = s[r].ok ? (int)A.kd[s[r].row] : 0;
-        lo[r] = s[r].ok ? (int)(A.kdr[slice] & 0xffffu) + 1 : 0;
+        const int kd = s[r].ok ? (A.dell_w ? A.dell_kd : (int)A.kd[s[r].row]) : 0;
+        lo[r] = s[r].ok ? (A.dell_w ? A.dell_kd : (int)(A.kdr[slice] & 0xffffu)) + 1 : 0;
         hi[r] = s[r].ok ? s[r].w : 1;
         kb[r] = s[r].ok ? kd + 1 : 0;
         ke[r] = s[r].ok ? s[r].w : 0;

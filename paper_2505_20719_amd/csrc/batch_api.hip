@@ -290,6 +290,7 @@ f3r_status f3r_solve_batched(f3r_batch* bt, const double* const* b, double* cons
     in.idx_bits = bt->mats[(size_t)i].A.idx16 ? 16 : 32;
     in.sell_c = 64;
     in.padded_nnz = bt->mats[(size_t)i].padded;
+    in.layout = bt->mats[(size_t)i].A.dell_w ? F3R_LAYOUT_DIAG : F3R_LAYOUT_SELL;
   }
   return worst;
 }

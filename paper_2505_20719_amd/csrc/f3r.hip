@@ -67,6 +67,7 @@ struct f3r_handle {
   uint32_t* off = nullptr;
   void* idx = nullptr;
   uint16_t* kd = nullptr;
+  uint16_t* kd_true = nullptr;  // diagonal-aligned format: true diagonal positions
   uint32_t* kdr = nullptr;
   int32_t* rp = nullptr;  // CSR row pointers, kept for debug read-back
   double* a64 = nullptr;
@@ -171,6 +172,7 @@ f3r_status check_params(const f3r_params* p) {
   if (!(p->alpha > 0.0) || !std::isfinite(p->alpha)) return F3R_ERR_ARG;
   if (p->c < 0 || p->max_outer < 1) return F3R_ERR_ARG;
   if (p->m_identity != 0) return F3R_ERR_ARG;  // M = I is not provided
+  if (p->layout < F3R_LAYOUT_AUTO || p->layout > F3R_LAYOUT_DIAG) return F3R_ERR_ARG;
   if (p->rows_per_lane != 0 && p->rows_per_lane != 1 && p->rows_per_lane != 2 && p->rows_per_lane != 4)
     return F3R_ERR_ARG;
   if (p->entry_chunk != 0) {
@@ -906,6 +908,7 @@ f3r_status outer_solve(f3r_handle* h, const double* b, double* x, double tol, in
       info->probe_ms = h->probe_ms;
       info->probe_launches = h->probe_n;
       info->padded_nnz = h->padded;
+      info->layout = h->A.dell_w ? F3R_LAYOUT_DIAG : F3R_LAYOUT_SELL;
       for (int f = 0; f < 3; f++) {
         info->rows_per_lane[f] = h->kr[f] / 10;
         info->entry_chunk[f] = h->kr[f] % 10;
@@ -1043,6 +1046,7 @@ f3r_status setup_impl(const f3r_csr* A, const f3r_params* p, void* hip_stream, i
     h->off = (uint32_t*)m.A.off;
     h->idx = (void*)m.A.idx;
     h->kd = (uint16_t*)m.A.kd;
+    h->kd_true = m.kd_true;
     h->kdr = (uint32_t*)m.A.kdr;
     h->rp = m.rp;
     h->a64 = m.a64;
@@ -1231,6 +1235,50 @@ f3r_status f3r_debug_spmv(f3r_handle* h, int32_t level, const double* x, double*
   });
 }
 
+f3r_status f3r_time_spmv(f3r_handle* h, int32_t level, int32_t reps, void* scrub,
+                         int64_t scrub_bytes, double* avg_ms) {
+  if (!h || !avg_ms || level < 0 || level >= h->p.nlev || reps < 1 || reps > 10000 ||
+      scrub_bytes < 0 || (scrub_bytes > 0 && !scrub))
+    return F3R_ERR_ARG;
+  if (h->lev[level].cfg.kind != F3R_FGMRES) return F3R_ERR_ARG;
+  return guarded(h, nullptr, [&]() -> f3r_status {
+    HIPCHK(hipSetDevice(h->device));
+    LevelRT& L = h->lev[level];
+    const int64_t n = h->n;
+    // the level's own operands: x = its first Z slot (zeroed), y = V_1
+    const int tx = level == 0 ? T64 : L.zt;
+    const int ty = level == 0 ? T64 : L.pv;
+    const void* av = level == 0 ? (const void*)h->a64 : h->ah[L.pa];
+    const int ta = level == 0 ? T64 : L.pa;
+    void* x = vec_at(L.Z, tx, 0, n);
+    void* y = vec_at(L.V, ty, 1, n);
+    HIPCHK(hipMemsetAsync(x, 0, (size_t)n * tsz(tx), h->st));
+    hipEvent_t e0, e1;
+    HIPCHK(hipEventCreate(&e0));
+    HIPCHK(hipEventCreate(&e1));
+    double total = 0.0;
+    hipError_t err = hipSuccess;
+    for (int r = 0; r < reps && err == hipSuccess; r++) {
+      // evict the matrix from the caches before each timed launch
+      if (scrub_bytes > 0) err = hipMemsetAsync(scrub, r & 0xff, (size_t)scrub_bytes, h->st);
+      if (err == hipSuccess) err = hipEventRecord(e0, h->st);
+      if (err == hipSuccess)
+        err = spmv_dots(h->st, h->A, av, ta, x, tx, nullptr, nullptr, y, ty, nullptr, nullptr, 0,
+                        h->partials, nullptr);
+      if (err == hipSuccess) err = hipEventRecord(e1, h->st);
+      if (err == hipSuccess) err = hipEventSynchronize(e1);
+      float ms = 0.f;
+      if (err == hipSuccess) err = hipEventElapsedTime(&ms, e0, e1);
+      total += ms;
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    HIPCHK(err);
+    *avg_ms = total / reps;
+    return F3R_OK;
+  });
+}
+
 f3r_status f3r_debug_apply_m(f3r_handle* h, int32_t prec, const double* r, double* y) {
   if (!h || !r || !y || !prec_ok(prec)) return F3R_ERR_ARG;
   return guarded(h, nullptr, [&]() -> f3r_status {
@@ -1333,7 +1381,8 @@ f3r_status f3r_debug_level_values(f3r_handle* h, int32_t prec, double* vals_host
   if (!h || !vals_host || !prec_ok(prec) || !h->ah[prec]) return F3R_ERR_ARG;
   return guarded(h, nullptr, [&]() {
     double* d = (double*)h->dalloc((size_t)h->nnz * 8);
-    HIPCHK(sell_to_csr_values(h->st, h->n, h->rp, h->off, h->ah[prec], prec, d));
+    HIPCHK(sell_to_csr_values(h->st, h->n, h->rp, h->off, h->kd_true, h->A.dell_kd, h->ah[prec], prec,
+                              d));
     HIPCHK(hipMemcpyAsync(vals_host, d, (size_t)h->nnz * 8, hipMemcpyDeviceToHost, h->st));
     HIPCHK(hipStreamSynchronize(h->st));
     h->al.release(d);
@@ -1603,6 +1652,7 @@ f3r_status krylov_impl(f3r_handle* h, int method, int prec, const double* b, dou
     info->idx_bits = h->A.idx16 ? 16 : 32;
     info->sell_c = 64;
     info->padded_nnz = h->padded;
+    info->layout = h->A.dell_w ? F3R_LAYOUT_DIAG : F3R_LAYOUT_SELL;
   }
   return status;
 }

@@ -58,6 +58,7 @@ struct MatrixDev {
   bool m_shared = true;       // M values are -ahat (alpha == 1)
   double gd[4] = {1, 1, 1, 1};  // diagonal of G: round_t(1 / alpha)
   double* s = nullptr;        // s_i = 1 / sqrt(|a_ii|)
+  uint16_t* kd_true = nullptr;  // diagonal-aligned format: each row's own diagonal position
 };
 
 // Validates the CSR matrix (host checks first, then the device checks of

@@ -37,6 +37,14 @@ struct SysLayout {
   int64_t dS = 0, dI = 0;
 };
 
+// Diagonal-aligned variant (dell_w > 0): every slice has width dell_w and
+// entry j of row r sits at position dell_kd - (lower entries of r) + j, so
+// the diagonal of every row is at position dell_kd; the positions before a
+// row's first entry and after its last are padding (value 0, the row's own
+// column).  off, kd (= dell_kd) and kdr (= dell_kd | dell_kd << 16) are
+// filled consistently, so code that reads them computes the same sums; the
+// kernels take the widths and bounds from dell_w/dell_kd instead, which
+// removes the dependent loads before the first entry load of a wave.
 struct SellDesc {
   int64_t n = 0, ns = 0;
   const uint32_t* off = nullptr;
@@ -45,6 +53,7 @@ struct SellDesc {
   const uint16_t* kd = nullptr;
   const uint32_t* kdr = nullptr;
   SysLayout sys;
+  int dell_w = 0, dell_kd = 0;
 };
 
 __host__ __device__ inline int64_t n_slices(int64_t n) { return (n + 63) / 64; }

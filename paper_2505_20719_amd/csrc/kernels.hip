@@ -789,10 +789,11 @@ __global__ __launch_bounds__(kBlock) void k_mw(SellDesc A, const TM* __restrict_
   for (int r = 0; r < KR; r++) {
     const int64_t slice = gw * KR + r;
     // loop bound from the slice; the row's own diagonal position only masks
+    // (diagonal-aligned format: every row's diagonal at dell_kd)
     lo[r] = 0;
-    hi[r] = s[r].ok ? max((int)(A.kdr[slice] >> 16), 1) : 1;
+    hi[r] = s[r].ok ? max(A.dell_w ? A.dell_kd : (int)(A.kdr[slice] >> 16), 1) : 1;
     kb[r] = 0;
-    ke[r] = s[r].ok ? (int)A.kd[s[r].row] : 0;
+    ke[r] = s[r].ok ? (A.dell_w ? A.dell_kd : (int)A.kd[s[r].row]) : 0;
     acc[r] = 0;
   }
   Q dg[KR];  // the unit-diagonal term, loaded with the matrix entries
@@ -897,9 +898,9 @@ __global__ __launch_bounds__(kBlock) void k_mg(SellDesc A, const TM* __restrict_
 #pragma unroll
   for (int r = 0; r < KR; r++) {
     const int64_t slice = gw * KR + r;
-    const int kd = s[r].ok ? (int)A.kd[s[r].row] : 0;
+    const int kd = s[r].ok ? (A.dell_w ? A.dell_kd : (int)A.kd[s[r].row]) : 0;
     // loop from just after the slice's smallest diagonal position
-    lo[r] = s[r].ok ? (int)(A.kdr[slice] & 0xffffu) + 1 : 0;
+    lo[r] = s[r].ok ? (A.dell_w ? A.dell_kd : (int)(A.kdr[slice] & 0xffffu)) + 1 : 0;
     hi[r] = s[r].ok ? s[r].w : 1;
     kb[r] = s[r].ok ? kd + 1 : 0;
     ke[r] = s[r].ok ? s[r].w : 0;

@@ -35,7 +35,9 @@ template <> __device__ __forceinline__ int64_t col_of<int32_t>(int32_t d, int64_
 // The KR rows of one lane: row index, first element of the row in the SELL
 // arrays, slice width, and whether the row exists.  A missing row (past n or
 // past the last slice) is pointed at entry 0 of row 0 so that every load it
-// takes part in stays inside the arrays; its sums are never used.
+// takes part in stays inside the arrays; its sums are never used.  In the
+// diagonal-aligned format the position and width follow from the slice
+// index, so no offset load precedes the entry loads.
 struct RowSlot {
   int64_t row;
   uint32_t e0;
@@ -51,13 +53,21 @@ __device__ __forceinline__ void make_slots(const SellDesc& A, int64_t gw, int la
     const int64_t slice = gw * KR + r;
     const bool sok = slice < A.ns;
     const int64_t sl = sok ? slice : 0;
-    const uint32_t o0 = A.off[sl], o1 = A.off[sl + 1];
+    uint32_t o0;
+    int w;
+    if (A.dell_w > 0) {
+      o0 = (uint32_t)(sl * kWave * A.dell_w);
+      w = A.dell_w;
+    } else {
+      o0 = A.off[sl];
+      w = (int)((A.off[sl + 1] - o0) / kWave);
+    }
     const int64_t row = slice * kWave + lane;
     const bool ok = sok && row < A.n;
     s[r].ok = ok;
     s[r].row = ok ? row : 0;
     s[r].e0 = ok ? o0 + (uint32_t)lane : 0u;
-    s[r].w = ok ? (int)((o1 - o0) / kWave) : 0;
+    s[r].w = ok ? w : 0;
   }
 }
 

@@ -21,9 +21,13 @@ hipError_t row_check(hipStream_t st, int64_t n, const int32_t* rp, const int32_t
                      const double* val, double* s, uint16_t* kd, int32_t* len, int* flags);
 
 // width[s] = max row length, kdr[s] = min | max << 16 of the diagonal
-// positions over the rows of slice s
+// positions, upm[s] = max count of entries right of the diagonal, over the
+// rows of slice s
 hipError_t slice_widths(hipStream_t st, int64_t n, const int32_t* len, const uint16_t* kd,
-                        uint32_t* width, uint32_t* kdr);
+                        uint32_t* width, uint32_t* kdr, uint32_t* upm);
+
+// kd[i] = v for every row (diagonal-aligned format)
+hipError_t fill_kd(hipStream_t st, int64_t n, uint16_t* kd, int v);
 
 struct SellOut {
   void* idx = nullptr;          // int16 offsets or int32 columns
@@ -38,15 +42,17 @@ struct SellOut {
 // Scatters every row into the SELL-64 arrays (padding included) and
 // computes ahat = (s_i a_ij) s_j, its rounded copies and the M values
 // W_ij = -ahat_ij / alpha (j < i), G_ij = (-ahat_ij / alpha) / alpha (j > i).
+// dkd >= 0: diagonal-aligned positions (entry j of row i at dkd - kd[i] + j).
 hipError_t to_sell(hipStream_t st, int64_t n, const int32_t* rp, const int32_t* ci,
                    const double* val, const double* s, const uint32_t* off, const int32_t* len,
-                   const SellOut& o, int* flags);
+                   const uint16_t* kd, int dkd, const SellOut& o, int* flags);
 
 // gd = round_t(1 / alpha) for every precision tag, written to out[4]
 hipError_t m_diag(hipStream_t st, double alpha, double* out);
 
-// vals[k] (CSR order, fp64) = SELL value array of type t, for debugging
+// vals[k] (CSR order, fp64) = SELL value array of type t, for debugging;
+// kdt/dkd as in to_sell (kdt = nullptr for the plain layout)
 hipError_t sell_to_csr_values(hipStream_t st, int64_t n, const int32_t* rp, const uint32_t* off,
-                              const void* v, int t, double* out);
+                              const uint16_t* kdt, int dkd, const void* v, int t, double* out);
 
 }  // namespace f3r

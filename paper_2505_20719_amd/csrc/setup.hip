@@ -1,4 +1,5 @@
 // Set-up kernels: one thread per row of the CSR input.
+#include <algorithm>
 #include <vector>
 
 #include "common.h"
@@ -56,25 +57,38 @@ hipError_t row_check(hipStream_t st, int64_t n, const int32_t* rp, const int32_t
 
 __global__ void k_slice_widths(int64_t n, const int32_t* __restrict__ len,
                                const uint16_t* __restrict__ kd, uint32_t* __restrict__ w,
-                               uint32_t* __restrict__ kdr) {
+                               uint32_t* __restrict__ kdr, uint32_t* __restrict__ upm) {
   const int64_t sl = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (sl >= n_slices(n)) return;
-  int32_t m = 0;
+  int32_t m = 0, u = 0;
   int kmax = 0, kmin = 65535;
   for (int64_t r = sl * 64; r < sl * 64 + 64 && r < n; r++) {
     m = len[r] > m ? len[r] : m;
     kmax = kd[r] > kmax ? kd[r] : kmax;
     kmin = kd[r] < kmin ? kd[r] : kmin;
+    const int32_t up = len[r] - 1 - (int32_t)kd[r];
+    u = up > u ? up : u;
   }
   w[sl] = (uint32_t)m;
   kdr[sl] = (uint32_t)kmin | ((uint32_t)kmax << 16);
+  upm[sl] = (uint32_t)u;
 }
 
 hipError_t slice_widths(hipStream_t st, int64_t n, const int32_t* len, const uint16_t* kd,
-                        uint32_t* width, uint32_t* kdr) {
+                        uint32_t* width, uint32_t* kdr, uint32_t* upm) {
   const int64_t ns = n_slices(n);
   hipLaunchKernelGGL(k_slice_widths, dim3((unsigned)((ns + 255) / 256)), dim3(256), 0, st, n, len,
-                     kd, width, kdr);
+                     kd, width, kdr, upm);
+  return hipGetLastError();
+}
+
+__global__ void k_fill_kd(int64_t n, uint16_t* __restrict__ kd, int v) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) kd[i] = (uint16_t)v;
+}
+
+hipError_t fill_kd(hipStream_t st, int64_t n, uint16_t* kd, int v) {
+  hipLaunchKernelGGL(k_fill_kd, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, n, kd, v);
   return hipGetLastError();
 }
 
@@ -90,7 +104,7 @@ template <class T> __device__ __forceinline__ void put(void* p, uint32_t e, doub
 __global__ void k_to_sell(int64_t n, const int32_t* __restrict__ rp, const int32_t* __restrict__ ci,
                           const double* __restrict__ val, const double* __restrict__ s,
                           const uint32_t* __restrict__ off, const int32_t* __restrict__ len,
-                          SellOut o, int* flags) {
+                          const uint16_t* __restrict__ kd, int dkd, SellOut o, int* flags) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   const int64_t sl = i / 64;
@@ -100,12 +114,15 @@ __global__ void k_to_sell(int64_t n, const int32_t* __restrict__ rp, const int32
   const int64_t lo = rp[i];
   const int L = len[i];
   const double si = s[i];
+  // position p holds CSR entry p - shift (padding outside [0, L))
+  const int shift = dkd >= 0 ? dkd - (int)kd[i] : 0;
   int bad = 0;
-  for (int k = 0; k < w; k++) {
-    const uint32_t e = base + (uint32_t)k * 64;
+  for (int p = 0; p < w; p++) {
+    const uint32_t e = base + (uint32_t)p * 64;
+    const int k = p - shift;
     int64_t c = i;
     double a = 0.0, ah = 0.0, mvv = 0.0;
-    if (k < L) {
+    if (k >= 0 && k < L) {
       c = ci[lo + k];
       a = val[lo + k];
       ah = (si * a) * s[c];
@@ -131,9 +148,9 @@ __global__ void k_to_sell(int64_t n, const int32_t* __restrict__ rp, const int32
 
 hipError_t to_sell(hipStream_t st, int64_t n, const int32_t* rp, const int32_t* ci,
                    const double* val, const double* s, const uint32_t* off, const int32_t* len,
-                   const SellOut& o, int* flags) {
+                   const uint16_t* kd, int dkd, const SellOut& o, int* flags) {
   hipLaunchKernelGGL(k_to_sell, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, n, rp, ci, val, s,
-                     off, len, o, flags);
+                     off, len, kd, dkd, o, flags);
   return hipGetLastError();
 }
 
@@ -153,22 +170,24 @@ hipError_t m_diag(hipStream_t st, double alpha, double* out) {
 
 template <class T>
 __global__ void k_sell_to_csr(int64_t n, const int32_t* __restrict__ rp, const uint32_t* __restrict__ off,
-                              const T* __restrict__ v, double* __restrict__ out) {
+                              const uint16_t* __restrict__ kdt, int dkd, const T* __restrict__ v,
+                              double* __restrict__ out) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
+  const int shift = kdt ? dkd - (int)kdt[i] : 0;
   const uint32_t base = off[i / 64] + (uint32_t)(i % 64);
   for (int64_t k = rp[i]; k < rp[i + 1]; k++)
-    out[k] = widen<double>(v[base + (uint32_t)(k - rp[i]) * 64]);
+    out[k] = widen<double>(v[base + (uint32_t)(k - rp[i] + shift) * 64]);
 }
 
 hipError_t sell_to_csr_values(hipStream_t st, int64_t n, const int32_t* rp, const uint32_t* off,
-                              const void* v, int t, double* out) {
+                              const uint16_t* kdt, int dkd, const void* v, int t, double* out) {
   const dim3 g((unsigned)((n + 255) / 256)), b(256);
   switch (t) {
-    case T64: hipLaunchKernelGGL(k_sell_to_csr<double>, g, b, 0, st, n, rp, off, (const double*)v, out); break;
-    case T32: hipLaunchKernelGGL(k_sell_to_csr<float>, g, b, 0, st, n, rp, off, (const float*)v, out); break;
-    case T16: hipLaunchKernelGGL(k_sell_to_csr<f16>, g, b, 0, st, n, rp, off, (const f16*)v, out); break;
-    case TB16: hipLaunchKernelGGL(k_sell_to_csr<bf16>, g, b, 0, st, n, rp, off, (const bf16*)v, out); break;
+    case T64: hipLaunchKernelGGL(k_sell_to_csr<double>, g, b, 0, st, n, rp, off, kdt, dkd, (const double*)v, out); break;
+    case T32: hipLaunchKernelGGL(k_sell_to_csr<float>, g, b, 0, st, n, rp, off, kdt, dkd, (const float*)v, out); break;
+    case T16: hipLaunchKernelGGL(k_sell_to_csr<f16>, g, b, 0, st, n, rp, off, kdt, dkd, (const f16*)v, out); break;
+    case TB16: hipLaunchKernelGGL(k_sell_to_csr<bf16>, g, b, 0, st, n, rp, off, kdt, dkd, (const bf16*)v, out); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
@@ -202,11 +221,14 @@ f3r_status build_matrix(hipStream_t st, const f3r_csr* A, const f3r_params* p, c
   HIPCHK(row_check(st, n, m.rp, ci, val, m.s, kd, len, flags));
   uint32_t* wdev = (uint32_t*)al.get((size_t)ns * 4);
   uint32_t* kdr = (uint32_t*)al.get((size_t)ns * 4);
-  HIPCHK(slice_widths(st, n, len, kd, wdev, kdr));
+  uint32_t* upmd = (uint32_t*)al.get((size_t)ns * 4);
+  HIPCHK(slice_widths(st, n, len, kd, wdev, kdr, upmd));
   int hflags = 0;
   HIPCHK(hipMemcpyAsync(&hflags, flags, sizeof(int), hipMemcpyDeviceToHost, st));
-  std::vector<uint32_t> w((size_t)ns), off((size_t)ns + 1);
+  std::vector<uint32_t> w((size_t)ns), off((size_t)ns + 1), kdrh((size_t)ns), upmh((size_t)ns);
   HIPCHK(hipMemcpyAsync(w.data(), wdev, (size_t)ns * 4, hipMemcpyDeviceToHost, st));
+  HIPCHK(hipMemcpyAsync(kdrh.data(), kdr, (size_t)ns * 4, hipMemcpyDeviceToHost, st));
+  HIPCHK(hipMemcpyAsync(upmh.data(), upmd, (size_t)ns * 4, hipMemcpyDeviceToHost, st));
   HIPCHK(hipStreamSynchronize(st));
   if (hflags & SF_MATRIX) return F3R_ERR_MATRIX;
   if (hflags & SF_LONGROW) return F3R_ERR_ARG;
@@ -217,6 +239,26 @@ f3r_status build_matrix(hipStream_t st, const f3r_csr* A, const f3r_params* p, c
     if (acc >= 0xFFFFFFF0ull) return F3R_ERR_ARG;
   }
   off[(size_t)ns] = (uint32_t)acc;
+  // the diagonal-aligned format: common width KD + 1 + UP over all rows
+  uint32_t dkd = 0, dup = 0;
+  for (int64_t sidx = 0; sidx < ns; sidx++) {
+    dkd = std::max(dkd, kdrh[(size_t)sidx] >> 16);
+    dup = std::max(dup, upmh[(size_t)sidx]);
+  }
+  const uint64_t dw = (uint64_t)dkd + 1 + dup;
+  const uint64_t dacc = (uint64_t)ns * 64 * dw;
+  const bool dfits = dacc < 0xFFFFFFF0ull;
+  bool diag = false;
+  if (p->layout == F3R_LAYOUT_DIAG) {
+    if (!dfits) return F3R_ERR_ARG;
+    diag = true;
+  } else if (p->layout == F3R_LAYOUT_AUTO) {
+    diag = dfits && dacc * 100 <= acc * 103;
+  }
+  if (diag) {
+    for (int64_t sidx = 0; sidx <= ns; sidx++) off[(size_t)sidx] = (uint32_t)((uint64_t)sidx * 64 * dw);
+    acc = dacc;
+  }
   m.padded = (int64_t)acc;
   uint32_t* offd = (uint32_t*)al.get((size_t)(ns + 1) * 4);
   HIPCHK(hipMemcpyAsync(offd, off.data(), (size_t)(ns + 1) * 4, hipMemcpyHostToDevice, st));
@@ -243,7 +285,19 @@ f3r_status build_matrix(hipStream_t st, const f3r_csr* A, const f3r_params* p, c
   for (int t = 0; t < 4; t++)
     if (need[t]) so.ah[t] = al.get((size_t)acc * type_size(t));
   so.range_mask = mask;
-  HIPCHK(to_sell(st, n, m.rp, ci, val, m.s, offd, len, so, flags));
+  HIPCHK(to_sell(st, n, m.rp, ci, val, m.s, offd, len, kd, diag ? (int)dkd : -1, so, flags));
+  uint16_t* kdk = kd;
+  if (diag) {
+    // the kernels see the common diagonal position; the true one is kept
+    // for reading values back in CSR order
+    kdk = (uint16_t*)al.get((size_t)n * 2);
+    HIPCHK(fill_kd(st, n, kdk, (int)dkd));
+    std::fill(kdrh.begin(), kdrh.end(), dkd | (dkd << 16));
+    HIPCHK(hipMemcpyAsync(kdr, kdrh.data(), (size_t)ns * 4, hipMemcpyHostToDevice, st));
+    m.kd_true = kd;
+    m.A.dell_w = (int)dw;
+    m.A.dell_kd = (int)dkd;
+  }
   double* gd = (double*)al.get(4 * sizeof(double));
   HIPCHK(m_diag(st, p->alpha, gd));
   HIPCHK(hipMemcpyAsync(m.gd, gd, 4 * sizeof(double), hipMemcpyDeviceToHost, st));
@@ -260,13 +314,14 @@ f3r_status build_matrix(hipStream_t st, const f3r_csr* A, const f3r_params* p, c
   m.A.off = offd;
   m.A.idx = so.idx;
   m.A.idx16 = so.idx16;
-  m.A.kd = kd;
+  m.A.kd = kdk;
   m.A.kdr = kdr;
   // the CSR copies are no longer needed
   al.release(ci);
   al.release(val);
   al.release(len);
   al.release(wdev);
+  al.release(upmd);
   al.release(flags);
   al.release(gd);
   return F3R_OK;

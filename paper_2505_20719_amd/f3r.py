@@ -24,6 +24,7 @@ USE_X0, PERSIST_WEIGHTS, NO_GRAPH, BATCH_LOCKSTEP = 1, 2, 4, 8
 MAX_LEVELS = 8
 
 OK, NOT_CONVERGED = 0, 1
+LAYOUT_AUTO, LAYOUT_SELL, LAYOUT_DIAG = 0, 1, 2  # device matrix formats
 CG, BICGSTAB = 0, 1  # comparison solvers of Sec. 5
 ERR_ARG, ERR_MATRIX, ERR_RANGE, ERR_NOMEM, ERR_DEVICE, ERR_BREAKDOWN = -1, -2, -3, -4, -5, -6
 
@@ -38,7 +39,7 @@ class Params(C.Structure):
                 ("omega_init", C.c_double), ("max_outer", C.c_int32), ("flags", C.c_uint32),
                 ("poison_call", C.c_int32), ("probe_kernel", C.c_int32),
                 ("rows_per_lane", C.c_int32), ("entry_chunk", C.c_int32),
-                ("reserved", C.c_int32 * 4)]
+                ("layout", C.c_int32), ("reserved", C.c_int32 * 3)]
 
 
 class Csr(C.Structure):
@@ -54,7 +55,8 @@ class Info(C.Structure):
                 ("relres_true", C.c_double), ("setup_ms", C.c_double), ("solve_ms", C.c_double),
                 ("graph_launches", C.c_int64), ("idx_bits", C.c_int32), ("sell_c", C.c_int32),
                 ("probe_ms", C.c_double), ("probe_launches", C.c_int64), ("padded_nnz", C.c_int64),
-                ("rows_per_lane", C.c_int32 * 3), ("entry_chunk", C.c_int32 * 3), ("tune_ms", C.c_double)]
+                ("rows_per_lane", C.c_int32 * 3), ("entry_chunk", C.c_int32 * 3), ("tune_ms", C.c_double),
+                ("layout", C.c_int32), ("reserved_i", C.c_int32)]
 
     def as_dict(self):
         arrays = ("spmv", "rows_per_lane", "entry_chunk")
@@ -81,6 +83,8 @@ EXPORTS = {
                                      C.c_int32, C.c_int32, C.POINTER(Info)]),
     "f3r_krylov_solve": (C.c_int32, [C.c_void_p, C.c_int32, C.c_int32, C.c_void_p, C.c_void_p,
                                      C.c_double, C.c_int32, C.POINTER(Info)]),
+    "f3r_time_spmv": (C.c_int32, [C.c_void_p, C.c_int32, C.c_int32, C.c_void_p, C.c_int64,
+                                  C.POINTER(C.c_double)]),
     "f3r_get_history": (C.c_int32, [C.c_void_p, C.c_int32, C.c_void_p, C.c_int64,
                                     C.POINTER(C.c_int64)]),
     "f3r_get_weights": (C.c_int32, [C.c_void_p, C.c_int32, C.c_void_p, C.POINTER(C.c_int64)]),
@@ -214,6 +218,15 @@ class Solver:
         if st < 0 and raise_on_error:
             raise F3RError(st, "f3r_krylov_solve")
         return x, info
+
+    def time_spmv(self, level, reps=10, scrub=None):
+        """Mean time (ms) of one launch of level `level`'s SpMV; with `scrub`
+        (a device tensor) overwritten before every launch."""
+        ms = C.c_double()
+        ptr = C.c_void_p(scrub.data_ptr()) if scrub is not None else None
+        nb = scrub.numel() * scrub.element_size() if scrub is not None else 0
+        self._check(self.L.f3r_time_spmv(self.h, level, reps, ptr, nb, C.byref(ms)), "time_spmv")
+        return ms.value
 
     def history(self, level=0):
         n = C.c_int64()

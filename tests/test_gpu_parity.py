@@ -53,27 +53,39 @@ MATS = {
 }
 
 
-def pair(name, variant=0):
+# both device formats: SELL (1) and diagonal-aligned (2)
+LAYOUTS = [1, 2]
+
+
+def params_of(variant=0, layout=0):
+    p = P().params_default(variant)
+    p.layout = layout
+    return p
+
+
+def pair(name, variant=0, layout=0):
     A = MATS[name]()
-    print(f"[case] {name} n={A.n} variant={variant}", flush=True)
-    g = P().Solver(A.row_ptr, A.col_idx, A.val, P().params_default(variant))
+    print(f"[case] {name} n={A.n} variant={variant} layout={layout}", flush=True)
+    g = P().Solver(A.row_ptr, A.col_idx, A.val, params_of(variant, layout))
     o = O.Oracle(A.row_ptr, A.col_idx, A.val, O.default_params(ORACLE_VARIANT[variant]))
     return A, g, o
 
 
+@pytest.mark.parametrize("layout", LAYOUTS)
 @pytest.mark.parametrize("name", list(MATS))
-def test_setup_bit_exact(name):
-    A, g, o = pair(name)
+def test_setup_bit_exact(name, layout):
+    A, g, o = pair(name, 0, layout)
     assert np.array_equal(g.debug_scaling(), o.scaling())
     for p in (O.F64, O.F32, O.F16):
         assert np.array_equal(g.debug_level_values(p), o.level_values(p)), p
-    A, g, o = pair(name, 4)
+    A, g, o = pair(name, 4, layout)
     assert np.array_equal(g.debug_level_values(O.BF16), o.level_values(O.BF16))
 
 
+@pytest.mark.parametrize("layout", LAYOUTS)
 @pytest.mark.parametrize("name", list(MATS))
-def test_level_spmv_bit_exact(name):
-    A, g, o = pair(name)
+def test_level_spmv_bit_exact(name, layout):
+    A, g, o = pair(name, 0, layout)
     rs = np.random.default_rng(3)
     x = rs.uniform(-1, 1, A.n)
     assert np.array_equal(host(g.debug_spmv(0, dev(x))), o.spmv(x, scaled=0))
@@ -84,23 +96,34 @@ def test_level_spmv_bit_exact(name):
     assert np.array_equal(host(g.debug_spmv(3, dev(x16))), o.spmv(x16, 1, O.F16, O.F32, O.F32))
 
 
+@pytest.mark.parametrize("layout", LAYOUTS)
 @pytest.mark.parametrize("name", list(MATS))
-def test_m_apply_bit_exact(name):
-    A, g, o = pair(name)
+def test_m_apply_bit_exact(name, layout):
+    A, g, o = pair(name, 0, layout)
     r = np.random.default_rng(4).uniform(-1, 1, A.n)
     r16 = O.round_to(O.F16, r)
     ref16 = o.apply_m(r16, O.F16, O.F32)
     assert np.array_equal(host(g.debug_apply_m(O.F16, dev(r16))), ref16)
     for kr, ch in ((1, 8), (2, 4), (4, 4), (2, 3), (4, 3)):  # every shape the tuner can pick
-        prm = P().params_default(0)
+        prm = params_of(0, layout)
         prm.rows_per_lane, prm.entry_chunk = kr, ch
         gk = P().Solver(A.row_ptr, A.col_idx, A.val, prm)
         assert np.array_equal(host(gk.debug_apply_m(O.F16, dev(r16))), ref16), (kr, ch)
         gk.close()
     r32 = O.round_to(O.F32, r)
     assert np.array_equal(host(g.debug_apply_m(O.F32, dev(r32))), o.apply_m(r32, O.F32, O.F32))
-    A, g, o = pair(name, 2)  # fp64 factors
+    A, g, o = pair(name, 2, layout)  # fp64 factors
     assert np.array_equal(host(g.debug_apply_m(O.F64, dev(r))), o.apply_m(r, O.F64, O.F64))
+    # alpha != 1: M's values stored apart from the matrix, same positions
+    p13 = params_of(0, layout)
+    p13.alpha = 1.3
+    q13 = O.default_params(O.FP16_F3R)
+    q13.alpha = 1.3
+    g13 = P().Solver(A.row_ptr, A.col_idx, A.val, p13)
+    o13 = O.Oracle(A.row_ptr, A.col_idx, A.val, q13)
+    assert np.array_equal(host(g13.debug_apply_m(O.F16, dev(r16))), o13.apply_m(r16, O.F16, O.F32))
+    g13.close()
+    o13.close()
 
 
 @pytest.mark.parametrize("name", ["poisson2d_64", "convdiff_12", "poisson3d_30"])
@@ -185,6 +208,12 @@ def test_end_to_end_poisson2d(variant):
 def test_end_to_end_other_structures(name):
     A, g, o, b, xg, ig, xo, io = _solve_pair(name, 0)
     assert ig.status == 0 and io.status == 0
+    # the other device format gives bitwise the same solve
+    other = P().LAYOUT_SELL if ig.layout == P().LAYOUT_DIAG else P().LAYOUT_DIAG
+    g2 = P().Solver(A.row_ptr, A.col_idx, A.val, params_of(0, other))
+    x2, i2 = g2.solve(dev(b))
+    assert i2.layout == other and np.array_equal(host(x2), xg) and i2.outer_iters == ig.outer_iters
+    g2.close()
     D = A.to_scipy()
     rg = np.linalg.norm(b - D @ xg) / np.linalg.norm(b)
     assert rg < 1e-10
@@ -269,13 +298,16 @@ def test_autotuned_shapes_change_time_not_results():
     A = MATS["poisson3d_30"]()
     xs, b = W.rhs(A, "poisson3d_30")
     ref = None
-    for kr, ch in ((0, 0), (1, 0), (2, 0), (4, 0), (2, 3), (4, 3)):
+    cases = [(kr, ch, lay) for lay in (0, 1, 2) for kr, ch in ((0, 0), (1, 0), (2, 0), (4, 0), (2, 3), (4, 3))]
+    for kr, ch, lay in cases:
         prm = PP.params_default(0)
-        prm.rows_per_lane, prm.entry_chunk = kr, ch
-        print(f"[case] poisson3d_30 rows_per_lane={kr} chunk={ch}", flush=True)
+        prm.rows_per_lane, prm.entry_chunk, prm.layout = kr, ch, lay
+        print(f"[case] poisson3d_30 rows_per_lane={kr} chunk={ch} layout={lay}", flush=True)
         g = PP.Solver(A.row_ptr, A.col_idx, A.val, prm)
         x, info = g.solve(dev(b))
         assert info.status == 0
+        # the automatic choice takes the diagonal-aligned format for this stencil
+        assert info.layout == (lay if lay else PP.LAYOUT_DIAG)
         shapes = list(info.rows_per_lane)
         assert all(v in (1, 2, 4) for v in shapes)
         assert all(c in (3, 4, 8) for c in info.entry_chunk)
@@ -290,9 +322,9 @@ def test_autotuned_shapes_change_time_not_results():
         else:
             assert torch.equal(x, ref[0]) and np.array_equal(g.history(), ref[1])
         g.close()
-    for kr, ch in ((3, 0), (1, 3), (2, 8)):
+    for kr, ch, lay in ((3, 0, 0), (1, 3, 0), (2, 8, 0), (0, 0, 3), (0, 0, -1)):
         bad = PP.params_default(0)
-        bad.rows_per_lane, bad.entry_chunk = kr, ch
+        bad.rows_per_lane, bad.entry_chunk, bad.layout = kr, ch, lay
         with pytest.raises(PP.F3RError):
             PP.Solver(A.row_ptr, A.col_idx, A.val, bad)
 
@@ -313,4 +345,26 @@ def test_kernel_probe_leaves_the_solve_unchanged():
         x1, i1 = g.solve(dev(b), override=ov)
         assert torch.equal(x0, x1) and i1.outer_iters == i0.outer_iters
         assert i1.probe_launches > 0 and i1.probe_launches % 4 == 0 and i1.probe_ms > 0
+    g.close()
+
+
+def test_time_spmv_entry():
+    # the standalone SpMV timer: positive times, the solve unaffected,
+    # Richardson levels and bad arguments rejected
+    import paper_2505_20719_amd as PP
+    A = W.poisson2d(64)
+    b = W.rhs(A, "poisson2d_64")[1]
+    g = PP.Solver(A.row_ptr, A.col_idx, A.val)
+    bt = torch.as_tensor(b, device="cuda")
+    x1, i1 = g.solve(bt)
+    scrub = torch.empty(1 << 20, dtype=torch.float64, device="cuda")
+    print("[case] time_spmv", flush=True)
+    for level in (0, 1, 2):
+        assert g.time_spmv(level, reps=3) > 0.0
+        assert g.time_spmv(level, reps=2, scrub=scrub) > 0.0
+    x2, i2 = g.solve(bt)
+    assert torch.equal(x1, x2) and i1.outer_iters == i2.outer_iters
+    for level, reps in ((3, 1), (4, 1), (-1, 1), (0, 0)):
+        with pytest.raises(PP.F3RError):
+            g.time_spmv(level, reps=reps)
     g.close()
