@@ -77,6 +77,13 @@ template <> __device__ __forceinline__ bool finite_val<float>(float x) { return 
 template <> __device__ __forceinline__ bool finite_val<f16>(f16 x) { return isfinite((float)x); }
 template <> __device__ __forceinline__ bool finite_val<bf16>(bf16 x) { return isfinite(bf16_to_float(x)); }
 
+// A value the compiler must treat as produced at this point (an empty
+// volatile asm that may change it): arithmetic on it cannot move above.
+template <class T> __device__ __forceinline__ T value_barrier(T x) {
+  asm volatile("" : "+v"(x));
+  return x;
+}
+
 // ---- launch geometry -------------------------------------------------------
 // Rows are processed in slices of 64 (one row per lane of a wave64).  Each
 // wave takes kR consecutive slices, so a lane owns kR rows and issues the
@@ -92,6 +99,28 @@ constexpr int kBlock = 256;
 constexpr int kR = 4;
 constexpr int kRowsPerBlock = kBlock * kR;
 constexpr int kXcd = 8;
+
+// index of the calling wave in its block, as a wave-uniform (scalar) value
+__device__ __forceinline__ int wave_index() {
+  return __builtin_amdgcn_readfirstlane((int)(threadIdx.x / kWave));
+}
+
+// A load of a device-resident scalar (flag, weight, scale) that stays a
+// vector load: its index is a per-lane zero the compiler cannot see through.
+// Scalar loads complete out of order, so the wave would wait for such a
+// value as soon as it waits for any scalar operand of its first entry loads;
+// vector loads complete in order and are waited for where they are used.
+template <class T> __device__ __forceinline__ T vload(const T* p) {
+  int z;
+  asm("v_mov_b32 %0, 0" : "=v"(z));
+  return p[z];
+}
+
+// A flag that is never set: a kernel given no flag reads this one, so every
+// flag is read with an unconditional load (a branch around the load would
+// make the wave wait at the branch).
+static __device__ int kNoFlag;
+__device__ __forceinline__ int read_flag(const int* p) { return vload(p ? p : &kNoFlag); }
 
 __device__ __forceinline__ int64_t logical_block(int64_t nb) {
   int64_t per = (nb + kXcd - 1) / kXcd;

@@ -513,30 +513,34 @@ void autotune(f3r_handle* h) {
   const int cand[5] = {18, 24, 44, 23, 43};
   const int ncand = tsz(tr) == 2 ? 5 : 3;
   for (int f = 0; f < 3; f++) {
-    float best = 0.f;
-    for (int c = 0; c < ncand; c++) {
-      const int kr = cand[c];
-      auto launch = [&]() {
-        if (f == 0)
-          HIPCHK(m_apply_w(h->st, At, mv, tm, neg, vec, R.rt, tr, nullptr, nullptr, kr));
-        else if (f == 1)
-          HIPCHK(m_apply_g(h->st, At, mv, tm, neg, gd, R.rr, tr, 2, h->one, R.rz[0], R.rt, tr,
-                           nullptr, nullptr, nullptr, nullptr, kr));
-        else
-          HIPCHK(rich_residual(h->st, At, h->ah[R.pa], R.pa, basis, R.rz[0], R.rt, tr, nullptr, kr));
-      };
-      launch();
-      HIPCHK(hipEventRecord(e0, h->st));
-      for (int i = 0; i < 5; i++) launch();
-      HIPCHK(hipEventRecord(e1, h->st));
-      HIPCHK(hipEventSynchronize(e1));
-      float ms = 0.f;
-      HIPCHK(hipEventElapsedTime(&ms, e0, e1));
-      if (c == 0 || ms < best) {
-        best = ms;
-        h->kr[f] = kr;
+    auto launch = [&](int kr) {
+      if (f == 0)
+        HIPCHK(m_apply_w(h->st, At, mv, tm, neg, vec, R.rt, tr, nullptr, nullptr, kr));
+      else if (f == 1)
+        HIPCHK(m_apply_g(h->st, At, mv, tm, neg, gd, R.rr, tr, 2, h->one, R.rz[0], R.rt, tr,
+                         nullptr, nullptr, nullptr, nullptr, kr));
+      else
+        HIPCHK(rich_residual(h->st, At, h->ah[R.pa], R.pa, basis, R.rz[0], R.rt, tr, nullptr, kr));
+    };
+    // three interleaved rounds; each candidate keeps its best round, so a
+    // slow moment of the device does not decide the shape
+    float best[5] = {0.f, 0.f, 0.f, 0.f, 0.f};
+    for (int c = 0; c < ncand; c++) launch(cand[c]);
+    for (int round = 0; round < 3; round++) {
+      for (int c = 0; c < ncand; c++) {
+        HIPCHK(hipEventRecord(e0, h->st));
+        for (int i = 0; i < 4; i++) launch(cand[c]);
+        HIPCHK(hipEventRecord(e1, h->st));
+        HIPCHK(hipEventSynchronize(e1));
+        float ms = 0.f;
+        HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+        if (round == 0 || ms < best[c]) best[c] = ms;
       }
     }
+    int bc = 0;
+    for (int c = 1; c < ncand; c++)
+      if (best[c] < best[bc]) bc = c;
+    h->kr[f] = cand[bc];
   }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);

@@ -77,10 +77,14 @@ __global__ __launch_bounds__(kBlock) void k_spmv_dots(SellDesc A, const TA* __re
   if (lb >= nb) return;
   const int sy = sys_of(A.sys, lb * kRowsPerBlock);
   stop = sys_ptr(stop, sy, A.sys.dI);
-  if (stop && *stop) return;
+  if (A.sys.blk && stop && *stop) return;  // several systems: finished ones skip their rows
+  // One system: the flags are read while the entry loads are in flight; a
+  // stopped level's blocks then write nothing.
+  const int stopped = read_flag(stop);
   fb = sys_ptr(fb, sy, A.sys.dI);
+  const int fbv = read_flag(fb);
   alt.at_sys(sy, A.sys);
-  const int wave = threadIdx.x / kWave, lane = threadIdx.x & (kWave - 1);
+  const int wave = wave_index(), lane = threadIdx.x & (kWave - 1);
   RowSlot s[kR];
   make_slots(A, lb * 4 + wave, lane, s);
   int kb[kR], ke[kR], kc[kR];
@@ -93,9 +97,13 @@ __global__ __launch_bounds__(kBlock) void k_spmv_dots(SellDesc A, const TA* __re
     acc[r] = 0;
   }
   const TI* idx = (const TI*)A.idx;
-  if (!(fb && *fb)) {
-    rows_sum<kUnroll, TI>(av, idx, s, kb, kc, kb, ke, acc, LdVec<TX, Q>{x});
-  } else {
+  rows_sum<kUnroll, TI>(av, idx, s, kb, kc, kb, ke, acc, LdVec<TX, Q>{x});
+  if (fbv) {
+    // rare: the input was non-finite and is replaced by the level's input
+    // basis; the sums are formed again from it (the flag is read only here,
+    // so the common pass never waits for it)
+#pragma unroll
+    for (int r = 0; r < kR; r++) acc[r] = 0;
     alt.init();
     rows_sum<kUnroll, TI>(av, idx, s, kb, kc, kb, ke, acc, alt);
   }
@@ -103,7 +111,7 @@ __global__ __launch_bounds__(kBlock) void k_spmv_dots(SellDesc A, const TA* __re
 #pragma unroll
   for (int r = 0; r < kR; r++) {
     const TY yr = round_to<TY>(acc[r]);
-    if (s[r].ok) y[s[r].row] = yr;
+    if (s[r].ok && !stopped) y[s[r].row] = yr;
     yv[r] = s[r].ok ? widen<Q>(yr) : Q(0);
   }
   for (int c0 = 0; c0 < nv; c0 += kDotChunk) {
@@ -129,7 +137,7 @@ __global__ __launch_bounds__(kBlock) void k_spmv_dots(SellDesc A, const TA* __re
       }
     }
     __syncthreads();
-    if ((int)threadIdx.x < cn) {
+    if ((int)threadIdx.x < cn && !stopped) {
       const int t = threadIdx.x;
       Q sum = lds[0][t];
       sum = sum + lds[1][t];
@@ -230,7 +238,8 @@ __global__ __launch_bounds__(kBlock) void k_axpy_norm(SysLayout sl, int64_t n, T
   if (lb >= nb) return;
   const int sy = sys_of(sl, lb * kRowsPerBlock);
   stop = sys_ptr(stop, sy, sl.dI);
-  if (stop && *stop) return;
+  if (sl.blk && stop && *stop) return;
+  const int stopped = read_flag(stop);  // checked at the stores (one system)
   h = sys_ptr(h, sy, sl.dS);
   scales = sys_ptr(scales, sy, sl.dS);
   int64_t row[kR];
@@ -268,12 +277,12 @@ __global__ __launch_bounds__(kBlock) void k_axpy_norm(SysLayout sl, int64_t n, T
 #pragma unroll
   for (int r = 0; r < kR; r++) {
     const TY wr = round_to<TY>(acc[r]);
-    if (ok[r]) w[row[r]] = wr;
+    if (ok[r] && !stopped) w[row[r]] = wr;
     const Q q = ok[r] ? widen<Q>(wr) : Q(0);
     sq = sq + q * q;
   }
   const Q tot = block_sum(sq, lds);
-  if (threadIdx.x == 0) part[lb] = tot;
+  if (threadIdx.x == 0 && !stopped) part[lb] = tot;
 }
 
 hipError_t axpy_norm(hipStream_t st, const SysLayout& sl, int64_t n, void* w, int tw, const void* v0,
@@ -653,7 +662,7 @@ __global__ __launch_bounds__(kBlock) void k_residual64(SellDesc A, const double*
   __shared__ double lds[kBlock / kWave];
   const int64_t lb = logical_block(nb);
   if (lb >= nb) return;
-  const int wave = threadIdx.x / kWave, lane = threadIdx.x & (kWave - 1);
+  const int wave = wave_index(), lane = threadIdx.x & (kWave - 1);
   RowSlot s[kR];
   make_slots(A, lb * 4 + wave, lane, s);
   int kb[kR], ke[kR], kc[kR];
@@ -776,8 +785,9 @@ __global__ __launch_bounds__(kBlock) void k_mw(SellDesc A, const TM* __restrict_
   if (lb >= nb) return;
   const int sy = sys_of(A.sys, lb * (kBlock * KR));
   stop = sys_ptr(stop, sy, A.sys.dI);
-  if (stop && *stop) return;
-  const int wave = threadIdx.x / kWave, lane = threadIdx.x & (kWave - 1);
+  if (A.sys.blk && stop && *stop) return;
+  const int stopped = read_flag(stop);  // checked at the stores (one system)
+  const int wave = wave_index(), lane = threadIdx.x & (kWave - 1);
   const int64_t gw = lb * 4 + wave;
   RowSlot s[KR];
   make_slots(A, gw, lane, s);
@@ -796,13 +806,13 @@ __global__ __launch_bounds__(kBlock) void k_mw(SellDesc A, const TM* __restrict_
     ke[r] = s[r].ok ? (A.dell_w ? A.dell_kd : (int)A.kd[s[r].row]) : 0;
     acc[r] = 0;
   }
-  Q dg[KR];  // the unit-diagonal term, loaded with the matrix entries
+  typename LD::raw_t dg[KR];  // the unit-diagonal term, loaded with the matrix entries
 #pragma unroll
-  for (int r = 0; r < KR; r++) dg[r] = ld(s[r].row);
+  for (int r = 0; r < KR; r++) dg[r] = ld.raw(s[r].row);
   rows_sum<U, TI>(mv, (const TI*)A.idx, s, lo, hi, kb, ke, acc, ld, neg != 0);
 #pragma unroll
   for (int r = 0; r < KR; r++)
-    if (s[r].ok) t[s[r].row] = round_to<TT>(acc[r] + dg[r]);
+    if (s[r].ok && !stopped) t[s[r].row] = round_to<TT>(acc[r] + ld.cook(dg[r]));
 }
 
 // Epilogues of the G sweep.  prefetch(k, row) issues the row-local loads of
@@ -827,7 +837,7 @@ template <class TT, class Q> struct EpiZ1 {
     wp = sys_ptr(wp, sy, sl.dS);
     fb = sys_ptr(fb, sy, sl.dI);
   }
-  __device__ __forceinline__ void init() { w = (Q)(*wp); }
+  __device__ __forceinline__ void init() { w = (Q)vload(wp); }
   __device__ __forceinline__ void prefetch(int, int64_t) {}
   __device__ __forceinline__ void operator()(int, int64_t r, TT y) const {
     const TT z = round_to<TT>(w * widen<Q>(y));
@@ -841,15 +851,15 @@ template <class TT, class Q> struct EpiZK {
   const double* wp;
   int* fb;
   Q w;
-  Q zv[4];  // one per row of the lane (at most four)
+  TT zv[4];  // one per row of the lane (at most four), converted when used
   __device__ __forceinline__ void at_sys(int sy, const SysLayout& sl) {
     wp = sys_ptr(wp, sy, sl.dS);
     fb = sys_ptr(fb, sy, sl.dI);
   }
-  __device__ __forceinline__ void init() { w = (Q)(*wp); }
-  __device__ __forceinline__ void prefetch(int k, int64_t r) { zv[k] = widen<Q>(zp[r]); }
+  __device__ __forceinline__ void init() { w = (Q)vload(wp); }
+  __device__ __forceinline__ void prefetch(int k, int64_t r) { zv[k] = zp[r]; }
   __device__ __forceinline__ void operator()(int k, int64_t r, TT y) const {
-    const TT z = round_to<TT>(zv[k] + w * widen<Q>(y));
+    const TT z = round_to<TT>(widen<Q>(zv[k]) + w * widen<Q>(y));
     out[r] = z;
     if (fb && !finite_val(z)) atomicOr(fb, 1);
   }
@@ -886,14 +896,16 @@ __global__ __launch_bounds__(kBlock) void k_mg(SellDesc A, const TM* __restrict_
   if (lb >= nb) return;
   const int sy = sys_of(A.sys, lb * (kBlock * KR));
   stop = sys_ptr(stop, sy, A.sys.dI);
-  if (stop && *stop) return;
-  const int wave = threadIdx.x / kWave, lane = threadIdx.x & (kWave - 1);
+  if (A.sys.blk && stop && *stop) return;
+  const int stopped = read_flag(stop);  // checked at the stores (one system)
+  const int wave = wave_index(), lane = threadIdx.x & (kWave - 1);
   const int64_t gw = lb * 4 + wave;
   RowSlot s[KR];
   make_slots(A, gw, lane, s);
   epi.at_sys(sy, A.sys);
   epi.init();
   int lo[KR], hi[KR], kb[KR], ke[KR];
+  TT traw[KR];
   Q acc[KR];
 #pragma unroll
   for (int r = 0; r < KR; r++) {
@@ -904,13 +916,18 @@ __global__ __launch_bounds__(kBlock) void k_mg(SellDesc A, const TM* __restrict_
     hi[r] = s[r].ok ? s[r].w : 1;
     kb[r] = s[r].ok ? kd + 1 : 0;
     ke[r] = s[r].ok ? s[r].w : 0;
-    acc[r] = gd * widen<Q>(t[s[r].row]);
+    traw[r] = t[s[r].row];
     epi.prefetch(r, s[r].row);
   }
-  rows_sum<U, TI>(mv, (const TI*)A.idx, s, lo, hi, kb, ke, acc, LdVec<TT, Q>{t}, neg != 0);
+  // the sums start from gd t_i, formed once the first entry loads are out
+  rows_sum<U, TI>(mv, (const TI*)A.idx, s, lo, hi, kb, ke, acc, LdVec<TT, Q>{t}, neg != 0,
+                  [&](Q (&a)[KR]) {
+#pragma unroll
+                    for (int r = 0; r < KR; r++) a[r] = gd * value_barrier(widen<Q>(traw[r]));
+                  });
 #pragma unroll
   for (int r = 0; r < KR; r++)
-    if (s[r].ok) epi(r, s[r].row, round_to<TT>(acc[r]));
+    if (s[r].ok && !stopped) epi(r, s[r].row, round_to<TT>(acc[r]));
 }
 
 template <class TM, class TT> constexpr bool ok_m() {
@@ -1024,8 +1041,9 @@ __global__ __launch_bounds__(kBlock) void k_rres(SellDesc A, const TA* __restric
   if (lb >= nb) return;
   const int sy = sys_of(A.sys, lb * (kBlock * KR));
   stop = sys_ptr(stop, sy, A.sys.dI);
-  if (stop && *stop) return;
-  const int wave = threadIdx.x / kWave, lane = threadIdx.x & (kWave - 1);
+  if (A.sys.blk && stop && *stop) return;
+  const int stopped = read_flag(stop);  // checked at the stores (one system)
+  const int wave = wave_index(), lane = threadIdx.x & (kWave - 1);
   RowSlot s[KR];
   make_slots(A, lb * 4 + wave, lane, s);
   ld.at_sys(sy, A.sys);
@@ -1039,13 +1057,13 @@ __global__ __launch_bounds__(kBlock) void k_rres(SellDesc A, const TA* __restric
     kc[q] = max(s[q].w, 1);
     acc[q] = 0;
   }
-  Q vr[KR];  // v at the row, loaded with the matrix entries
+  typename LD::raw_t vr[KR];  // v at the row, loaded with the matrix entries
 #pragma unroll
-  for (int q = 0; q < KR; q++) vr[q] = ld(s[q].row);
+  for (int q = 0; q < KR; q++) vr[q] = ld.raw(s[q].row);
   rows_sum<U, TI>(av, (const TI*)A.idx, s, kb, kc, kb, ke, acc, LdVec<TR, Q>{z});
 #pragma unroll
   for (int q = 0; q < KR; q++)
-    if (s[q].ok) r[s[q].row] = round_to<TR>(vr[q] - acc[q]);
+    if (s[q].ok && !stopped) r[s[q].row] = round_to<TR>(ld.cook(vr[q]) - acc[q]);
 }
 
 hipError_t rich_residual(hipStream_t st, const SellDesc& A, const void* av, int ta,
@@ -1091,7 +1109,7 @@ __global__ __launch_bounds__(kBlock) void k_rtdots(SellDesc A, const TA* __restr
   const int sy = sys_of(A.sys, lb * kRowsPerBlock);
   stop = sys_ptr(stop, sy, A.sys.dI);
   if (stop && *stop) return;
-  const int wave = threadIdx.x / kWave, lane = threadIdx.x & (kWave - 1);
+  const int wave = wave_index(), lane = threadIdx.x & (kWave - 1);
   RowSlot s[kR];
   make_slots(A, lb * 4 + wave, lane, s);
   rld.at_sys(sy, A.sys);

@@ -45,29 +45,39 @@ struct RowSlot {
   bool ok;
 };
 
+// gw (the wave's group of KR slices) is wave-uniform, so the offsets are
+// scalar loads, issued together.
 template <int KR>
 __device__ __forceinline__ void make_slots(const SellDesc& A, int64_t gw, int lane,
                                            RowSlot (&s)[KR]) {
+  uint32_t o0[KR];
+  int w[KR];
+  if (A.dell_w > 0) {
+#pragma unroll
+    for (int r = 0; r < KR; r++) {
+      const int64_t slice = gw * KR + r;
+      const int64_t sl = slice < A.ns ? slice : 0;
+      o0[r] = (uint32_t)(sl * kWave * A.dell_w);
+      w[r] = A.dell_w;
+    }
+  } else {
+#pragma unroll
+    for (int r = 0; r < KR; r++) {
+      const int64_t slice = gw * KR + r;
+      const int64_t sl = slice < A.ns ? slice : 0;
+      o0[r] = A.off[sl];
+      w[r] = (int)((A.off[sl + 1] - o0[r]) / kWave);
+    }
+  }
 #pragma unroll
   for (int r = 0; r < KR; r++) {
     const int64_t slice = gw * KR + r;
-    const bool sok = slice < A.ns;
-    const int64_t sl = sok ? slice : 0;
-    uint32_t o0;
-    int w;
-    if (A.dell_w > 0) {
-      o0 = (uint32_t)(sl * kWave * A.dell_w);
-      w = A.dell_w;
-    } else {
-      o0 = A.off[sl];
-      w = (int)((A.off[sl + 1] - o0) / kWave);
-    }
     const int64_t row = slice * kWave + lane;
-    const bool ok = sok && row < A.n;
+    const bool ok = slice < A.ns && row < A.n;
     s[r].ok = ok;
     s[r].row = ok ? row : 0;
-    s[r].e0 = ok ? o0 + (uint32_t)lane : 0u;
-    s[r].w = ok ? w : 0;
+    s[r].e0 = ok ? o0[r] + (uint32_t)lane : 0u;
+    s[r].w = ok ? w[r] : 0;
   }
 }
 
@@ -80,16 +90,28 @@ __device__ __forceinline__ void make_slots(const SellDesc& A, int64_t gw, int la
 // then the sums, whose predicate is a select.  No load sits behind a branch,
 // so a wave keeps KR x U entries in flight; the order of the sums of a row
 // (and so its rounding) is that of the definition.
-template <int U, class TI, class TV, class Q, class XF, int KR>
+//
+// init(acc), when given, sets the starting values of the sums inside the
+// first iteration, after its loads are issued: a starting value computed
+// before the loop makes the wave wait for its operands before the loop's
+// first load (init must keep its arithmetic from being hoisted out of the
+// loop; value_barrier does that).  The first iteration always runs (its
+// clamped loads stay inside the arrays; its sums are masked when the range
+// is empty).
+struct NoInit {
+  template <class A> __device__ __forceinline__ void operator()(A&) const {}
+};
+template <int U, class TI, class TV, class Q, class XF, int KR, class INIT = NoInit>
 __device__ __forceinline__ void rows_sum(const TV* __restrict__ val, const TI* __restrict__ idx,
                                          const RowSlot (&s)[KR], const int (&lo)[KR],
                                          const int (&hi)[KR], const int (&kb)[KR],
                                          const int (&ke)[KR], Q (&acc)[KR], const XF& x,
-                                         bool neg = false) {
+                                         bool neg = false, const INIT& init = INIT()) {
   int it = 0;
 #pragma unroll
   for (int r = 0; r < KR; r++) it = max(it, hi[r] - lo[r]);
-  for (int i0 = 0; i0 < it; i0 += U) {
+  int i0 = 0;
+  do {
     TV v[KR][U];
     TI d[KR][U];
 #pragma unroll
@@ -107,6 +129,7 @@ __device__ __forceinline__ void rows_sum(const TV* __restrict__ val, const TI* _
 #pragma unroll
       for (int u = 0; u < U; u++) xv[r][u] = x(col_of<TI>(d[r][u], s[r].row));
     }
+    if (i0 == 0) init(acc);
 #pragma unroll
     for (int r = 0; r < KR; r++) {
 #pragma unroll
@@ -118,7 +141,8 @@ __device__ __forceinline__ void rows_sum(const TV* __restrict__ val, const TI* _
         acc[r] = (k >= kb[r] && k < ke[r]) ? t : acc[r];
       }
     }
-  }
+    i0 += U;
+  } while (i0 < it);
 }
 
 constexpr int kUnroll = 4;
@@ -126,10 +150,16 @@ constexpr int kUnroll = 4;
 // ---------------------------------------------------------------------------
 // vector loaders (value of entry c as the consumer's arithmetic type Q)
 // ---------------------------------------------------------------------------
+// raw(c) loads what entry c needs and cook(raw) converts it; a kernel that
+// uses the row's own value after its sums loads it with raw() first and
+// converts it at the end, so nothing waits for it before the entry loads.
 template <class TT, class Q> struct LdVec {
+  using raw_t = TT;
   const TT* p;
   __device__ __forceinline__ void at_sys(int, const SysLayout&) {}
   __device__ __forceinline__ void init() {}
+  __device__ __forceinline__ raw_t raw(int64_t c) const { return p[c]; }
+  __device__ __forceinline__ Q cook(raw_t v) const { return widen<Q>(v); }
   __device__ __forceinline__ Q operator()(int64_t c) const { return widen<Q>(p[c]); }
 };
 
@@ -139,6 +169,7 @@ template <class TT, class Q> struct LdVec {
 // fp64, so this is the fp32 product, and no conversion waits for the scale
 // load before the matrix loads are issued.
 template <class TIN, class TT, class Q> struct LdBasis {
+  using raw_t = TIN;
   const TIN* p;
   const double* scp;
   const int* cur;
@@ -150,19 +181,25 @@ template <class TIN, class TT, class Q> struct LdBasis {
     cur = sys_ptr(cur, sy, sl.dI);
   }
   __device__ __forceinline__ void init() {
-    int64_t j = cur ? *cur : 0;
+    int64_t j = cur ? vload(cur) : 0;
     p += j * stride;
-    sc = scp[j];
+    sc = vload(scp + j);
   }
-  __device__ __forceinline__ Q operator()(int64_t c) const {
-    const Q v = (Q)(widen<double>(p[c]) * sc);
+  __device__ __forceinline__ raw_t raw(int64_t c) const { return p[c]; }
+  __device__ __forceinline__ Q cook(raw_t r) const {
+    const Q v = (Q)(widen<double>(r) * sc);
     return widen<Q>(round_to<TT>(v));
   }
+  __device__ __forceinline__ Q operator()(int64_t c) const { return cook(p[c]); }
 };
 
 // round_to<TT>(s_c * (raw_c * sc)) with fp64 products (outermost -> scaled
 // inner system, P(v) = S F(S v))
+struct SRaw {
+  double v, s;
+};
 template <class TT, class Q> struct LdSBasis {
+  using raw_t = SRaw;
   const double* p;
   const double* scp;
   const double* s;
@@ -174,14 +211,16 @@ template <class TT, class Q> struct LdSBasis {
     cur = sys_ptr(cur, sy, sl.dI);
   }
   __device__ __forceinline__ void init() {
-    int64_t j = cur ? *cur : 0;
+    int64_t j = cur ? vload(cur) : 0;
     p += j * stride;
-    sc = scp[j];
+    sc = vload(scp + j);
   }
-  __device__ __forceinline__ Q operator()(int64_t c) const {
-    double v = s[c] * (p[c] * sc);
+  __device__ __forceinline__ raw_t raw(int64_t c) const { return SRaw{p[c], s[c]}; }
+  __device__ __forceinline__ Q cook(raw_t r) const {
+    double v = r.s * (r.v * sc);
     return widen<Q>(round_to<TT>(v));
   }
+  __device__ __forceinline__ Q operator()(int64_t c) const { return cook(raw(c)); }
 };
 
 // j-th vector of a level basis (V_0 separate, V_j = vb + (j-1) n), used by
