@@ -70,23 +70,47 @@ def measured_traffic(kernel: str, workload: str):
     return int(m.group(1))
 
 
-def algorithmic_bytes(A, idx_bits: int):
-    """Bytes each probed kernel must move per launch (the data structure it
-    reads once and the vectors it reads/writes once), fp16 level storage."""
+def survey_bytes(A):
+    """Algorithmic bytes per launch by the per-unit figures of the hot-path
+    scope table (CSR with 4-byte column indices and row pointers; fp16
+    values and Richardson vectors, fp32 level-2 vectors; each vector read
+    once): SpMV nnz (s_A + 4) + 4 (n + 1) + n s_x + n s_y; one M sweep
+    (nnz + n) / 2 (s_M + 4) + 4 n + its vectors (W sweep: input, 3 bytes on
+    average over the fp32 basis and the fp16 residual, and t; G sweep: t and
+    z); the Richardson residual adds the read of v (fp32 basis); the level-2
+    SpMV adds its Gram-Schmidt dots, (j + 1) n s with j + 1 = 2.5 on
+    average."""
+    n, nnz = A.n, A.nnz
+    sweep = (nnz + n) / 2.0 * (2 + 4) + 4.0 * n
+    spmv16 = nnz * (2 + 4) + 4.0 * (n + 1)
+    return {
+        "m_lower": sweep + n * (3 + 2),
+        "m_upper": sweep + n * (2 + 2),
+        "r_residual": spmv16 + n * 2 + n * 2 + n * 4,
+        "spmv_l2": spmv16 + n * 2 + n * 4 + 2.5 * n * 4,
+    }
+
+
+def algorithmic_bytes(A, idx_bits: int, diag: bool):
+    """Bytes each probed kernel must move per launch in the device format (the
+    data structure it reads once and the vectors it reads/writes once), fp16
+    level storage; the diagonal-aligned format reads neither the per-row
+    diagonal positions nor the slice offsets."""
     n = A.n
     nnz = A.nnz
     rows = np.repeat(np.arange(n), np.diff(A.row_ptr))
     nl = int(np.count_nonzero(A.col_idx < rows))
     nu = int(np.count_nonzero(A.col_idx > rows))
     sv, si = 2, idx_bits // 8
-    off = n / 16.0  # one 4-byte slice offset per 64 rows
+    off = 0.0 if diag else n / 16.0  # one 4-byte slice offset per 64 rows
+    kdb = 0 if diag else 2  # diagonal positions, 2 bytes per row
     return {
         # W sweep: kd (2n), lower entries, input (fp32 basis at k=1, fp16 r
         # at k=2: 3n on average), t written (2n)
-        "m_lower": 7 * n + (sv + si) * nl + off,
+        "m_lower": (5 + kdb) * n + (sv + si) * nl + off,
         # G sweep + update: kd, upper entries, t (2n), z written (2n), z_prev
         # read at k=2 only (n on average)
-        "m_upper": 7 * n + (sv + si) * nu + off,
+        "m_upper": (5 + kdb) * n + (sv + si) * nu + off,
         # r = v - A z: all entries, z (2n), fp32 basis (4n), r written (2n)
         "r_residual": 8 * n + (sv + si) * nnz + off,
         # level-2 SpMV + dots: all entries, z (2n), w written (4n), 2.5 fp32
@@ -373,7 +397,8 @@ def main():
 
     # live per-kernel timing of the hot kernels inside one solve (HIP events
     # on the solve's stream, direct launches)
-    ab = algorithmic_bytes(A, info16.idx_bits)
+    ab = algorithmic_bytes(A, info16.idx_bits, info16.layout == P.LAYOUT_DIAG)
+    sb = survey_bytes(A)
     probes = {"m_lower": P.PROBE_M_LOWER, "m_upper": P.PROBE_M_UPPER,
               "r_residual": P.PROBE_R_RESIDUAL, "spmv_l2": P.PROBE_SPMV_L2}
     kern = {}
@@ -383,15 +408,21 @@ def main():
         _, ip = s16.solve(bt, tol=tol, override=ov)
         avg_ms = ip.probe_ms / max(ip.probe_launches, 1)
         kern[key] = {"total_ms": ip.probe_ms, "launches": ip.probe_launches, "avg_us": avg_ms * 1e3,
-                     "gbs": ab[key] / (avg_ms * 1e-3) / 1e9}
+                     "gbs": sb[key] / (avg_ms * 1e-3) / 1e9,
+                     "gbs_format": ab[key] / (avg_ms * 1e-3) / 1e9}
         log(f"[bench] probe {key}: {ip.probe_launches} launches, avg {avg_ms * 1e3:.2f} us, "
-            f"{kern[key]['gbs']:.0f} GB/s (algorithmic {ab[key] / 1e6:.1f} MB/launch)")
+            f"{kern[key]['gbs']:.0f} GB/s ({sb[key] / 1e6:.1f} MB/launch); "
+            f"format bytes {ab[key] / 1e6:.1f} MB: {kern[key]['gbs_format']:.0f} GB/s")
     dom = max(kern, key=lambda k: kern[k]["launches"] * kern[k]["avg_us"])
     achieved = kern[dom]["gbs"]
     traffic = measured_traffic(dom, name)
     roofline = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
-                "bytes_per_launch": int(ab[dom]), "avg_launch_us": round(kern[dom]["avg_us"], 3)}
+                "bytes_per_launch": int(sb[dom]), "avg_launch_us": round(kern[dom]["avg_us"], 3),
+                # the same launch priced by the bytes the device format must move
+                "format_bytes_per_launch": int(ab[dom]),
+                "achieved_format": round(kern[dom]["gbs_format"], 1),
+                "frac_format": round(kern[dom]["gbs_format"] / HBM_PEAK_GBS, 4)}
     result_cfg["kernels"] = {k: {kk: round(vv, 3) if isinstance(vv, float) else vv for kk, vv in v.items()}
                              for k, v in kern.items()}
     # standalone level SpMVs, warm (back to back) and cold (a 1 GiB buffer

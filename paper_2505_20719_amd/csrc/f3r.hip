@@ -173,8 +173,10 @@ f3r_status check_params(const f3r_params* p) {
   if (p->c < 0 || p->max_outer < 1) return F3R_ERR_ARG;
   if (p->m_identity != 0) return F3R_ERR_ARG;  // M = I is not provided
   if (p->layout < F3R_LAYOUT_AUTO || p->layout > F3R_LAYOUT_DIAG) return F3R_ERR_ARG;
-  if (p->rows_per_lane != 0 && p->rows_per_lane != 1 && p->rows_per_lane != 2 && p->rows_per_lane != 4)
+  if (p->rows_per_lane != -1 && p->rows_per_lane != 0 && p->rows_per_lane != 1 &&
+      p->rows_per_lane != 2 && p->rows_per_lane != 4)
     return F3R_ERR_ARG;
+  if (p->entry_chunk != 0 && p->rows_per_lane <= 0) return F3R_ERR_ARG;
   if (p->entry_chunk != 0) {
     const int code = 10 * p->rows_per_lane + p->entry_chunk;
     const int plast = p->lev[p->nlev - 1].prec_v;
@@ -477,12 +479,35 @@ void enqueue_fgmres(Ctx& c, int d, const Basis& vin, const void* alias_raw, cons
 // changes only the time, never a result.
 void autotune(f3r_handle* h) {
   const int fixed = h->p.rows_per_lane;
-  if (fixed) {
+  if (fixed > 0) {
     const int code = h->p.entry_chunk ? 10 * fixed + h->p.entry_chunk : fixed == 1 ? 18 : fixed == 2 ? 24 : 44;
     h->kr[0] = h->kr[1] = h->kr[2] = code;
     return;
   }
   if (h->rich < 0) return;
+  if (fixed == 0) {
+    // Rule from measurements of whole solves (stencils with 3-13 entries
+    // per half row, elasticity with 41): rows with at most four entries on
+    // a side of the diagonal take two rows per lane and one chunk for the
+    // side (three entries with narrow vectors), longer rows one row per
+    // lane and chunks of eight; the residual sweeps whole rows, one per
+    // lane, chunks of eight.  Timing the candidates at set-up (-1) measures
+    // them on warm caches, which the solve does not see.
+    const LevelRT& R = h->lev[h->rich];
+    const bool narrow = tsz(R.pv) == 2;
+    int lower, upper;
+    if (h->A.dell_w) {
+      lower = h->A.dell_kd;
+      upper = h->A.dell_w - 1 - h->A.dell_kd;
+    } else {
+      lower = upper = (int)((h->padded / std::max<int64_t>(h->n, 1) - 1) / 2);
+    }
+    auto pick = [&](int side) { return side <= 3 && narrow ? 23 : side <= 4 ? 24 : 18; };
+    h->kr[0] = pick(lower);
+    h->kr[1] = pick(upper);
+    h->kr[2] = 18;
+    return;
+  }
   const double t0 = now_ms();
   LevelRT& R = h->lev[h->rich];
   const int tr = R.pv;
@@ -514,16 +539,18 @@ void autotune(f3r_handle* h) {
   const int ncand = tsz(tr) == 2 ? 5 : 3;
   for (int f = 0; f < 3; f++) {
     auto launch = [&](int kr) {
-      if (f == 0)
+      if (f == 0) {
+        // the two W sweeps of a Richardson call: from the level's input
+        // basis (wider, scaled) and from the residual
+        HIPCHK(m_apply_w(h->st, At, mv, tm, neg, basis, R.rt, tr, nullptr, nullptr, kr));
         HIPCHK(m_apply_w(h->st, At, mv, tm, neg, vec, R.rt, tr, nullptr, nullptr, kr));
-      else if (f == 1)
+      } else if (f == 1)
         HIPCHK(m_apply_g(h->st, At, mv, tm, neg, gd, R.rr, tr, 2, h->one, R.rz[0], R.rt, tr,
                          nullptr, nullptr, nullptr, nullptr, kr));
       else
         HIPCHK(rich_residual(h->st, At, h->ah[R.pa], R.pa, basis, R.rz[0], R.rt, tr, nullptr, kr));
     };
-    // three interleaved rounds; each candidate keeps its best round, so a
-    // slow moment of the device does not decide the shape
+    // three interleaved rounds; each candidate keeps its best round
     float best[5] = {0.f, 0.f, 0.f, 0.f, 0.f};
     for (int c = 0; c < ncand; c++) launch(cand[c]);
     for (int round = 0; round < 3; round++) {

@@ -293,12 +293,14 @@ def test_poisoned_richardson_output_falls_back_like_the_oracle():
 
 def test_autotuned_shapes_change_time_not_results():
     # every rows-per-lane shape of the M sweeps and the Richardson residual,
-    # fixed or picked by the set-up timing, gives bitwise the same solve
+    # fixed, picked by the row-length rule (0) or by set-up timing (-1),
+    # gives bitwise the same solve
     PP = P()
     A = MATS["poisson3d_30"]()
     xs, b = W.rhs(A, "poisson3d_30")
     ref = None
-    cases = [(kr, ch, lay) for lay in (0, 1, 2) for kr, ch in ((0, 0), (1, 0), (2, 0), (4, 0), (2, 3), (4, 3))]
+    cases = [(kr, ch, lay) for lay in (0, 1, 2)
+             for kr, ch in ((0, 0), (-1, 0), (1, 0), (2, 0), (4, 0), (2, 3), (4, 3))]
     for kr, ch, lay in cases:
         prm = PP.params_default(0)
         prm.rows_per_lane, prm.entry_chunk, prm.layout = kr, ch, lay
@@ -311,10 +313,14 @@ def test_autotuned_shapes_change_time_not_results():
         shapes = list(info.rows_per_lane)
         assert all(v in (1, 2, 4) for v in shapes)
         assert all(c in (3, 4, 8) for c in info.entry_chunk)
-        if kr:
+        if kr > 0:
             assert shapes == [kr] * 3 and info.tune_ms == 0.0
             if ch:
                 assert list(info.entry_chunk) == [ch] * 3
+        elif kr == 0:
+            # 7-point stencil: three entries on each side of the diagonal
+            # (at most, in the SELL format's mean): two rows per lane
+            assert info.tune_ms == 0.0 and shapes == [2, 2, 1], shapes
         else:
             assert info.tune_ms > 0.0
         if ref is None:
@@ -322,7 +328,8 @@ def test_autotuned_shapes_change_time_not_results():
         else:
             assert torch.equal(x, ref[0]) and np.array_equal(g.history(), ref[1])
         g.close()
-    for kr, ch, lay in ((3, 0, 0), (1, 3, 0), (2, 8, 0), (0, 0, 3), (0, 0, -1)):
+    for kr, ch, lay in ((3, 0, 0), (1, 3, 0), (2, 8, 0), (0, 0, 3), (0, 0, -1), (-2, 0, 0), (0, 4, 0),
+                        (-1, 4, 0)):
         bad = PP.params_default(0)
         bad.rows_per_lane, bad.entry_chunk, bad.layout = kr, ch, lay
         with pytest.raises(PP.F3RError):
