@@ -177,6 +177,58 @@ WORKLOADS = {
 }
 
 
+def ablation_settings(P):
+    """The parameter studies of Sec. 6 (Table 4 and Figs. 3, 5 and 6) as
+    (name, levels, c, omega_init); levels are (kind, m, prec_a, prec_v)."""
+    F, R = P.FGMRES, P.RICHARDSON
+    D, S, H = P.FP64, P.FP32, P.FP16
+
+    def nest(m2=8, m3=4, m4=2):
+        return [(F, 100, D, D), (F, m2, S, S), (F, m3, H, S), (R, m4, H, H)]
+
+    out = [("F3R (F100, F8, F4, R2)", nest(), 64, 1.0)]
+    out += [(f"m2={m}", nest(m2=m), 64, 1.0) for m in (2, 4, 16, 32)]
+    out += [(f"m3={m}", nest(m3=m), 64, 1.0) for m in (2, 8, 16)]
+    out += [(f"m4={m}", nest(m4=m), 64, 1.0) for m in (1, 4, 8)]
+    out += [(f"c={c}", nest(), c, 1.0) for c in (1, 8, 512)]
+    out += [(f"static w={w}", nest(), 0, w) for w in (0.6, 0.8, 1.0, 1.2)]
+    out += [("F2", [(F, 100, D, D), (F, 64, S, S)], 64, 1.0),
+            ("fp16-F2", [(F, 100, D, D), (F, 64, H, H)], 64, 1.0),
+            ("F3", [(F, 100, D, D), (F, 8, S, S), (F, 8, H, S)], 64, 1.0),
+            ("fp16-F3", [(F, 100, D, D), (F, 8, S, S), (F, 8, H, H)], 64, 1.0),
+            ("F4", [(F, 100, D, D), (F, 8, S, S), (F, 4, H, S), (F, 2, H, H)], 64, 1.0)]
+    return out
+
+
+def bench_ablation(args, P, W, torch):
+    """Time every setting of the parameter studies on the workload (mean of
+    --steps solves after --warmup) with its outermost iterations and M
+    applications."""
+    gen, desc, _ = WORKLOADS[args.workload]
+    A = gen(W)
+    xs, b = W.rhs(A, args.workload)
+    bt = torch.as_tensor(b, device="cuda")
+    rows = []
+    for name, levels, c, w0 in ablation_settings(P):
+        p = P.params_default(P.VARIANT_FP16)
+        p.nlev = len(levels)
+        for d, (kind, m, pa, pv) in enumerate(levels):
+            p.lev[d].kind, p.lev[d].m, p.lev[d].prec_a, p.lev[d].prec_v = kind, m, pa, pv
+        p.c, p.omega_init = c, w0
+        s = P.Solver(A.row_ptr, A.col_idx, A.val, p)
+        (x, info), times, total = timed_solves(lambda: s.solve(bt, raise_on_error=False), args.steps,
+                                               args.warmup)
+        row = {"setting": name, "ms": round(total / args.steps * 1e3, 3), "status": info.status,
+               "outer_iters": info.outer_iters, "m_calls": info.m_calls,
+               "relres_true": info.relres_true}
+        rows.append(row)
+        log(f"[bench] ablation {name}: {row['ms']:.2f} ms, outer {info.outer_iters}, "
+            f"M calls {info.m_calls}, status {info.status}")
+        s.close()
+    return {"ablation": args.workload, "workload": f"{args.workload}: {desc} (n={A.n}, nnz={A.nnz})",
+            "tol": 1e-10, "steps": args.steps, "warmup": args.warmup, "rows": rows}
+
+
 def bench_batch(args, P, W, torch):
     """Batched solve in both modes (one persistent launch; lockstep per-kernel
     path) against the same systems solved one at a time."""
@@ -257,6 +309,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="poisson3d_128", choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--ablation", action="store_true",
+                    help="time the parameter studies of Sec. 6 on the workload instead of the metric")
     ap.add_argument("--cpu-outer", type=int, default=1)
     ap.add_argument("--only-f3r", action="store_true", help="time the fp16-F3R solves only (profiling)")
     ap.add_argument("--paper-protocol", action="store_true",
@@ -289,6 +343,9 @@ def main():
     name = args.workload
     if name == "varcoef2d_batch256":
         print(json.dumps(bench_batch(args, P, W, torch)), flush=True)
+        return
+    if args.ablation:
+        print(json.dumps(bench_ablation(args, P, W, torch)), flush=True)
         return
     gen, desc, extra = WORKLOADS[name]
     A = gen(W)
