@@ -18,6 +18,7 @@ LIB_PATH = os.path.join(HERE, "liboracle.so")
 F64, F32, F16, BF16 = 0, 1, 2, 3
 FGMRES, RICH = 0, 1
 OK, NOT_CONVERGED = 0, 1
+M_SGS, M_ILU = 0, 1  # primary preconditioner: two-SpMV truncated inverse, block-Jacobi ILU(0)
 CG, BICGSTAB = 0, 1  # comparison solvers of Sec. 5
 ERR_ARG, ERR_MATRIX, ERR_RANGE, ERR_NOMEM, ERR_BREAKDOWN = -1, -2, -3, -4, -6
 MAX_LEV = 8
@@ -37,7 +38,8 @@ class Params(C.Structure):
                 ("c", C.c_int32), ("alpha", C.c_double),
                 ("omega_init", C.c_double), ("max_outer", C.c_int32),
                 ("use_x0", C.c_int32), ("persist_weights", C.c_int32),
-                ("poison_call", C.c_int32)]
+                ("poison_call", C.c_int32), ("m_kind", C.c_int32),
+                ("ilu_blocks", C.c_int32)]
 
 
 class Info(C.Structure):
@@ -90,6 +92,8 @@ def lib():
         "or_krylov_solve": (C.c_int32, [H, C.c_int32, C.c_int32, _dp, _dp, C.c_double,
                                         C.c_int32, C.POINTER(Info)]),
         "or_n": (C.c_int64, [H]),
+        "or_get_ilu_values": (None, [H, C.c_int32, _dp]),
+        "or_ilu_block_start": (C.c_int64, [H, C.c_int64]),
         "or_get_scaling": (None, [H, _dp]),
         "or_get_level_values": (None, [H, C.c_int32, _dp]),
         "or_get_m_factors": (None, [H, _ip, _ip, _dp, _ip, _ip, _dp]),
@@ -219,6 +223,16 @@ class Oracle:
         info = Info()
         self.L.or_krylov_solve(self.h, method, int(bool(m64)), b, x, tol, max_iter, C.byref(info))
         return x, info
+
+    def ilu_values(self, use64=True):
+        """Block-Jacobi ILU(0) factors in the CSR order of A."""
+        v = np.empty(self.nnz)
+        self.L.or_get_ilu_values(self.h, int(bool(use64)), v)
+        return v
+
+    def ilu_block_starts(self):
+        return np.array([self.L.or_ilu_block_start(self.h, b)
+                         for b in range(self.params.ilu_blocks + 1)], dtype=np.int64)
 
     def scaling(self):
         s = np.empty(self.n)

@@ -190,6 +190,8 @@ struct or_handle {
   double *wv64, *gv64; /* fp64 factors */
   double *wv, *gv;     /* factors rounded to pM */
   double* mtmp;        /* intermediate of the two-SpMV application */
+  double *iv64, *iv;   /* block-Jacobi ILU(0) factors (CSR order of A), fp64 and pM */
+  int32_t* idiag;      /* position of each row's diagonal in its CSR row */
   level_ws ws[OR_MAX_LEV];
   double omega[OR_MAX_LEV][64];
   int64_t cntr[OR_MAX_LEV];
@@ -265,6 +267,9 @@ void or_destroy(or_handle* h) {
   free(h->gci);
   free(h->wv64);
   free(h->gv64);
+  free(h->iv64);
+  free(h->iv);
+  free(h->idiag);
   free(h->wv);
   free(h->gv);
   free(h->mtmp);
@@ -392,6 +397,103 @@ static int build_m(or_handle* h) {
   return OR_OK;
 }
 
+/* Block-Jacobi ILU(0) (Sec. 5.1, the CPU experiments' primary
+   preconditioner): rows split into `blocks` contiguous ranges of nearly equal
+   size, the couplings between ranges dropped; each diagonal block of the
+   scaled matrix, with its diagonal multiplied by alpha, is factored as
+   L U keeping the sparsity of A (ILU(0)): for every row i in order, for each
+   k < i of its pattern in increasing order, l_ik = a_ik / u_kk and then
+   a_ij -= l_ik u_kj for every j > k of row i's pattern that row k also
+   holds.  Built in fp64, then cast to pM. */
+int64_t or_ilu_block_start(const or_handle* h, int64_t b) {
+  return (b * h->n) / h->p.ilu_blocks;
+}
+
+static int64_t block_of(const or_handle* h, int64_t i) {
+  /* largest b with start(b) <= i */
+  int64_t b = (i * h->p.ilu_blocks) / h->n;
+  while (b + 1 <= h->p.ilu_blocks && or_ilu_block_start(h, b + 1) <= i) b++;
+  while (b > 0 && or_ilu_block_start(h, b) > i) b--;
+  return b;
+}
+
+static int build_ilu(or_handle* h) {
+  const int64_t n = h->n;
+  h->iv64 = xcalloc(h->nnz, sizeof(double));
+  h->iv = xcalloc(h->nnz, sizeof(double));
+  h->idiag = xcalloc(n, sizeof(int32_t));
+  if (!h->iv64 || !h->iv || !h->idiag) return OR_ERR_NOMEM;
+  for (int64_t i = 0; i < n; i++) {
+    const int64_t b = block_of(h, i);
+    const int64_t r0 = or_ilu_block_start(h, b), r1 = or_ilu_block_start(h, b + 1);
+    for (int64_t k = h->rp[i]; k < h->rp[i + 1]; k++) {
+      const int64_t c = h->ci[k];
+      if (c == i) {
+        h->idiag[i] = (int32_t)(k - h->rp[i]);
+        h->iv64[k] = h->p.alpha * h->ahat[k];
+      } else {
+        h->iv64[k] = (c >= r0 && c < r1) ? h->ahat[k] : 0.0;
+      }
+    }
+  }
+  double* v = h->iv64;
+  for (int64_t i = 0; i < n; i++) {
+    const int64_t b = block_of(h, i);
+    const int64_t r0 = or_ilu_block_start(h, b);
+    const int64_t lo = h->rp[i], hi = h->rp[i + 1];
+    for (int64_t p = lo; p < hi; p++) {
+      const int64_t k = h->ci[p];
+      if (k >= i) break;
+      if (k < r0) continue;  /* dropped coupling */
+      const double ukk = v[h->rp[k] + h->idiag[k]];
+      v[p] = v[p] / ukk;
+      /* row i's entries right of k against row k's upper entries */
+      int64_t q = h->rp[k] + h->idiag[k] + 1;
+      for (int64_t pj = p + 1; pj < hi; pj++) {
+        const int64_t j = h->ci[pj];
+        while (q < h->rp[k + 1] && h->ci[q] < j) q++;
+        if (q < h->rp[k + 1] && h->ci[q] == j) v[pj] = v[pj] - v[p] * v[q];
+      }
+    }
+  }
+  for (int64_t k = 0; k < h->nnz; k++) {
+    if (!isfinite(v[k])) return OR_ERR_MATRIX;
+    h->iv[k] = RND(h->p.pM, v[k]);
+  }
+  return OR_OK;
+}
+
+/* y = U^-1 L^-1 r per block, vectors stored in pv, arithmetic in q: the
+   forward sweep forms t_i = r_i - sum_k l_ik t_k, the backward sweep
+   y_i = (t_i - sum_j u_ij y_j) / u_ii, terms in column order, each product
+   and difference rounded to q, t and y stored in pv. */
+static void apply_ilu(or_handle* h, int32_t pv, int32_t q, int use64, const double* r,
+                      double* y) {
+  const int64_t n = h->n;
+  const double* v = use64 ? h->iv64 : h->iv;
+  double* t = h->mtmp;
+  for (int64_t i = 0; i < n; i++) {
+    const int64_t r0 = or_ilu_block_start(h, block_of(h, i));
+    double acc = r[i];
+    for (int64_t p = h->rp[i]; p < h->rp[i + 1] && h->ci[p] < i; p++)
+      if (h->ci[p] >= r0) acc = RND(q, acc - RND(q, v[p] * t[h->ci[p]]));
+    t[i] = RND(pv, acc);
+  }
+  for (int64_t i = n - 1; i >= 0; i--) {
+    const int64_t r1 = or_ilu_block_start(h, block_of(h, i) + 1);
+    const int64_t pd = h->rp[i] + h->idiag[i];
+    double acc = t[i];
+    for (int64_t p = pd + 1; p < h->rp[i + 1]; p++)
+      if (h->ci[p] < r1) acc = RND(q, acc - RND(q, v[p] * y[h->ci[p]]));
+    y[i] = RND(pv, RND(q, acc / v[pd]));
+  }
+}
+
+void or_get_ilu_values(const or_handle* h, int32_t use64, double* vals) {
+  if (!h->iv64) return;
+  memcpy(vals, use64 ? h->iv64 : h->iv, (size_t)h->nnz * sizeof(double));
+}
+
 int32_t or_setup(int64_t n, int64_t nnz, const int32_t* rp, const int32_t* ci,
                  const double* val, const or_params* p, or_handle** out) {
   *out = NULL;
@@ -401,6 +503,8 @@ int32_t or_setup(int64_t n, int64_t nnz, const int32_t* rp, const int32_t* ci,
     if (p->lev[d].m < 1 || p->lev[d].m > (d == 0 ? 100000 : 64))
       return OR_ERR_ARG;
   if (!(p->alpha > 0.0)) return OR_ERR_ARG;
+  if (p->m_kind != OR_M_SGS && p->m_kind != OR_M_ILU) return OR_ERR_ARG;
+  if (p->m_kind == OR_M_ILU && (p->ilu_blocks < 1 || p->ilu_blocks > n)) return OR_ERR_ARG;
   int st = validate(n, nnz, rp, ci, val);
   if (st != OR_OK) return st;
   or_handle* h = calloc(1, sizeof(*h));
@@ -447,6 +551,7 @@ int32_t or_setup(int64_t n, int64_t nnz, const int32_t* rp, const int32_t* ci,
     }
   }
   st = build_m(h);
+  if (st == OR_OK && p->m_kind == OR_M_ILU) st = build_ilu(h);
   if (st != OR_OK) {
     or_destroy(h);
     return st;
@@ -517,6 +622,10 @@ static void apply_m_impl(or_handle* h, int32_t pv, int32_t q, int use64,
   h->st.m_calls++;
   if (h->p.m_identity) {
     for (int64_t i = 0; i < h->n; i++) y[i] = RND(pv, r[i]);
+    return;
+  }
+  if (h->p.m_kind == OR_M_ILU) {
+    apply_ilu(h, pv, q, use64, r, y);
     return;
   }
   const double* wv = use64 ? h->wv64 : h->wv;

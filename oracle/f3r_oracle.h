@@ -59,7 +59,12 @@ typedef struct {
   int32_t use_x0;          /* 1: x holds the initial guess */
   int32_t persist_weights; /* 1: keep omega and c_ntr from the previous solve */
   int32_t poison_call;     /* >0: inject NaN into the output of that R call */
+  int32_t m_kind;          /* OR_M_SGS (two-SpMV truncated inverse) or OR_M_ILU */
+  int32_t ilu_blocks;      /* block-Jacobi ILU(0): number of row blocks */
 } or_params;
+
+#define OR_M_SGS 0
+#define OR_M_ILU 1
 
 typedef struct {
   int32_t status;
@@ -111,6 +116,12 @@ void or_get_scaling(const or_handle* h, double* s);
 void or_get_level_values(const or_handle* h, int32_t p, double* vals);
 void or_get_m_factors(const or_handle* h, int32_t* wrp, int32_t* wci,
                       double* wv, int32_t* grp, int32_t* gci, double* gv);
+/* block-Jacobi ILU(0) factors in CSR order of A (L strictly below the
+   diagonal, unit diagonal implied; U on and above it; couplings across
+   blocks 0): fp64 (use64 = 1) or rounded to pM */
+void or_get_ilu_values(const or_handle* h, int32_t use64, double* vals);
+/* first row of block b (b = 0 .. blocks) */
+int64_t or_ilu_block_start(const or_handle* h, int64_t b);
 int64_t or_m_nnz_lower(const or_handle* h);
 int64_t or_m_nnz_upper(const or_handle* h);
 /* y = A_p x with A's values stored in pA, products and sums in pacc, result
