@@ -82,6 +82,18 @@ typedef int32_t f3r_status;
                                   row's diagonal at one common position: no
                                   per-slice offsets or bounds to load */
 
+/* primary preconditioner M (f3r_params.m_kind) */
+#define F3R_M_SGS 0   /* two-SpMV truncated inverse of the alpha-shifted
+                         symmetric Gauss-Seidel factors (Sec. 5.2) */
+#define F3R_M_ILU 1   /* block-Jacobi ILU(0) (Sec. 5.1): the rows split into
+                         ilu_blocks contiguous ranges of nearly equal size
+                         (block b: rows [b n / B, (b + 1) n / B)), couplings
+                         between ranges dropped, each diagonal block of the
+                         scaled matrix with its diagonal multiplied by alpha
+                         factored as L U with A's sparsity; applied by a
+                         forward and a backward sweep per block.  Not for
+                         batches; the M_UPPER probe is refused. */
+
 #define F3R_MAX_LEVELS 8
 
 typedef struct {
@@ -121,7 +133,10 @@ typedef struct {
                                     allowed with 2 or 4 rows and narrow vectors) */
   int32_t layout;                /* F3R_LAYOUT_*: device format of the matrix
                                     and M; results do not depend on it */
-  int32_t reserved[3];
+  int32_t m_kind;                /* F3R_M_SGS (default) or F3R_M_ILU */
+  int32_t ilu_blocks;            /* F3R_M_ILU: number of row blocks (1 .. n;
+                                    default 112, Sec. 5.1) */
+  int32_t reserved[1];
 } f3r_params;
 
 typedef struct {
@@ -327,6 +342,11 @@ f3r_status f3r_debug_round(int32_t prec, const double* in, double* out, int64_t 
 f3r_status f3r_debug_scaling(f3r_handle* h, double* s_host);
 f3r_status f3r_debug_level_values(f3r_handle* h, int32_t prec,
                                   double* vals_host);
+/* M's stored values in CSR order of A (nnz doubles) in storage prec, when M
+   has its own values (alpha != 1 or block-Jacobi ILU(0): the factors, L left
+   of the diagonal, U on and right of it, zero across blocks); else
+   F3R_ERR_ARG. */
+f3r_status f3r_debug_m_values(f3r_handle* h, int32_t prec, double* vals_host);
 
 #ifdef __cplusplus
 }

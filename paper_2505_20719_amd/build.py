@@ -17,7 +17,7 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 BUILD = os.path.join(PKG, "_build")
 LIB = os.path.join(PKG, "libf3r.so")
-SOURCES = ["kernels.hip", "setup.hip", "f3r.hip", "batch.hip", "batch_api.hip", "krylov.hip"]
+SOURCES = ["kernels.hip", "setup.hip", "f3r.hip", "batch.hip", "batch_api.hip", "krylov.hip", "ilu.hip"]
 ARCH = os.environ.get("F3R_OFFLOAD_ARCH", "gfx950")
 
 CFLAGS = [

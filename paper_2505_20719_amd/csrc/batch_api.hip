@@ -109,6 +109,7 @@ f3r_status f3r_setup_batched(int32_t count, const f3r_csr* A, const f3r_params* 
   if (!out) return F3R_ERR_ARG;
   *out = nullptr;
   if (count < 1 || !A || !p) return F3R_ERR_ARG;
+  if (p->m_kind != F3R_M_SGS) return F3R_ERR_ARG;  // batches use the two-sweep M
   if (p->flags & F3R_BATCH_LOCKSTEP) {
     f3r_params q = *p;
     q.flags &= ~F3R_BATCH_LOCKSTEP;

@@ -68,6 +68,7 @@ struct f3r_handle {
   void* idx = nullptr;
   uint16_t* kd = nullptr;
   uint16_t* kd_true = nullptr;  // diagonal-aligned format: true diagonal positions
+  IluDesc ilu;                  // block-Jacobi ILU(0) schedule when M is ILU
   uint32_t* kdr = nullptr;
   int32_t* rp = nullptr;  // CSR row pointers, kept for debug read-back
   double* a64 = nullptr;
@@ -173,6 +174,8 @@ f3r_status check_params(const f3r_params* p) {
   if (p->c < 0 || p->max_outer < 1) return F3R_ERR_ARG;
   if (p->m_identity != 0) return F3R_ERR_ARG;  // M = I is not provided
   if (p->layout < F3R_LAYOUT_AUTO || p->layout > F3R_LAYOUT_DIAG) return F3R_ERR_ARG;
+  if (p->m_kind != F3R_M_SGS && p->m_kind != F3R_M_ILU) return F3R_ERR_ARG;
+  if (p->m_kind == F3R_M_ILU && p->ilu_blocks < 1) return F3R_ERR_ARG;
   if (p->rows_per_lane != -1 && p->rows_per_lane != 0 && p->rows_per_lane != 1 &&
       p->rows_per_lane != 2 && p->rows_per_lane != 4)
     return F3R_ERR_ARG;
@@ -485,6 +488,13 @@ void autotune(f3r_handle* h) {
     return;
   }
   if (h->rich < 0) return;
+  if (h->ilu.blocks > 0) {
+    // block-Jacobi ILU(0): M runs its own sweeps; only the residual's shape
+    // matters, the row-length rule below picks it
+    h->kr[0] = h->kr[1] = 24;
+    h->kr[2] = 18;
+    return;
+  }
   if (fixed == 0) {
     // Rule from measurements of whole solves (stencils with 3-13 entries
     // per half row, elasticity with 41): rows with at most four entries on
@@ -990,6 +1000,7 @@ void f3r_params_default(f3r_params* p, int32_t variant) {
   p->alpha = 1.0;
   p->omega_init = 1.0;
   p->max_outer = 300;
+  p->ilu_blocks = 112;  // Sec. 5.1 (block-Jacobi ILU(0), when selected)
   p->nlev = 4;
   const int ms[4] = {100, 8, 4, 2};
   int pa[4] = {F3R_FP64, F3R_FP32, F3R_FP16, F3R_FP16};
@@ -1078,6 +1089,8 @@ f3r_status setup_impl(const f3r_csr* A, const f3r_params* p, void* hip_stream, i
     h->idx = (void*)m.A.idx;
     h->kd = (uint16_t*)m.A.kd;
     h->kd_true = m.kd_true;
+    h->ilu = m.ilu;
+    if (h->ilu.blocks > 0) h->A.ilu = &h->ilu;
     h->kdr = (uint32_t*)m.A.kdr;
     h->rp = m.rp;
     h->a64 = m.a64;
@@ -1181,6 +1194,11 @@ f3r_status f3r_solve(f3r_handle* h, const double* b, double* x, double tol,
     h->p.flags = lo->flags;
     h->p.poison_call = lo->poison_call;
     h->p.probe_kernel = lo->probe_kernel;
+    // the ILU backward sweep overwrites its input, so it cannot be repeated
+    if (h->ilu.blocks > 0 && h->p.probe_kernel == F3R_PROBE_M_UPPER) {
+      h->p = saved;
+      return F3R_ERR_ARG;
+    }
     if (h->p.c != saved.c || h->p.poison_call != saved.poison_call) destroy_graphs(h);
   }
   f3r_status s = guarded(h, info, [&]() {
@@ -1404,6 +1422,19 @@ f3r_status f3r_debug_scaling(f3r_handle* h, double* s_host) {
   if (!h || !s_host) return F3R_ERR_ARG;
   return guarded(h, nullptr, [&]() {
     HIPCHK(hipMemcpy(s_host, h->s, (size_t)h->n * 8, hipMemcpyDeviceToHost));
+    return F3R_OK;
+  });
+}
+
+f3r_status f3r_debug_m_values(f3r_handle* h, int32_t prec, double* vals_host) {
+  if (!h || !vals_host || !prec_ok(prec) || h->m_shared || !h->mv[prec]) return F3R_ERR_ARG;
+  return guarded(h, nullptr, [&]() {
+    double* d = (double*)h->dalloc((size_t)h->nnz * 8);
+    HIPCHK(sell_to_csr_values(h->st, h->n, h->rp, h->off, h->kd_true, h->A.dell_kd, h->mv[prec], prec,
+                              d));
+    HIPCHK(hipMemcpyAsync(vals_host, d, (size_t)h->nnz * 8, hipMemcpyDeviceToHost, h->st));
+    HIPCHK(hipStreamSynchronize(h->st));
+    h->al.release(d);
     return F3R_OK;
   });
 }

@@ -9,6 +9,7 @@
 #include <vector>
 
 #include "f3r.h"
+#include "ilu.h"
 #include "kernels.h"
 
 namespace f3r {
@@ -59,6 +60,7 @@ struct MatrixDev {
   double gd[4] = {1, 1, 1, 1};  // diagonal of G: round_t(1 / alpha)
   double* s = nullptr;        // s_i = 1 / sqrt(|a_ii|)
   uint16_t* kd_true = nullptr;  // diagonal-aligned format: each row's own diagonal position
+  IluDesc ilu;                  // block-Jacobi ILU(0) schedule (blocks = 0: not used)
 };
 
 // Validates the CSR matrix (host checks first, then the device checks of

@@ -1,0 +1,58 @@
+// Block-Jacobi ILU(0) as the primary preconditioner (Sec. 5.1): the rows
+// are split into `blocks` contiguous ranges, row r0(b) = b n / blocks; the
+// couplings between ranges are dropped; each diagonal block of the scaled
+// matrix, its diagonal multiplied by alpha, is factored as L U with the
+// sparsity of A.  The factors live in M's value arrays, at the positions of
+// the matrix entries in the device format (L strictly left of each row's
+// diagonal with a unit diagonal implied, U on and right of it).
+//
+// Triangular solves and the factorisation run one workgroup per block,
+// level by level: a row's level is one more than the largest level of the
+// in-block rows it depends on, the rows of a level are independent, and a
+// workgroup barrier separates the levels.  Rows are stored sorted by level
+// per block (rows[r0 .. r1)), with level boundaries lptr[r0 + b + l].
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "kernels.h"
+
+namespace f3r {
+
+constexpr int kIluThreads = 256;
+
+struct IluDesc {
+  int blocks = 0;
+  const int* rows_lo = nullptr;  // forward sweep order (lower dependencies)
+  const int* lptr_lo = nullptr;
+  const int* nlev_lo = nullptr;  // levels per block
+  const int* rows_up = nullptr;  // backward sweep order (upper dependencies)
+  const int* lptr_up = nullptr;
+  const int* nlev_up = nullptr;
+};
+
+// Writable arrays of the schedule, filled at set-up.
+struct IluBuild {
+  int blocks = 0;
+  int *lev = nullptr, *rows_lo = nullptr, *lptr_lo = nullptr, *nlev_lo = nullptr;
+  int *rows_up = nullptr, *lptr_up = nullptr, *nlev_up = nullptr;
+};
+
+// level schedules of both sweeps (A's pattern, in-block couplings only)
+hipError_t ilu_schedule(hipStream_t st, const SellDesc& A, const IluBuild& b);
+// in-place ILU(0) of the fp64 values v64 (initial values: the shifted
+// in-block matrix, zero across blocks), then rounded copies to each non-null
+// narrow[t]; non-finite fp64 factors set SF_MATRIX, overflowing copies
+// SF_RANGE in *flags
+hipError_t ilu_factor(hipStream_t st, const SellDesc& A, const IluBuild& b, double* v64,
+                      void* const narrow[4], int* flags);
+
+// t = L^-1 r (input as in m_apply_w), y = U^-1 t in place of t with the
+// epilogue of m_apply_g applied to y
+hipError_t ilu_apply_fwd(hipStream_t st, const SellDesc& A, const void* mv, int tm,
+                         const Basis& in, void* t, int tt, const int* stop, int64_t* cntr);
+hipError_t ilu_apply_bwd(hipStream_t st, const SellDesc& A, const void* mv, int tm, void* t,
+                         int tt, int mode, const double* omega, const void* zprev, void* out,
+                         int tout, const double* s, int* fbflag, const int* stop, const int* cur);
+
+}  // namespace f3r

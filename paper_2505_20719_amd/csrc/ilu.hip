@@ -1,0 +1,322 @@
+// Block-Jacobi ILU(0) (see ilu.h): level schedules, the factorisation and
+// the two triangular sweeps, one workgroup per row block.
+//
+// Every row is processed by one thread, in the order of the definition: the
+// factorisation walks the row's entries left of the diagonal in increasing
+// column order (l_ik = a_ik / u_kk, then a_ij -= l_ik u_kj for the later
+// entries j that row k also holds); the forward sweep forms
+// t_i = r_i - sum_k l_ik t_k and the backward sweep
+// y_i = (t_i - sum_j u_ij y_j) / u_ii, terms in column order with separate
+// multiply and subtract.  Rows of one level do not depend on each other, so
+// the order inside a level changes nothing.
+#include "ilu.h"
+
+#include "common.h"
+#include "kernels.h"
+#include "sell.h"
+#include "setup.h"
+
+namespace f3r {
+
+namespace {
+
+__device__ __forceinline__ int64_t blk_start(int64_t b, int64_t n, int nb) { return (b * n) / nb; }
+
+// one row of the device format: first element, width, diagonal position
+struct RowAt {
+  uint32_t e0;
+  int w, dp;
+};
+__device__ __forceinline__ RowAt row_at(const SellDesc& A, int64_t i) {
+  const int64_t s = i / kWave;
+  const uint32_t lane = (uint32_t)(i % kWave);
+  RowAt r;
+  if (A.dell_w > 0) {
+    r.e0 = (uint32_t)(s * kWave * A.dell_w) + lane;
+    r.w = A.dell_w;
+  } else {
+    const uint32_t o0 = A.off[s];
+    r.e0 = o0 + lane;
+    r.w = (int)((A.off[s + 1] - o0) / kWave);
+  }
+  r.dp = (int)A.kd[i];  // the diagonal-aligned format stores the common position
+  return r;
+}
+template <class TI>
+__device__ __forceinline__ int64_t col_at(const SellDesc& A, const RowAt& r, int64_t i, int p) {
+  return col_of<TI>(((const TI*)A.idx)[r.e0 + (uint32_t)p * kWave], i);
+}
+__device__ __forceinline__ uint32_t at(const RowAt& r, int p) { return r.e0 + (uint32_t)p * kWave; }
+
+// Levels of both sweeps and the rows sorted by level, one block per
+// workgroup, computed by its first thread (set-up only).
+template <class TI>
+__global__ void k_ilu_sched(SellDesc A, IluBuild b) {
+  if (threadIdx.x != 0) return;
+  const int bk = blockIdx.x;
+  const int64_t n = A.n;
+  const int64_t r0 = blk_start(bk, n, b.blocks), r1 = blk_start(bk + 1, n, b.blocks);
+  for (int dir = 0; dir < 2; dir++) {
+    int* rows = dir == 0 ? b.rows_lo : b.rows_up;
+    int* lptr = (dir == 0 ? b.lptr_lo : b.lptr_up) + r0 + bk;
+    int maxl = 0;
+    for (int64_t q = 0; q < r1 - r0; q++) {
+      const int64_t i = dir == 0 ? r0 + q : r1 - 1 - q;
+      const RowAt ra = row_at(A, i);
+      int l = 0;
+      for (int p = 0; p < ra.w; p++) {
+        if (p == ra.dp) continue;
+        const int64_t c = col_at<TI>(A, ra, i, p);
+        if (c == i || c < r0 || c >= r1) continue;  // padding, dropped coupling
+        if (dir == 0 ? c < i : c > i) l = max(l, b.lev[c] + 1);
+      }
+      b.lev[i] = l;
+      maxl = max(maxl, l);
+    }
+    const int nl = maxl + 1;
+    for (int l = 0; l <= nl; l++) lptr[l] = 0;
+    for (int64_t i = r0; i < r1; i++) lptr[b.lev[i] + 1]++;
+    for (int l = 0; l < nl; l++) lptr[l + 1] += lptr[l];
+    for (int64_t i = r0; i < r1; i++) rows[r0 + lptr[b.lev[i]]++] = (int)i;
+    for (int l = nl; l > 0; l--) lptr[l] = lptr[l - 1];
+    lptr[0] = 0;
+    (dir == 0 ? b.nlev_lo : b.nlev_up)[bk] = nl;
+  }
+}
+
+template <class TI>
+__global__ __launch_bounds__(kIluThreads) void k_ilu_factor(SellDesc A, IluBuild b,
+                                                            double* __restrict__ v) {
+  const int bk = blockIdx.x;
+  const int64_t n = A.n;
+  const int64_t r0 = blk_start(bk, n, b.blocks);
+  const int* lptr = b.lptr_lo + r0 + bk;
+  const int nl = b.nlev_lo[bk];
+  for (int l = 0; l < nl; l++) {
+    for (int q = lptr[l] + (int)threadIdx.x; q < lptr[l + 1]; q += kIluThreads) {
+      const int64_t i = b.rows_lo[r0 + q];
+      const RowAt ra = row_at(A, i);
+      for (int p = 0; p < ra.dp; p++) {
+        const int64_t k = col_at<TI>(A, ra, i, p);
+        if (k == i || k < r0) continue;  // padding, dropped coupling
+        const RowAt rk = row_at(A, k);
+        const double lik = v[at(ra, p)] / v[at(rk, rk.dp)];
+        v[at(ra, p)] = lik;
+        int qk = rk.dp + 1;
+        for (int pj = p + 1; pj < ra.w; pj++) {
+          const int64_t j = col_at<TI>(A, ra, i, pj);
+          if (j == i && pj != ra.dp) continue;  // padding
+          // row k's upper entries ascend; its padding (column k) never matches
+          while (qk < rk.w && col_at<TI>(A, rk, k, qk) < j) qk++;
+          if (qk < rk.w && col_at<TI>(A, rk, k, qk) == j)
+            v[at(ra, pj)] = v[at(ra, pj)] - lik * v[at(rk, qk)];
+        }
+      }
+    }
+    __syncthreads();
+  }
+}
+
+// fp64 factors checked, narrow copies rounded from them
+template <class T>
+__device__ __forceinline__ void put_narrow(void* p, int64_t e, double x, int* bad) {
+  if (!p) return;
+  const T r = round_to<T>(x);
+  ((T*)p)[e] = r;
+  if (!finite_val(r)) *bad |= SF_RANGE;
+}
+__global__ void k_ilu_finish(int64_t count, const double* __restrict__ v, void* n32, void* n16,
+                             void* nb16, int* flags) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= count) return;
+  const double x = v[e];
+  int bad = isfinite(x) ? 0 : SF_MATRIX;
+  put_narrow<float>(n32, e, x, &bad);
+  put_narrow<f16>(n16, e, x, &bad);
+  put_narrow<bf16>(nb16, e, x, &bad);
+  if (bad) atomicOr(flags, bad);
+}
+
+template <class TI, class TM, class TT, class Q, class LD>
+__global__ __launch_bounds__(kIluThreads) void k_ilu_fwd(SellDesc A, IluDesc D, const TM* __restrict__ mv,
+                                                         LD ld, TT* __restrict__ t, const int* stop,
+                                                         int64_t* cntr) {
+  if (cntr && blockIdx.x == 0 && threadIdx.x == 0) *cntr += 1;
+  if (read_flag(stop)) return;  // one system: the whole launch is stopped or not
+  const int bk = blockIdx.x;
+  const int64_t r0 = blk_start(bk, A.n, D.blocks);
+  ld.at_sys(0, A.sys);
+  ld.init();
+  const int* lptr = D.lptr_lo + r0 + bk;
+  const int nl = D.nlev_lo[bk];
+  for (int l = 0; l < nl; l++) {
+    for (int q = lptr[l] + (int)threadIdx.x; q < lptr[l + 1]; q += kIluThreads) {
+      const int64_t i = D.rows_lo[r0 + q];
+      const RowAt ra = row_at(A, i);
+      Q acc = ld(i);
+      for (int p = 0; p < ra.dp; p++) {
+        const int64_t k = col_at<TI>(A, ra, i, p);
+        if (k == i || k < r0) continue;
+        acc = acc - widen<Q>(mv[at(ra, p)]) * widen<Q>(t[k]);
+      }
+      t[i] = round_to<TT>(acc);
+    }
+    __syncthreads();
+  }
+}
+
+template <class TI, class TM, class TT, class Q, class EPI>
+__global__ __launch_bounds__(kIluThreads) void k_ilu_bwd(SellDesc A, IluDesc D, const TM* __restrict__ mv,
+                                                         TT* __restrict__ t, EPI epi, const int* stop) {
+  if (read_flag(stop)) return;
+  const int bk = blockIdx.x;
+  const int64_t r0 = blk_start(bk, A.n, D.blocks), r1 = blk_start(bk + 1, A.n, D.blocks);
+  epi.at_sys(0, A.sys);
+  epi.init();
+  const int* lptr = D.lptr_up + r0 + bk;
+  const int nl = D.nlev_up[bk];
+  for (int l = 0; l < nl; l++) {
+    for (int q = lptr[l] + (int)threadIdx.x; q < lptr[l + 1]; q += kIluThreads) {
+      const int64_t i = D.rows_up[r0 + q];
+      const RowAt ra = row_at(A, i);
+      epi.prefetch(0, i);
+      Q acc = widen<Q>(t[i]);
+      for (int p = ra.dp + 1; p < ra.w; p++) {
+        const int64_t j = col_at<TI>(A, ra, i, p);
+        if (j == i || j >= r1) continue;
+        acc = acc - widen<Q>(mv[at(ra, p)]) * widen<Q>(t[j]);
+      }
+      const Q yq = acc / widen<Q>(mv[at(ra, ra.dp)]);
+      const TT y = round_to<TT>(yq);
+      t[i] = y;
+      epi(0, i, y);
+    }
+    __syncthreads();
+  }
+}
+
+}  // namespace
+
+hipError_t ilu_schedule(hipStream_t st, const SellDesc& A, const IluBuild& b) {
+  return with_idx(A.idx16, [&](auto pi) {
+    using TI = TYPE_OF(pi);
+    hipLaunchKernelGGL((k_ilu_sched<TI>), dim3((unsigned)b.blocks), dim3(64), 0, st, A, b);
+    return hipGetLastError();
+  });
+}
+
+hipError_t ilu_factor(hipStream_t st, const SellDesc& A, const IluBuild& b, double* v64,
+                      void* const narrow[4], int* flags) {
+  hipError_t e = with_idx(A.idx16, [&](auto pi) {
+    using TI = TYPE_OF(pi);
+    hipLaunchKernelGGL((k_ilu_factor<TI>), dim3((unsigned)b.blocks), dim3(kIluThreads), 0, st, A, b,
+                       v64);
+    return hipGetLastError();
+  });
+  if (e != hipSuccess) return e;
+  int64_t count = 0;
+  {
+    // the arrays hold every position of the format, padding included
+    const int64_t ns = n_slices(A.n);
+    count = A.dell_w > 0 ? ns * kWave * A.dell_w : -1;
+  }
+  if (count < 0) {
+    uint32_t last = 0;
+    e = hipMemcpyAsync(&last, A.off + n_slices(A.n), sizeof(uint32_t), hipMemcpyDeviceToHost, st);
+    if (e != hipSuccess) return e;
+    e = hipStreamSynchronize(st);
+    if (e != hipSuccess) return e;
+    count = last;
+  }
+  hipLaunchKernelGGL(k_ilu_finish, dim3((unsigned)((count + 255) / 256)), dim3(256), 0, st, count, v64,
+                     narrow[T32], narrow[T16], narrow[TB16], flags);
+  return hipGetLastError();
+}
+
+hipError_t ilu_apply_fwd(hipStream_t st, const SellDesc& A, const void* mv, int tm, const Basis& in,
+                         void* t, int tt, const int* stop, int64_t* cntr) {
+  const IluDesc D = *A.ilu;
+  const dim3 grid((unsigned)D.blocks), blk(kIluThreads);
+  return with_idx(A.idx16, [&](auto pi) {
+    using TI = TYPE_OF(pi);
+    return with_type(tm, [&](auto pm) {
+      using TM = TYPE_OF(pm);
+      return with_type(tt, [&](auto pt) -> hipError_t {
+        using TT = TYPE_OF(pt);
+        if constexpr (!ok_m<TM, TT>()) {
+          return hipErrorInvalidValue;
+        } else {
+          using Q = wider_t<TM, TT>;
+          if (in.s) {
+            if (in.type != T64 || !is_dbl<TT>::value) return hipErrorInvalidValue;
+            LdSBasis<TT, Q> ld{(const double*)in.raw, in.scale, in.s, in.cur, in.stride, 0.0};
+            hipLaunchKernelGGL((k_ilu_fwd<TI, TM, TT, Q, LdSBasis<TT, Q>>), grid, blk, 0, st, A, D,
+                               (const TM*)mv, ld, (TT*)t, stop, cntr);
+            return hipGetLastError();
+          }
+          if (!in.scale) {
+            if (in.type != tt) return hipErrorInvalidValue;
+            LdVec<TT, Q> ld{(const TT*)in.raw};
+            hipLaunchKernelGGL((k_ilu_fwd<TI, TM, TT, Q, LdVec<TT, Q>>), grid, blk, 0, st, A, D,
+                               (const TM*)mv, ld, (TT*)t, stop, cntr);
+            return hipGetLastError();
+          }
+          return with_type(in.type, [&](auto pin) -> hipError_t {
+            using TIN = TYPE_OF(pin);
+            using QQ = wider_t<TIN, Q>;
+            LdBasis<TIN, TT, QQ> ld{(const TIN*)in.raw, in.scale, in.cur, in.stride, 0.0};
+            hipLaunchKernelGGL((k_ilu_fwd<TI, TM, TT, QQ, LdBasis<TIN, TT, QQ>>), grid, blk, 0, st, A,
+                               D, (const TM*)mv, ld, (TT*)t, stop, cntr);
+            return hipGetLastError();
+          });
+        }
+      });
+    });
+  });
+}
+
+hipError_t ilu_apply_bwd(hipStream_t st, const SellDesc& A, const void* mv, int tm, void* t, int tt,
+                         int mode, const double* omega, const void* zprev, void* out, int tout,
+                         const double* s, int* fbflag, const int* stop, const int* cur) {
+  if (mode != 3 && tout != tt) return hipErrorInvalidValue;
+  const IluDesc D = *A.ilu;
+  const dim3 g((unsigned)D.blocks), b(kIluThreads);
+  return with_idx(A.idx16, [&](auto pi) {
+    using TI = TYPE_OF(pi);
+    return with_type(tm, [&](auto pm) {
+      using TM = TYPE_OF(pm);
+      return with_type(tt, [&](auto pt) -> hipError_t {
+        using TT = TYPE_OF(pt);
+        if constexpr (!ok_m<TM, TT>()) {
+          return hipErrorInvalidValue;
+        } else {
+          using Q = wider_t<TM, TT>;
+          if (mode == 0) {
+            EpiStore<TT, Q> ep{(TT*)out, fbflag};
+            hipLaunchKernelGGL((k_ilu_bwd<TI, TM, TT, Q, EpiStore<TT, Q>>), g, b, 0, st, A, D,
+                               (const TM*)mv, (TT*)t, ep, stop);
+          } else if (mode == 1) {
+            EpiZ1<TT, Q> ep{(TT*)out, omega, fbflag, (Q)0};
+            hipLaunchKernelGGL((k_ilu_bwd<TI, TM, TT, Q, EpiZ1<TT, Q>>), g, b, 0, st, A, D,
+                               (const TM*)mv, (TT*)t, ep, stop);
+          } else if (mode == 2) {
+            EpiZK<TT, Q> ep{(TT*)out, (const TT*)zprev, omega, fbflag, (Q)0};
+            hipLaunchKernelGGL((k_ilu_bwd<TI, TM, TT, Q, EpiZK<TT, Q>>), g, b, 0, st, A, D,
+                               (const TM*)mv, (TT*)t, ep, stop);
+          } else {
+            if constexpr (!is_dbl<TT>::value) {
+              return hipErrorInvalidValue;
+            } else {
+              EpiS64 ep{(double*)out, s, fbflag, cur, A.n};
+              hipLaunchKernelGGL((k_ilu_bwd<TI, TM, TT, Q, EpiS64>), g, b, 0, st, A, D,
+                                 (const TM*)mv, (TT*)t, ep, stop);
+            }
+          }
+          return hipGetLastError();
+        }
+      });
+    });
+  });
+}
+
+}  // namespace f3r

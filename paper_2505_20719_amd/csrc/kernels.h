@@ -37,6 +37,8 @@ struct SysLayout {
   int64_t dS = 0, dI = 0;
 };
 
+struct IluDesc;  // block-Jacobi ILU(0) schedule (ilu.h)
+
 // Diagonal-aligned variant (dell_w > 0): every slice has width dell_w and
 // entry j of row r sits at position dell_kd - (lower entries of r) + j, so
 // the diagonal of every row is at position dell_kd; the positions before a
@@ -54,6 +56,9 @@ struct SellDesc {
   const uint32_t* kdr = nullptr;
   SysLayout sys;
   int dell_w = 0, dell_kd = 0;
+  // host pointer: when set, M is block-Jacobi ILU(0) and the M launchers run
+  // its triangular sweeps (never read on the device)
+  const IluDesc* ilu = nullptr;
 };
 
 __host__ __device__ inline int64_t n_slices(int64_t n) { return (n + 63) / 64; }
@@ -202,6 +207,8 @@ hipError_t m_apply_w(hipStream_t st, const SellDesc& A, const void* mv, int tm, 
                      const Basis& in, void* t, int tt, const int* stop, int64_t* cntr_inc,
                      int kr = 44);
 
+// With A.ilu set, m_apply_w is the forward sweep t = L^-1 r and m_apply_g
+// the backward sweep y = U^-1 t, which overwrites t with y.
 // y = round(gd t_i + sum_{k > kd} g_k t_c): G = (1/alpha)(I - U/alpha).
 // mode 0: out = y; 1: out = round(w y); 2: out = round(zprev + w y) with
 // w = *omega; 3: out = s_i y (fp64 output, s scaling of the comparison solver).

@@ -12,6 +12,7 @@
 #include <type_traits>
 
 #include "common.h"
+#include "ilu.h"
 #include "kernels.h"
 #include "sell.h"
 
@@ -19,19 +20,6 @@ namespace f3r {
 
 static_assert(kRowsPerBlock == kSysAlign, "systems are aligned to reduction blocks");
 
-template <class F> static hipError_t with_type(int t, F&& f) {
-  switch (t) {
-    case T64: return f((double*)nullptr);
-    case T32: return f((float*)nullptr);
-    case T16: return f((f16*)nullptr);
-    case TB16: return f((bf16*)nullptr);
-  }
-  return hipErrorInvalidValue;
-}
-template <class F> static hipError_t with_idx(int idx16, F&& f) {
-  return idx16 ? f((int16_t*)nullptr) : f((int32_t*)nullptr);
-}
-#define TYPE_OF(p) typename std::remove_pointer<decltype(p)>::type
 
 // Shape of the sweeps whose shape the set-up autotuner picks (their results
 // do not depend on it), coded as 10 KR + U: KR rows per lane, entries in
@@ -815,79 +803,6 @@ __global__ __launch_bounds__(kBlock) void k_mw(SellDesc A, const TM* __restrict_
     if (s[r].ok && !stopped) t[s[r].row] = round_to<TT>(acc[r] + ld.cook(dg[r]));
 }
 
-// Epilogues of the G sweep.  prefetch(k, row) issues the row-local loads of
-// lane slot k before the row sums so they overlap the matrix loads.
-template <class TT, class Q> struct EpiStore {
-  TT* out;
-  int* fb;
-  __device__ __forceinline__ void at_sys(int sy, const SysLayout& sl) { fb = sys_ptr(fb, sy, sl.dI); }
-  __device__ __forceinline__ void init() {}
-  __device__ __forceinline__ void prefetch(int, int64_t) {}
-  __device__ __forceinline__ void operator()(int, int64_t r, TT y) const {
-    out[r] = y;
-    if (fb && !finite_val(y)) atomicOr(fb, 1);
-  }
-};
-template <class TT, class Q> struct EpiZ1 {
-  TT* out;
-  const double* wp;
-  int* fb;
-  Q w;
-  __device__ __forceinline__ void at_sys(int sy, const SysLayout& sl) {
-    wp = sys_ptr(wp, sy, sl.dS);
-    fb = sys_ptr(fb, sy, sl.dI);
-  }
-  __device__ __forceinline__ void init() { w = (Q)vload(wp); }
-  __device__ __forceinline__ void prefetch(int, int64_t) {}
-  __device__ __forceinline__ void operator()(int, int64_t r, TT y) const {
-    const TT z = round_to<TT>(w * widen<Q>(y));
-    out[r] = z;
-    if (fb && !finite_val(z)) atomicOr(fb, 1);
-  }
-};
-template <class TT, class Q> struct EpiZK {
-  TT* out;
-  const TT* zp;
-  const double* wp;
-  int* fb;
-  Q w;
-  TT zv[4];  // one per row of the lane (at most four), converted when used
-  __device__ __forceinline__ void at_sys(int sy, const SysLayout& sl) {
-    wp = sys_ptr(wp, sy, sl.dS);
-    fb = sys_ptr(fb, sy, sl.dI);
-  }
-  __device__ __forceinline__ void init() { w = (Q)vload(wp); }
-  __device__ __forceinline__ void prefetch(int k, int64_t r) { zv[k] = zp[r]; }
-  __device__ __forceinline__ void operator()(int k, int64_t r, TT y) const {
-    const TT z = round_to<TT>(widen<Q>(zv[k]) + w * widen<Q>(y));
-    out[r] = z;
-    if (fb && !finite_val(z)) atomicOr(fb, 1);
-  }
-};
-struct EpiS64 {
-  double* out;
-  const double* s;
-  int* fb;
-  const int* cur;
-  int64_t n;
-  __device__ __forceinline__ void at_sys(int sy, const SysLayout& sl) {
-    fb = sys_ptr(fb, sy, sl.dI);
-    cur = sys_ptr(cur, sy, sl.dI);
-  }
-  __device__ __forceinline__ void init() {
-    if (cur) {
-      out += (int64_t)(*cur) * n;
-      if (fb) fb += *cur;
-    }
-  }
-  __device__ __forceinline__ void prefetch(int, int64_t) {}
-  __device__ __forceinline__ void operator()(int, int64_t r, double y) const {
-    const double z = s[r] * y;
-    out[r] = z;
-    if (fb && !isfinite(z)) atomicOr(fb, 1);
-  }
-};
-
 template <int KR, int U, class TI, class TM, class TT, class Q, class EPI>
 __global__ __launch_bounds__(kBlock) void k_mg(SellDesc A, const TM* __restrict__ mv, int neg, Q gd,
                                                const TT* __restrict__ t, EPI epi, const int* stop,
@@ -930,15 +845,10 @@ __global__ __launch_bounds__(kBlock) void k_mg(SellDesc A, const TM* __restrict_
     if (s[r].ok && !stopped) epi(r, s[r].row, round_to<TT>(acc[r]));
 }
 
-template <class TM, class TT> constexpr bool ok_m() {
-  // M stored no wider than the vectors it is applied to
-  if (is_dbl<TT>::value) return true;
-  if (std::is_same<TT, float>::value) return !is_dbl<TM>::value;
-  return std::is_same<TM, TT>::value;
-}
 
 hipError_t m_apply_w(hipStream_t st, const SellDesc& A, const void* mv, int tm, int neg,
                      const Basis& in, void* t, int tt, const int* stop, int64_t* cntr, int kr) {
+  if (A.ilu) return ilu_apply_fwd(st, A, mv, tm, in, t, tt, stop, cntr);
   return with_kr(kr, [&](auto KRc, auto Uc) {
   constexpr int KR = decltype(KRc)::value, U = decltype(Uc)::value;
   const int64_t nb = n_blocks_kr(A.n, KR);
@@ -986,6 +896,10 @@ hipError_t m_apply_g(hipStream_t st, const SellDesc& A, const void* mv, int tm, 
                      const void* t, int tt, int mode, const double* omega, const void* zprev,
                      void* out, int tout, const double* s, int* fbflag, const int* stop,
                      const int* cur, int kr) {
+  // block-Jacobi ILU(0): the backward sweep, y kept in place of t
+  if (A.ilu)
+    return ilu_apply_bwd(st, A, mv, tm, const_cast<void*>(t), tt, mode, omega, zprev, out, tout, s,
+                         fbflag, stop, cur);
   if (mode != 3 && tout != tt) return hipErrorInvalidValue;
   return with_kr(kr, [&](auto KRc, auto Uc) {
   constexpr int KR = decltype(KRc)::value, U = decltype(Uc)::value;

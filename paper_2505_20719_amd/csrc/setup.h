@@ -37,6 +37,7 @@ struct SellOut {
   void* mv[4] = {};             // M values per precision (lower part W, upper part G)
   double alpha = 1.0;
   int range_mask = 0;           // precision tags (bit t) whose overflow is an error
+  int ilu_blocks = 0;           // > 0: M values are the shifted in-block matrix (ILU input)
 };
 
 // Scatters every row into the SELL-64 arrays (padding included) and

@@ -4,6 +4,7 @@
 
 #include "common.h"
 #include "host.h"
+#include "ilu.h"
 #include "kernels.h"
 #include "setup.h"
 
@@ -126,8 +127,19 @@ __global__ void k_to_sell(int64_t n, const int32_t* __restrict__ rp, const int32
       c = ci[lo + k];
       a = val[lo + k];
       ah = (si * a) * s[c];
-      if (c < i) mvv = -ah / o.alpha;
-      if (c > i) mvv = (-ah / o.alpha) / o.alpha;
+      if (o.ilu_blocks > 0) {
+        // block-Jacobi ILU(0) input: diagonal times alpha, couplings to other
+        // row blocks dropped (block b holds rows [b n / B, (b + 1) n / B))
+        const int64_t nb = o.ilu_blocks;
+        int64_t b = (i * nb) / n;
+        while (b + 1 <= nb && ((b + 1) * n) / nb <= i) b++;
+        while (b > 0 && (b * n) / nb > i) b--;
+        const int64_t r0 = (b * n) / nb, r1 = ((b + 1) * n) / nb;
+        mvv = c == i ? o.alpha * ah : (c >= r0 && c < r1 ? ah : 0.0);
+      } else {
+        if (c < i) mvv = -ah / o.alpha;
+        if (c > i) mvv = (-ah / o.alpha) / o.alpha;
+      }
     }
     if (o.idx16)
       ((int16_t*)o.idx)[e] = (int16_t)(c - i);
@@ -267,7 +279,11 @@ f3r_status build_matrix(hipStream_t st, const f3r_csr* A, const f3r_params* p, c
   so.idx = al.get((size_t)acc * (so.idx16 ? 2 : 4));
   so.a64 = (double*)al.get((size_t)acc * 8);
   so.alpha = p->alpha;
-  m.m_shared = p->alpha == 1.0;
+  const bool ilu = p->m_kind == F3R_M_ILU;
+  if (ilu && (p->ilu_blocks < 1 || p->ilu_blocks > n)) return F3R_ERR_ARG;
+  so.ilu_blocks = ilu ? p->ilu_blocks : 0;
+  // M reads the matrix values when it is the alpha = 1 truncated inverse
+  m.m_shared = p->alpha == 1.0 && !ilu;
   bool need[4] = {need_in[0], need_in[1], need_in[2], need_in[3]};
   int mask = 0;
   for (int d = 1; d < p->nlev; d++) {
@@ -316,6 +332,35 @@ f3r_status build_matrix(hipStream_t st, const f3r_csr* A, const f3r_params* p, c
   m.A.idx16 = so.idx16;
   m.A.kd = kdk;
   m.A.kdr = kdr;
+  if (ilu) {
+    // level schedules, then the factorisation in place of the fp64 M values
+    // and their narrow copies
+    IluBuild ib;
+    ib.blocks = p->ilu_blocks;
+    const int64_t lp = n + p->ilu_blocks + 1;
+    ib.lev = (int*)al.get((size_t)n * sizeof(int));
+    ib.rows_lo = (int*)al.get((size_t)n * sizeof(int));
+    ib.rows_up = (int*)al.get((size_t)n * sizeof(int));
+    ib.lptr_lo = (int*)al.get((size_t)lp * sizeof(int));
+    ib.lptr_up = (int*)al.get((size_t)lp * sizeof(int));
+    ib.nlev_lo = (int*)al.get((size_t)p->ilu_blocks * sizeof(int));
+    ib.nlev_up = (int*)al.get((size_t)p->ilu_blocks * sizeof(int));
+    HIPCHK(ilu_schedule(st, m.A, ib));
+    void* narrow[4] = {nullptr, so.mv[T32], so.mv[T16], so.mv[TB16]};
+    HIPCHK(ilu_factor(st, m.A, ib, so.mv[T64] ? (double*)so.mv[T64] : nullptr, narrow, flags));
+    al.release(ib.lev);
+    m.ilu.blocks = ib.blocks;
+    m.ilu.rows_lo = ib.rows_lo;
+    m.ilu.rows_up = ib.rows_up;
+    m.ilu.lptr_lo = ib.lptr_lo;
+    m.ilu.lptr_up = ib.lptr_up;
+    m.ilu.nlev_lo = ib.nlev_lo;
+    m.ilu.nlev_up = ib.nlev_up;
+    HIPCHK(hipMemcpyAsync(&hflags, flags, sizeof(int), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    if (hflags & SF_MATRIX) return F3R_ERR_MATRIX;
+    if (hflags & SF_RANGE) return F3R_ERR_RANGE;
+  }
   // the CSR copies are no longer needed
   al.release(ci);
   al.release(val);

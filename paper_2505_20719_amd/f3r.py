@@ -25,6 +25,7 @@ MAX_LEVELS = 8
 
 OK, NOT_CONVERGED = 0, 1
 LAYOUT_AUTO, LAYOUT_SELL, LAYOUT_DIAG = 0, 1, 2  # device matrix formats
+M_SGS, M_ILU = 0, 1  # primary preconditioner: two-sweep truncated inverse, block-Jacobi ILU(0)
 CG, BICGSTAB = 0, 1  # comparison solvers of Sec. 5
 ERR_ARG, ERR_MATRIX, ERR_RANGE, ERR_NOMEM, ERR_DEVICE, ERR_BREAKDOWN = -1, -2, -3, -4, -5, -6
 
@@ -39,7 +40,8 @@ class Params(C.Structure):
                 ("omega_init", C.c_double), ("max_outer", C.c_int32), ("flags", C.c_uint32),
                 ("poison_call", C.c_int32), ("probe_kernel", C.c_int32),
                 ("rows_per_lane", C.c_int32), ("entry_chunk", C.c_int32),
-                ("layout", C.c_int32), ("reserved", C.c_int32 * 3)]
+                ("layout", C.c_int32), ("m_kind", C.c_int32), ("ilu_blocks", C.c_int32),
+                ("reserved", C.c_int32 * 1)]
 
 
 class Csr(C.Structure):
@@ -104,6 +106,7 @@ EXPORTS = {
     "f3r_debug_scaling": (C.c_int32, [C.c_void_p, C.c_void_p]),
     "f3r_debug_round": (C.c_int32, [C.c_int32, C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p]),
     "f3r_debug_level_values": (C.c_int32, [C.c_void_p, C.c_int32, C.c_void_p]),
+    "f3r_debug_m_values": (C.c_int32, [C.c_void_p, C.c_int32, C.c_void_p]),
 }
 
 
@@ -273,6 +276,11 @@ class Solver:
     def debug_level_values(self, prec):
         v = np.empty(self.nnz)
         self._check(self.L.f3r_debug_level_values(self.h, prec, v.ctypes.data), "debug_level_values")
+        return v
+
+    def debug_m_values(self, prec):
+        v = np.empty(self.nnz)
+        self._check(self.L.f3r_debug_m_values(self.h, prec, v.ctypes.data), "debug_m_values")
         return v
 
     @staticmethod
