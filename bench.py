@@ -229,6 +229,57 @@ def bench_ablation(args, P, W, torch):
             "tol": 1e-10, "steps": args.steps, "warmup": args.warmup, "rows": rows}
 
 
+def bench_ilu(args, P, W, torch):
+    """Block-Jacobi ILU(0) as M (Sec. 5.1's CPU preconditioner) against the
+    two-sweep M on the workload: fp16-F3R with several block counts, fp64-F3R
+    and fp64 CG / FGMRES(64) with the paper's 112 blocks; each with its set-up
+    time and the duration of one forward sweep (HIP events, probe solve)."""
+    gen, desc, _ = WORKLOADS[args.workload]
+    A = gen(W)
+    xs, b = W.rhs(A, args.workload)
+    bt = torch.as_tensor(b, device="cuda")
+    rows = []
+
+    def run(label, variant, m_kind, blocks, solver="f3r"):
+        p = P.params_default(variant)
+        p.m_kind, p.ilu_blocks = m_kind, blocks
+        t = time.perf_counter()
+        s = P.Solver(A.row_ptr, A.col_idx, A.val, p)
+        torch.cuda.synchronize()
+        setup_s = time.perf_counter() - t
+        if solver == "f3r":
+            fn = lambda: s.solve(bt, raise_on_error=False)  # noqa: E731
+        elif solver == "cg":
+            fn = lambda: s.krylov_solve(bt, P.CG, P.FP64, max_iter=19200, raise_on_error=False)  # noqa: E731
+        else:
+            fn = lambda: s.fgmres_solve(bt, m=64, raise_on_error=False)  # noqa: E731
+        (x, info), times, total = timed_solves(fn, args.steps, args.warmup)
+        row = {"setting": label, "ms": round(total / args.steps * 1e3, 3), "status": info.status,
+               "iters": info.outer_iters, "m_calls": info.m_calls, "setup_s": round(setup_s, 4),
+               "relres_true": info.relres_true}
+        if solver == "f3r":
+            ov = P.params_default(variant)
+            ov.probe_kernel = P.PROBE_M_LOWER
+            _, ip = s.solve(bt, override=ov, raise_on_error=False)
+            row["m_forward_sweep_us"] = round(ip.probe_ms / max(ip.probe_launches, 1) * 1e3, 2)
+        rows.append(row)
+        log(f"[bench] {label}: {row['ms']:.2f} ms, iters {info.outer_iters}, M calls {info.m_calls}, "
+            f"set-up {setup_s:.3f} s" + (f", forward sweep {row['m_forward_sweep_us']} us"
+                                         if "m_forward_sweep_us" in row else ""))
+        s.close()
+
+    run("fp16-F3R, two-sweep M", P.VARIANT_FP16, P.M_SGS, 112)
+    for nb in (112, 1024, 8192):
+        run(f"fp16-F3R, block-Jacobi ILU(0), {nb} blocks", P.VARIANT_FP16, P.M_ILU, nb)
+    run("fp64-F3R, block-Jacobi ILU(0), 112 blocks", P.VARIANT_FP64, P.M_ILU, 112)
+    Asp = A.to_scipy()
+    if abs(Asp - Asp.T).max() == 0.0:  # CG for symmetric matrices only
+        run("fp64 CG, block-Jacobi ILU(0), 112 blocks", P.VARIANT_FP16, P.M_ILU, 112, "cg")
+    run("fp64 FGMRES(64), block-Jacobi ILU(0), 112 blocks", P.VARIANT_FP16, P.M_ILU, 112, "fgmres")
+    return {"ilu": args.workload, "workload": f"{args.workload}: {desc} (n={A.n}, nnz={A.nnz})",
+            "tol": 1e-10, "steps": args.steps, "warmup": args.warmup, "rows": rows}
+
+
 def bench_batch(args, P, W, torch):
     """Batched solve in both modes (one persistent launch; lockstep per-kernel
     path) against the same systems solved one at a time."""
@@ -309,6 +360,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="poisson3d_128", choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--ilu", action="store_true",
+                    help="block-Jacobi ILU(0) as M against the two-sweep M on the workload")
     ap.add_argument("--ablation", action="store_true",
                     help="time the parameter studies of Sec. 6 on the workload instead of the metric")
     ap.add_argument("--cpu-outer", type=int, default=1)
@@ -346,6 +399,9 @@ def main():
         return
     if args.ablation:
         print(json.dumps(bench_ablation(args, P, W, torch)), flush=True)
+        return
+    if args.ilu:
+        print(json.dumps(bench_ilu(args, P, W, torch)), flush=True)
         return
     gen, desc, extra = WORKLOADS[name]
     A = gen(W)
