@@ -11,6 +11,12 @@
 // in-block rows it depends on, the rows of a level are independent, and a
 // workgroup barrier separates the levels.  Rows are stored sorted by level
 // per block (rows[r0 .. r1)), with level boundaries lptr[r0 + b + l].
+// For the sweeps, each row's in-block factor entries are also packed in
+// that order (position q of block b: entries ptr[r0 + b + q] ..
+// ptr[r0 + b + q + 1], columns as offsets from r0, values per stored
+// precision, U's diagonal at r0 + q), inside the block's own CSR range
+// [rp[r0], rp[r1]); a level then reads its rows' entries with one
+// dependent load instead of walking the device format.
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -29,6 +35,13 @@ struct IluDesc {
   const int* rows_up = nullptr;  // backward sweep order (upper dependencies)
   const int* lptr_up = nullptr;
   const int* nlev_up = nullptr;
+  const int* ptr_lo = nullptr;   // packed entries (n + blocks + 1 each)
+  const int* ptr_up = nullptr;
+  const int* col_lo = nullptr;   // offsets from the block's first row
+  const int* col_up = nullptr;
+  const void* val_lo[4] = {};    // per precision tag held by M
+  const void* val_up[4] = {};
+  const void* diag_up[4] = {};   // u_ii at each backward position
 };
 
 // Writable arrays of the schedule, filled at set-up.
@@ -36,6 +49,10 @@ struct IluBuild {
   int blocks = 0;
   int *lev = nullptr, *rows_lo = nullptr, *lptr_lo = nullptr, *nlev_lo = nullptr;
   int *rows_up = nullptr, *lptr_up = nullptr, *nlev_up = nullptr;
+  int *ptr_lo = nullptr, *ptr_up = nullptr, *col_lo = nullptr, *col_up = nullptr;
+  void* val_lo[4] = {};
+  void* val_up[4] = {};
+  void* diag_up[4] = {};
 };
 
 // level schedules of both sweeps (A's pattern, in-block couplings only)
@@ -46,6 +63,10 @@ hipError_t ilu_schedule(hipStream_t st, const SellDesc& A, const IluBuild& b);
 // SF_RANGE in *flags
 hipError_t ilu_factor(hipStream_t st, const SellDesc& A, const IluBuild& b, double* v64,
                       void* const narrow[4], int* flags);
+// packs the factors (M's value arrays mv[t], device format) for the sweeps;
+// rp: CSR row pointers of A (bounds of each block's packed range)
+hipError_t ilu_pack(hipStream_t st, const SellDesc& A, const IluBuild& b, const int32_t* rp,
+                    const void* const mv[4]);
 
 // t = L^-1 r (input as in m_apply_w), y = U^-1 t in place of t with the
 // epilogue of m_apply_g applied to y

@@ -137,14 +137,78 @@ __global__ void k_ilu_finish(int64_t count, const double* __restrict__ v, void* 
   if (bad) atomicOr(flags, bad);
 }
 
-template <class TI, class TM, class TT, class Q, class LD>
-__global__ __launch_bounds__(kIluThreads) void k_ilu_fwd(SellDesc A, IluDesc D, const TM* __restrict__ mv,
+// Offsets of each position's in-block entries inside the block's CSR range
+// (first thread of the block, sequentially); the block's end follows its
+// last position, hence n + blocks + 1 offsets.
+template <class TI>
+__global__ void k_ilu_pack_ptr(SellDesc A, IluBuild b, const int32_t* __restrict__ rp) {
+  if (threadIdx.x != 0) return;
+  const int bk = blockIdx.x;
+  const int64_t n = A.n;
+  const int64_t r0 = blk_start(bk, n, b.blocks), r1 = blk_start(bk + 1, n, b.blocks);
+  for (int dir = 0; dir < 2; dir++) {
+    const int* rows = dir == 0 ? b.rows_lo : b.rows_up;
+    int* ptr = dir == 0 ? b.ptr_lo : b.ptr_up;
+    int acc = rp[r0];
+    for (int64_t q = 0; q < r1 - r0; q++) {
+      ptr[r0 + bk + q] = acc;
+      const int64_t i = rows[r0 + q];
+      const RowAt ra = row_at(A, i);
+      for (int p = 0; p < ra.w; p++) {
+        if (p == ra.dp) continue;
+        const int64_t c = col_at<TI>(A, ra, i, p);
+        if (c == i || c < r0 || c >= r1) continue;
+        if (dir == 0 ? c < i : c > i) acc++;
+      }
+    }
+    ptr[r1 + bk] = acc;  // this block's end
+  }
+}
+
+// Entries of one position in column order; cols when write_cols.
+template <class TI, class TM>
+__global__ void k_ilu_pack_fill(SellDesc A, IluBuild b, const TM* __restrict__ mv, TM* val_lo,
+                                TM* val_up, TM* diag_up, int write_cols) {
+  const int64_t pos = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t n = A.n;
+  if (pos >= n) return;
+  // the block of this position (positions r0 .. r1 belong to block b)
+  int64_t bk = (pos * b.blocks) / n;
+  while (bk + 1 <= b.blocks && blk_start(bk + 1, n, b.blocks) <= pos) bk++;
+  while (bk > 0 && blk_start(bk, n, b.blocks) > pos) bk--;
+  const int64_t r0 = blk_start(bk, n, b.blocks), r1 = blk_start(bk + 1, n, b.blocks);
+  for (int dir = 0; dir < 2; dir++) {
+    const int64_t i = (dir == 0 ? b.rows_lo : b.rows_up)[pos];
+    int e = (dir == 0 ? b.ptr_lo : b.ptr_up)[pos + bk];
+    const RowAt ra = row_at(A, i);
+    for (int p = 0; p < ra.w; p++) {
+      if (p == ra.dp) continue;
+      const int64_t c = col_at<TI>(A, ra, i, p);
+      if (c == i || c < r0 || c >= r1) continue;
+      if (dir == 0 ? c < i : c > i) {
+        if (write_cols) (dir == 0 ? b.col_lo : b.col_up)[e] = (int)(c - r0);
+        (dir == 0 ? val_lo : val_up)[e] = mv[at(ra, p)];
+        e++;
+      }
+    }
+    if (dir == 1) diag_up[pos] = mv[at(ra, ra.dp)];
+  }
+}
+
+// The block's part of t lives in LDS when it fits (lds = true): a level
+// then reads the previous levels' results from LDS instead of L2, and the
+// block copies its rows to t once at the end.
+template <class TM, class TT, class Q, class LD, bool LDS>
+__global__ __launch_bounds__(kIluThreads) void k_ilu_fwd(SellDesc A, IluDesc D, const TM* __restrict__ vl,
                                                          LD ld, TT* __restrict__ t, const int* stop,
                                                          int64_t* cntr) {
+  extern __shared__ __align__(16) unsigned char ilu_lds[];
+  TT* tl = reinterpret_cast<TT*>(ilu_lds);
   if (cntr && blockIdx.x == 0 && threadIdx.x == 0) *cntr += 1;
   if (read_flag(stop)) return;  // one system: the whole launch is stopped or not
   const int bk = blockIdx.x;
-  const int64_t r0 = blk_start(bk, A.n, D.blocks);
+  const int64_t r0 = blk_start(bk, A.n, D.blocks), r1 = blk_start(bk + 1, A.n, D.blocks);
+  TT* tb = LDS ? tl : t + r0;  // the block's rows, from its first one
   ld.at_sys(0, A.sys);
   ld.init();
   const int* lptr = D.lptr_lo + r0 + bk;
@@ -152,47 +216,51 @@ __global__ __launch_bounds__(kIluThreads) void k_ilu_fwd(SellDesc A, IluDesc D, 
   for (int l = 0; l < nl; l++) {
     for (int q = lptr[l] + (int)threadIdx.x; q < lptr[l + 1]; q += kIluThreads) {
       const int64_t i = D.rows_lo[r0 + q];
-      const RowAt ra = row_at(A, i);
+      const int p0 = D.ptr_lo[r0 + bk + q], p1 = D.ptr_lo[r0 + bk + q + 1];
       Q acc = ld(i);
-      for (int p = 0; p < ra.dp; p++) {
-        const int64_t k = col_at<TI>(A, ra, i, p);
-        if (k == i || k < r0) continue;
-        acc = acc - widen<Q>(mv[at(ra, p)]) * widen<Q>(t[k]);
-      }
-      t[i] = round_to<TT>(acc);
+      for (int p = p0; p < p1; p++) acc = acc - widen<Q>(vl[p]) * widen<Q>(tb[D.col_lo[p]]);
+      tb[i - r0] = round_to<TT>(acc);
     }
     __syncthreads();
   }
+  if (LDS)
+    for (int64_t i = r0 + threadIdx.x; i < r1; i += kIluThreads) t[i] = tl[i - r0];
 }
 
-template <class TI, class TM, class TT, class Q, class EPI>
-__global__ __launch_bounds__(kIluThreads) void k_ilu_bwd(SellDesc A, IluDesc D, const TM* __restrict__ mv,
-                                                         TT* __restrict__ t, EPI epi, const int* stop) {
+template <class TM, class TT, class Q, class EPI, bool LDS>
+__global__ __launch_bounds__(kIluThreads) void k_ilu_bwd(SellDesc A, IluDesc D, const TM* __restrict__ vu,
+                                                         const TM* __restrict__ du, TT* __restrict__ t,
+                                                         EPI epi, const int* stop) {
+  extern __shared__ __align__(16) unsigned char ilu_lds[];
+  TT* tl = reinterpret_cast<TT*>(ilu_lds);
   if (read_flag(stop)) return;
   const int bk = blockIdx.x;
   const int64_t r0 = blk_start(bk, A.n, D.blocks), r1 = blk_start(bk + 1, A.n, D.blocks);
+  TT* tb = LDS ? tl : t + r0;
   epi.at_sys(0, A.sys);
   epi.init();
+  if (LDS) {
+    for (int64_t i = r0 + threadIdx.x; i < r1; i += kIluThreads) tl[i - r0] = t[i];
+    __syncthreads();
+  }
   const int* lptr = D.lptr_up + r0 + bk;
   const int nl = D.nlev_up[bk];
   for (int l = 0; l < nl; l++) {
     for (int q = lptr[l] + (int)threadIdx.x; q < lptr[l + 1]; q += kIluThreads) {
       const int64_t i = D.rows_up[r0 + q];
-      const RowAt ra = row_at(A, i);
+      const int p0 = D.ptr_up[r0 + bk + q], p1 = D.ptr_up[r0 + bk + q + 1];
       epi.prefetch(0, i);
-      Q acc = widen<Q>(t[i]);
-      for (int p = ra.dp + 1; p < ra.w; p++) {
-        const int64_t j = col_at<TI>(A, ra, i, p);
-        if (j == i || j >= r1) continue;
-        acc = acc - widen<Q>(mv[at(ra, p)]) * widen<Q>(t[j]);
-      }
-      const Q yq = acc / widen<Q>(mv[at(ra, ra.dp)]);
+      Q acc = widen<Q>(tb[i - r0]);
+      for (int p = p0; p < p1; p++) acc = acc - widen<Q>(vu[p]) * widen<Q>(tb[D.col_up[p]]);
+      const Q yq = acc / widen<Q>(du[r0 + q]);
       const TT y = round_to<TT>(yq);
-      t[i] = y;
+      tb[i - r0] = y;
       epi(0, i, y);
     }
     __syncthreads();
   }
+  if (LDS)
+    for (int64_t i = r0 + threadIdx.x; i < r1; i += kIluThreads) t[i] = tl[i - r0];
 }
 
 }  // namespace
@@ -233,15 +301,51 @@ hipError_t ilu_factor(hipStream_t st, const SellDesc& A, const IluBuild& b, doub
   return hipGetLastError();
 }
 
+hipError_t ilu_pack(hipStream_t st, const SellDesc& A, const IluBuild& b, const int32_t* rp,
+                    const void* const mv[4]) {
+  hipError_t e = with_idx(A.idx16, [&](auto pi) {
+    using TI = TYPE_OF(pi);
+    hipLaunchKernelGGL((k_ilu_pack_ptr<TI>), dim3((unsigned)b.blocks), dim3(64), 0, st, A, b, rp);
+    return hipGetLastError();
+  });
+  if (e != hipSuccess) return e;
+  int first = 1;
+  for (int tg = 0; tg < 4; tg++) {
+    if (!mv[tg]) continue;
+    e = with_idx(A.idx16, [&](auto pi) {
+      using TI = TYPE_OF(pi);
+      return with_type(tg, [&](auto pm) {
+        using TM = TYPE_OF(pm);
+        hipLaunchKernelGGL((k_ilu_pack_fill<TI, TM>), dim3((unsigned)((A.n + 255) / 256)), dim3(256), 0,
+                           st, A, b, (const TM*)mv[tg], (TM*)b.val_lo[tg], (TM*)b.val_up[tg],
+                           (TM*)b.diag_up[tg], first);
+        return hipGetLastError();
+      });
+    });
+    if (e != hipSuccess) return e;
+    first = 0;
+  }
+  return hipSuccess;
+}
+
+// LDS bytes for the largest block's part of a vector of type tt, or 0 when
+// it does not fit in the 64 KB a workgroup may take
+static size_t lds_bytes(const SellDesc& A, int blocks, int tt) {
+  const int64_t rows = (A.n + blocks - 1) / blocks + 1;
+  const size_t bytes = (size_t)rows * type_size(tt);
+  return bytes <= 65536 ? bytes : 0;
+}
+
 hipError_t ilu_apply_fwd(hipStream_t st, const SellDesc& A, const void* mv, int tm, const Basis& in,
                          void* t, int tt, const int* stop, int64_t* cntr) {
   const IluDesc D = *A.ilu;
   const dim3 grid((unsigned)D.blocks), blk(kIluThreads);
-  return with_idx(A.idx16, [&](auto pi) {
-    using TI = TYPE_OF(pi);
-    return with_type(tm, [&](auto pm) {
-      using TM = TYPE_OF(pm);
-      return with_type(tt, [&](auto pt) -> hipError_t {
+  const size_t lb = lds_bytes(A, D.blocks, tt);
+  if (!mv || tm < 0 || tm > 3 || !D.val_lo[tm]) return hipErrorInvalidValue;
+  return with_type(tm, [&](auto pm) {
+    using TM = TYPE_OF(pm);
+    const TM* vl = (const TM*)D.val_lo[tm];
+    return with_type(tt, [&](auto pt) -> hipError_t {
         using TT = TYPE_OF(pt);
         if constexpr (!ok_m<TM, TT>()) {
           return hipErrorInvalidValue;
@@ -250,27 +354,38 @@ hipError_t ilu_apply_fwd(hipStream_t st, const SellDesc& A, const void* mv, int 
           if (in.s) {
             if (in.type != T64 || !is_dbl<TT>::value) return hipErrorInvalidValue;
             LdSBasis<TT, Q> ld{(const double*)in.raw, in.scale, in.s, in.cur, in.stride, 0.0};
-            hipLaunchKernelGGL((k_ilu_fwd<TI, TM, TT, Q, LdSBasis<TT, Q>>), grid, blk, 0, st, A, D,
-                               (const TM*)mv, ld, (TT*)t, stop, cntr);
+            if (lb)
+              hipLaunchKernelGGL((k_ilu_fwd<TM, TT, Q, LdSBasis<TT, Q>, true>), grid, blk, lb, st, A, D,
+                                 vl, ld, (TT*)t, stop, cntr);
+            else
+              hipLaunchKernelGGL((k_ilu_fwd<TM, TT, Q, LdSBasis<TT, Q>, false>), grid, blk, 0, st, A, D,
+                                 vl, ld, (TT*)t, stop, cntr);
             return hipGetLastError();
           }
           if (!in.scale) {
             if (in.type != tt) return hipErrorInvalidValue;
             LdVec<TT, Q> ld{(const TT*)in.raw};
-            hipLaunchKernelGGL((k_ilu_fwd<TI, TM, TT, Q, LdVec<TT, Q>>), grid, blk, 0, st, A, D,
-                               (const TM*)mv, ld, (TT*)t, stop, cntr);
+            if (lb)
+              hipLaunchKernelGGL((k_ilu_fwd<TM, TT, Q, LdVec<TT, Q>, true>), grid, blk, lb, st, A, D,
+                                 vl, ld, (TT*)t, stop, cntr);
+            else
+              hipLaunchKernelGGL((k_ilu_fwd<TM, TT, Q, LdVec<TT, Q>, false>), grid, blk, 0, st, A, D,
+                                 vl, ld, (TT*)t, stop, cntr);
             return hipGetLastError();
           }
           return with_type(in.type, [&](auto pin) -> hipError_t {
             using TIN = TYPE_OF(pin);
             using QQ = wider_t<TIN, Q>;
             LdBasis<TIN, TT, QQ> ld{(const TIN*)in.raw, in.scale, in.cur, in.stride, 0.0};
-            hipLaunchKernelGGL((k_ilu_fwd<TI, TM, TT, QQ, LdBasis<TIN, TT, QQ>>), grid, blk, 0, st, A,
-                               D, (const TM*)mv, ld, (TT*)t, stop, cntr);
+            if (lb)
+              hipLaunchKernelGGL((k_ilu_fwd<TM, TT, QQ, LdBasis<TIN, TT, QQ>, true>), grid, blk, lb,
+                                 st, A, D, vl, ld, (TT*)t, stop, cntr);
+            else
+              hipLaunchKernelGGL((k_ilu_fwd<TM, TT, QQ, LdBasis<TIN, TT, QQ>, false>), grid, blk, 0,
+                                 st, A, D, vl, ld, (TT*)t, stop, cntr);
             return hipGetLastError();
           });
         }
-      });
     });
   });
 }
@@ -281,11 +396,13 @@ hipError_t ilu_apply_bwd(hipStream_t st, const SellDesc& A, const void* mv, int 
   if (mode != 3 && tout != tt) return hipErrorInvalidValue;
   const IluDesc D = *A.ilu;
   const dim3 g((unsigned)D.blocks), b(kIluThreads);
-  return with_idx(A.idx16, [&](auto pi) {
-    using TI = TYPE_OF(pi);
-    return with_type(tm, [&](auto pm) {
-      using TM = TYPE_OF(pm);
-      return with_type(tt, [&](auto pt) -> hipError_t {
+  const size_t lb = lds_bytes(A, D.blocks, tt);
+  if (!mv || tm < 0 || tm > 3 || !D.val_up[tm] || !D.diag_up[tm]) return hipErrorInvalidValue;
+  return with_type(tm, [&](auto pm) {
+    using TM = TYPE_OF(pm);
+    const TM* vu = (const TM*)D.val_up[tm];
+    const TM* du = (const TM*)D.diag_up[tm];
+    return with_type(tt, [&](auto pt) -> hipError_t {
         using TT = TYPE_OF(pt);
         if constexpr (!ok_m<TM, TT>()) {
           return hipErrorInvalidValue;
@@ -293,28 +410,43 @@ hipError_t ilu_apply_bwd(hipStream_t st, const SellDesc& A, const void* mv, int 
           using Q = wider_t<TM, TT>;
           if (mode == 0) {
             EpiStore<TT, Q> ep{(TT*)out, fbflag};
-            hipLaunchKernelGGL((k_ilu_bwd<TI, TM, TT, Q, EpiStore<TT, Q>>), g, b, 0, st, A, D,
-                               (const TM*)mv, (TT*)t, ep, stop);
+            if (lb)
+              hipLaunchKernelGGL((k_ilu_bwd<TM, TT, Q, EpiStore<TT, Q>, true>), g, b, lb, st, A, D,
+                                 vu, du, (TT*)t, ep, stop);
+            else
+              hipLaunchKernelGGL((k_ilu_bwd<TM, TT, Q, EpiStore<TT, Q>, false>), g, b, 0, st, A, D,
+                                 vu, du, (TT*)t, ep, stop);
           } else if (mode == 1) {
             EpiZ1<TT, Q> ep{(TT*)out, omega, fbflag, (Q)0};
-            hipLaunchKernelGGL((k_ilu_bwd<TI, TM, TT, Q, EpiZ1<TT, Q>>), g, b, 0, st, A, D,
-                               (const TM*)mv, (TT*)t, ep, stop);
+            if (lb)
+              hipLaunchKernelGGL((k_ilu_bwd<TM, TT, Q, EpiZ1<TT, Q>, true>), g, b, lb, st, A, D,
+                                 vu, du, (TT*)t, ep, stop);
+            else
+              hipLaunchKernelGGL((k_ilu_bwd<TM, TT, Q, EpiZ1<TT, Q>, false>), g, b, 0, st, A, D,
+                                 vu, du, (TT*)t, ep, stop);
           } else if (mode == 2) {
             EpiZK<TT, Q> ep{(TT*)out, (const TT*)zprev, omega, fbflag, (Q)0};
-            hipLaunchKernelGGL((k_ilu_bwd<TI, TM, TT, Q, EpiZK<TT, Q>>), g, b, 0, st, A, D,
-                               (const TM*)mv, (TT*)t, ep, stop);
+            if (lb)
+              hipLaunchKernelGGL((k_ilu_bwd<TM, TT, Q, EpiZK<TT, Q>, true>), g, b, lb, st, A, D,
+                                 vu, du, (TT*)t, ep, stop);
+            else
+              hipLaunchKernelGGL((k_ilu_bwd<TM, TT, Q, EpiZK<TT, Q>, false>), g, b, 0, st, A, D,
+                                 vu, du, (TT*)t, ep, stop);
           } else {
             if constexpr (!is_dbl<TT>::value) {
               return hipErrorInvalidValue;
             } else {
               EpiS64 ep{(double*)out, s, fbflag, cur, A.n};
-              hipLaunchKernelGGL((k_ilu_bwd<TI, TM, TT, Q, EpiS64>), g, b, 0, st, A, D,
-                                 (const TM*)mv, (TT*)t, ep, stop);
+              if (lb)
+                hipLaunchKernelGGL((k_ilu_bwd<TM, TT, Q, EpiS64, true>), g, b, lb, st, A, D,
+                                   vu, du, (TT*)t, ep, stop);
+              else
+                hipLaunchKernelGGL((k_ilu_bwd<TM, TT, Q, EpiS64, false>), g, b, 0, st, A, D,
+                                   vu, du, (TT*)t, ep, stop);
             }
           }
           return hipGetLastError();
         }
-      });
     });
   });
 }

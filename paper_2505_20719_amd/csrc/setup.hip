@@ -348,6 +348,18 @@ f3r_status build_matrix(hipStream_t st, const f3r_csr* A, const f3r_params* p, c
     HIPCHK(ilu_schedule(st, m.A, ib));
     void* narrow[4] = {nullptr, so.mv[T32], so.mv[T16], so.mv[TB16]};
     HIPCHK(ilu_factor(st, m.A, ib, so.mv[T64] ? (double*)so.mv[T64] : nullptr, narrow, flags));
+    // the factors packed in sweep order for the triangular solves
+    ib.ptr_lo = (int*)al.get((size_t)lp * sizeof(int));
+    ib.ptr_up = (int*)al.get((size_t)lp * sizeof(int));
+    ib.col_lo = (int*)al.get((size_t)nnz * sizeof(int));
+    ib.col_up = (int*)al.get((size_t)nnz * sizeof(int));
+    for (int t = 0; t < 4; t++) {
+      if (!so.mv[t]) continue;
+      ib.val_lo[t] = al.get((size_t)nnz * type_size(t));
+      ib.val_up[t] = al.get((size_t)nnz * type_size(t));
+      ib.diag_up[t] = al.get((size_t)n * type_size(t));
+    }
+    HIPCHK(ilu_pack(st, m.A, ib, m.rp, so.mv));
     al.release(ib.lev);
     m.ilu.blocks = ib.blocks;
     m.ilu.rows_lo = ib.rows_lo;
@@ -356,6 +368,15 @@ f3r_status build_matrix(hipStream_t st, const f3r_csr* A, const f3r_params* p, c
     m.ilu.lptr_up = ib.lptr_up;
     m.ilu.nlev_lo = ib.nlev_lo;
     m.ilu.nlev_up = ib.nlev_up;
+    m.ilu.ptr_lo = ib.ptr_lo;
+    m.ilu.ptr_up = ib.ptr_up;
+    m.ilu.col_lo = ib.col_lo;
+    m.ilu.col_up = ib.col_up;
+    for (int t = 0; t < 4; t++) {
+      m.ilu.val_lo[t] = ib.val_lo[t];
+      m.ilu.val_up[t] = ib.val_up[t];
+      m.ilu.diag_up[t] = ib.diag_up[t];
+    }
     HIPCHK(hipMemcpyAsync(&hflags, flags, sizeof(int), hipMemcpyDeviceToHost, st));
     HIPCHK(hipStreamSynchronize(st));
     if (hflags & SF_MATRIX) return F3R_ERR_MATRIX;
