@@ -91,26 +91,31 @@ def survey_bytes(A):
     }
 
 
-def algorithmic_bytes(A, idx_bits: int, diag: bool):
+def algorithmic_bytes(A, idx_bits: int, layout: int, width: int):
     """Bytes each probed kernel must move per launch in the device format (the
     data structure it reads once and the vectors it reads/writes once), fp16
-    level storage; the diagonal-aligned format reads neither the per-row
-    diagonal positions nor the slice offsets."""
+    level storage.  SELL (1) also reads one 4-byte offset per slice and a
+    2-byte diagonal position per row; the diagonal-aligned format (2) reads
+    neither; the slice-offset format (3) reads no per-entry index but one
+    4-byte offset per slice and position (width per slice; about half of them
+    for a one-sided sweep)."""
     n = A.n
     nnz = A.nnz
     rows = np.repeat(np.arange(n), np.diff(A.row_ptr))
     nl = int(np.count_nonzero(A.col_idx < rows))
     nu = int(np.count_nonzero(A.col_idx > rows))
     sv, si = 2, idx_bits // 8
-    off = 0.0 if diag else n / 16.0  # one 4-byte slice offset per 64 rows
-    kdb = 0 if diag else 2  # diagonal positions, 2 bytes per row
+    ns = (n + 63) // 64
+    off = {1: n / 16.0, 2: 0.0}.get(layout, 4.0 * ns * width)
+    half = {1: n / 16.0, 2: 0.0}.get(layout, 4.0 * ns * (width - 1) / 2)
+    kdb = 2 if layout == 1 else 0  # diagonal positions, 2 bytes per row
     return {
         # W sweep: kd (2n), lower entries, input (fp32 basis at k=1, fp16 r
         # at k=2: 3n on average), t written (2n)
-        "m_lower": (5 + kdb) * n + (sv + si) * nl + off,
+        "m_lower": (5 + kdb) * n + (sv + si) * nl + half,
         # G sweep + update: kd, upper entries, t (2n), z written (2n), z_prev
         # read at k=2 only (n on average)
-        "m_upper": (5 + kdb) * n + (sv + si) * nu + off,
+        "m_upper": (5 + kdb) * n + (sv + si) * nu + half,
         # r = v - A z: all entries, z (2n), fp32 basis (4n), r written (2n)
         "r_residual": 8 * n + (sv + si) * nnz + off,
         # level-2 SpMV + dots: all entries, z (2n), w written (4n), 2.5 fp32
@@ -369,7 +374,7 @@ def main():
     ap.add_argument("--paper-protocol", action="store_true",
                     help="b uniform on [0,1) and tolerance 1e-8 (the paper's runs, Sec. 5) instead of "
                          "b = A x* and 1e-10")
-    ap.add_argument("--layout", choices=("auto", "sell", "diag"), default="auto",
+    ap.add_argument("--layout", choices=("auto", "sell", "diag", "slice"), default="auto",
                     help="device matrix format (default: picked at set-up by padding)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="first run one plain device copy of MIB MiB (reference for HBM byte counters)")
@@ -416,7 +421,8 @@ def main():
     log(f"[bench] {name} n={A.n} nnz={A.nnz}")
 
     t = time.perf_counter()
-    layout = {"auto": P.LAYOUT_AUTO, "sell": P.LAYOUT_SELL, "diag": P.LAYOUT_DIAG}[args.layout]
+    layout = {"auto": P.LAYOUT_AUTO, "sell": P.LAYOUT_SELL, "diag": P.LAYOUT_DIAG,
+              "slice": P.LAYOUT_SLICE}[args.layout]
 
     def params(variant):
         p = P.params_default(variant)
@@ -451,9 +457,12 @@ def main():
         "f3r_fp16_m_calls": info16.m_calls,
         "relres_true": info16.relres_true,
         "err_vs_xstar": err_xstar,
-        "device_format": ("diagonal-aligned " if info16.layout == P.LAYOUT_DIAG else "")
-                         + f"SELL-64, {info16.idx_bits}-bit column indices, "
-                         f"{info16.padded_nnz / A.nnz:.4f} padded/stored entries",
+        "device_format": {P.LAYOUT_SELL: "SELL-64, ", P.LAYOUT_DIAG: "diagonal-aligned SELL-64, ",
+                          P.LAYOUT_SLICE: "diagonal-aligned SELL-64 with column offsets per slice, "}
+                         [info16.layout]
+                         + (f"{info16.idx_bits}-bit column indices, " if info16.idx_bits
+                            else "no per-entry index, ")
+                         + f"{info16.padded_nnz / A.nnz:.4f} padded/stored entries",
         "tuned_shapes": {k: f"{info16.rows_per_lane[i]} rows/lane, chunks of {info16.entry_chunk[i]}"
                          for i, k in enumerate(("m_lower", "m_upper", "r_residual"))},
         "tune_ms": round(info16.tune_ms, 3),
@@ -510,7 +519,8 @@ def main():
 
     # live per-kernel timing of the hot kernels inside one solve (HIP events
     # on the solve's stream, direct launches)
-    ab = algorithmic_bytes(A, info16.idx_bits, info16.layout == P.LAYOUT_DIAG)
+    width = int(round(info16.padded_nnz / (((A.n + 63) // 64) * 64)))
+    ab = algorithmic_bytes(A, info16.idx_bits, info16.layout, width)
     sb = survey_bytes(A)
     probes = {"m_lower": P.PROBE_M_LOWER, "m_upper": P.PROBE_M_UPPER,
               "r_residual": P.PROBE_R_RESIDUAL, "spmv_l2": P.PROBE_SPMV_L2}

@@ -76,11 +76,24 @@ typedef int32_t f3r_status;
 #define F3R_PROBE_SPMV_L0 6    /* SpMV + Gram-Schmidt dots of level 0 */
 
 /* device matrix formats (f3r_params.layout) */
-#define F3R_LAYOUT_AUTO 0      /* DIAG when it stores at most 3 % more entries than SELL */
+#define F3R_LAYOUT_AUTO 0      /* SLICE when it stores at most 25 % more entries than
+                                  the better of SELL and DIAG (not with M_ILU, not
+                                  in the persistent batch kernel), else DIAG when
+                                  it stores at most 3 % more entries than SELL,
+                                  else SELL */
 #define F3R_LAYOUT_SELL 1      /* slices of 64 rows, each padded to its longest row */
 #define F3R_LAYOUT_DIAG 2      /* slices of 64 rows of one common width with every
                                   row's diagonal at one common position: no
                                   per-slice offsets or bounds to load */
+#define F3R_LAYOUT_SLICE 3     /* DIAG whose column offsets are stored once per
+                                  slice: each slice's positions are the sorted
+                                  union of its rows' offsets (a row without an
+                                  entry there holds 0), so no per-entry index
+                                  is read.  At most 64 offsets per slice;
+                                  refused (F3R_ERR_ARG) with M_ILU, whose
+                                  ILU(0) needs each row's own pattern, and by
+                                  the persistent batch kernel (the lockstep
+                                  batch mode supports it) */
 
 /* primary preconditioner M (f3r_params.m_kind) */
 #define F3R_M_SGS 0   /* two-SpMV truncated inverse of the alpha-shifted
@@ -162,7 +175,8 @@ typedef struct {
   double setup_ms;       /* wall time of f3r_setup */
   double solve_ms;       /* wall time of the solve */
   int64_t graph_launches; /* F2-call graphs replayed */
-  int32_t idx_bits;      /* 16 or 32: column index width of the device format */
+  int32_t idx_bits;      /* 16 or 32: column index width of the device format
+                            (0: offsets per slice, no per-entry index) */
   int32_t sell_c;        /* rows per slice of the device format */
   double probe_ms;       /* summed duration of the probed kernel's launches */
   int64_t probe_launches; /* launches of the probed kernel (each probed call is
@@ -171,7 +185,7 @@ typedef struct {
   int32_t rows_per_lane[3]; /* shapes in use: W sweep, G sweep, Richardson residual */
   int32_t entry_chunk[3];   /* entries per load chunk of the same three sweeps */
   double tune_ms;        /* set-up time spent timing the candidate shapes */
-  int32_t layout;        /* F3R_LAYOUT_SELL or F3R_LAYOUT_DIAG: format in use */
+  int32_t layout;        /* F3R_LAYOUT_SELL, _DIAG or _SLICE: format in use */
   int32_t reserved_i;
 } f3r_info;
 

@@ -147,7 +147,7 @@ f3r_status f3r_setup_batched(int32_t count, const f3r_csr* A, const f3r_params* 
         bt->mats.resize((size_t)count);
         bt->ws.resize((size_t)count);
         for (int i = 0; i < count; i++) {
-          const f3r_status bs = build_matrix(bt->st, &A[i], p, need, bt->al, bt->mats[(size_t)i]);
+          const f3r_status bs = build_matrix(bt->st, &A[i], p, need, bt->al, bt->mats[(size_t)i], false);
           if (bs != F3R_OK) return bs;
           const MatrixDev& m = bt->mats[(size_t)i];
           bt->ws[(size_t)i] = (char*)bt->al.get(batch_ws_bytes(m.n, p->lev[0].m, p->lev[1].m, p->lev[2].m));

@@ -68,6 +68,7 @@ struct f3r_handle {
   void* idx = nullptr;
   uint16_t* kd = nullptr;
   uint16_t* kd_true = nullptr;  // diagonal-aligned format: true diagonal positions
+  int32_t* ci = nullptr;        // slice-offset format: CSR columns (read-back)
   IluDesc ilu;                  // block-Jacobi ILU(0) schedule when M is ILU
   uint32_t* kdr = nullptr;
   int32_t* rp = nullptr;  // CSR row pointers, kept for debug read-back
@@ -129,6 +130,17 @@ struct f3r_handle {
   void* dalloc(size_t bytes) { return al.get(bytes); }
 };
 
+// format in use and bits of its per-entry index (0: none, offsets per slice)
+static int32_t layout_of(const SellDesc& A) {
+  if (A.idx16 == 2) return F3R_LAYOUT_SLICE;
+  return A.dell_w ? F3R_LAYOUT_DIAG : F3R_LAYOUT_SELL;
+}
+static int32_t idx_bits_of(const SellDesc& A) { return A.idx16 == 2 ? 0 : (A.idx16 ? 16 : 32); }
+static const int32_t* soff_of(const f3r_handle* h) {
+  return h->A.idx16 == 2 ? (const int32_t*)h->A.idx : nullptr;
+}
+
+
 namespace {
 
 void destroy_graphs(f3r_handle* h);
@@ -173,7 +185,7 @@ f3r_status check_params(const f3r_params* p) {
   if (!(p->alpha > 0.0) || !std::isfinite(p->alpha)) return F3R_ERR_ARG;
   if (p->c < 0 || p->max_outer < 1) return F3R_ERR_ARG;
   if (p->m_identity != 0) return F3R_ERR_ARG;  // M = I is not provided
-  if (p->layout < F3R_LAYOUT_AUTO || p->layout > F3R_LAYOUT_DIAG) return F3R_ERR_ARG;
+  if (p->layout < F3R_LAYOUT_AUTO || p->layout > F3R_LAYOUT_SLICE) return F3R_ERR_ARG;
   if (p->m_kind != F3R_M_SGS && p->m_kind != F3R_M_ILU) return F3R_ERR_ARG;
   if (p->m_kind == F3R_M_ILU && p->ilu_blocks < 1) return F3R_ERR_ARG;
   if (p->rows_per_lane != -1 && p->rows_per_lane != 0 && p->rows_per_lane != 1 &&
@@ -944,12 +956,12 @@ f3r_status outer_solve(f3r_handle* h, const double* b, double* x, double tol, in
       info->setup_ms = h->setup_ms;
       info->solve_ms = t1 - t0;
       info->graph_launches = h->graph_launches;
-      info->idx_bits = h->A.idx16 ? 16 : 32;
+      info->idx_bits = idx_bits_of(h->A);
       info->sell_c = 64;
       info->probe_ms = h->probe_ms;
       info->probe_launches = h->probe_n;
       info->padded_nnz = h->padded;
-      info->layout = h->A.dell_w ? F3R_LAYOUT_DIAG : F3R_LAYOUT_SELL;
+      info->layout = layout_of(h->A);
       for (int f = 0; f < 3; f++) {
         info->rows_per_lane[f] = h->kr[f] / 10;
         info->entry_chunk[f] = h->kr[f] % 10;
@@ -1089,6 +1101,7 @@ f3r_status setup_impl(const f3r_csr* A, const f3r_params* p, void* hip_stream, i
     h->idx = (void*)m.A.idx;
     h->kd = (uint16_t*)m.A.kd;
     h->kd_true = m.kd_true;
+    h->ci = m.ci;
     h->ilu = m.ilu;
     if (h->ilu.blocks > 0) h->A.ilu = &h->ilu;
     h->kdr = (uint32_t*)m.A.kdr;
@@ -1430,7 +1443,7 @@ f3r_status f3r_debug_m_values(f3r_handle* h, int32_t prec, double* vals_host) {
   if (!h || !vals_host || !prec_ok(prec) || h->m_shared || !h->mv[prec]) return F3R_ERR_ARG;
   return guarded(h, nullptr, [&]() {
     double* d = (double*)h->dalloc((size_t)h->nnz * 8);
-    HIPCHK(sell_to_csr_values(h->st, h->n, h->rp, h->off, h->kd_true, h->A.dell_kd, h->mv[prec], prec,
+    HIPCHK(sell_to_csr_values(h->st, h->n, h->rp, h->off, h->kd_true, h->A.dell_kd, h->ci, soff_of(h), h->mv[prec], prec,
                               d));
     HIPCHK(hipMemcpyAsync(vals_host, d, (size_t)h->nnz * 8, hipMemcpyDeviceToHost, h->st));
     HIPCHK(hipStreamSynchronize(h->st));
@@ -1443,7 +1456,7 @@ f3r_status f3r_debug_level_values(f3r_handle* h, int32_t prec, double* vals_host
   if (!h || !vals_host || !prec_ok(prec) || !h->ah[prec]) return F3R_ERR_ARG;
   return guarded(h, nullptr, [&]() {
     double* d = (double*)h->dalloc((size_t)h->nnz * 8);
-    HIPCHK(sell_to_csr_values(h->st, h->n, h->rp, h->off, h->kd_true, h->A.dell_kd, h->ah[prec], prec,
+    HIPCHK(sell_to_csr_values(h->st, h->n, h->rp, h->off, h->kd_true, h->A.dell_kd, h->ci, soff_of(h), h->ah[prec], prec,
                               d));
     HIPCHK(hipMemcpyAsync(vals_host, d, (size_t)h->nnz * 8, hipMemcpyDeviceToHost, h->st));
     HIPCHK(hipStreamSynchronize(h->st));
@@ -1711,10 +1724,10 @@ f3r_status krylov_impl(f3r_handle* h, int method, int prec, const double* b, dou
     info->relres_true = rel;
     info->setup_ms = h->setup_ms;
     info->solve_ms = t1 - t0;
-    info->idx_bits = h->A.idx16 ? 16 : 32;
+    info->idx_bits = idx_bits_of(h->A);
     info->sell_c = 64;
     info->padded_nnz = h->padded;
-    info->layout = h->A.dell_w ? F3R_LAYOUT_DIAG : F3R_LAYOUT_SELL;
+    info->layout = layout_of(h->A);
   }
   return status;
 }

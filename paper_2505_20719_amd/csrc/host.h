@@ -60,6 +60,7 @@ struct MatrixDev {
   double gd[4] = {1, 1, 1, 1};  // diagonal of G: round_t(1 / alpha)
   double* s = nullptr;        // s_i = 1 / sqrt(|a_ii|)
   uint16_t* kd_true = nullptr;  // diagonal-aligned format: each row's own diagonal position
+  int32_t* ci = nullptr;        // slice-offset format: CSR columns (for read-back)
   IluDesc ilu;                  // block-Jacobi ILU(0) schedule (blocks = 0: not used)
 };
 
@@ -68,8 +69,10 @@ struct MatrixDev {
 // copies the parameters ask for.  need[t] forces the scaled copy of tag t.
 // Returns F3R_OK or the status of the first failed check; throws DevErr on a
 // HIP error and StatusErr on an allocation failure.
+// allow_slice: the slice-offset format may be chosen (not for the batch
+// kernel, which reads per-entry indices only).
 f3r_status build_matrix(hipStream_t st, const f3r_csr* A, const f3r_params* p, const bool need[4],
-                        DevAllocs& al, MatrixDev& m);
+                        DevAllocs& al, MatrixDev& m, bool allow_slice = true);
 
 // Several systems solved in lockstep by the per-kernel path: one handle whose
 // matrix holds the systems on its diagonal (each padded with identity rows

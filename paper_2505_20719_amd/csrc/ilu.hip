@@ -44,7 +44,7 @@ __device__ __forceinline__ RowAt row_at(const SellDesc& A, int64_t i) {
 }
 template <class TI>
 __device__ __forceinline__ int64_t col_at(const SellDesc& A, const RowAt& r, int64_t i, int p) {
-  return col_of<TI>(((const TI*)A.idx)[r.e0 + (uint32_t)p * kWave], i);
+  return col_of<TI>(idx_lane<TI>((const TI*)A.idx, r.e0, p), i, A.n);
 }
 __device__ __forceinline__ uint32_t at(const RowAt& r, int p) { return r.e0 + (uint32_t)p * kWave; }
 

@@ -47,11 +47,18 @@ struct IluDesc;  // block-Jacobi ILU(0) schedule (ilu.h)
 // filled consistently, so code that reads them computes the same sums; the
 // kernels take the widths and bounds from dell_w/dell_kd instead, which
 // removes the dependent loads before the first entry load of a wave.
+//
+// Slice-offset variant (idx16 = 2, also diagonal-aligned): position k of
+// every row of slice s has the same column offset, idx[s * dell_w + k]
+// (int32), the sorted offsets of the slice's rows below the diagonal ending
+// at dell_kd - 1 and those above it starting at dell_kd + 1; a row without
+// an entry at an offset holds value 0 there (its column, when outside the
+// matrix, replaced by the row's own).  No per-entry index is stored.
 struct SellDesc {
   int64_t n = 0, ns = 0;
   const uint32_t* off = nullptr;
   const void* idx = nullptr;
-  int idx16 = 0;
+  int idx16 = 0;  // 0: int32 columns, 1: int16 offsets, 2: offsets per slice
   const uint16_t* kd = nullptr;
   const uint32_t* kdr = nullptr;
   SysLayout sys;

@@ -28,9 +28,43 @@ template <class T> struct is_dbl : std::is_same<T, double> {};
 template <class A, class B, class C = float> using wider_t =
     typename std::conditional<is_dbl<A>::value || is_dbl<B>::value || is_dbl<C>::value, double, float>::type;
 
-template <class TI> __device__ __forceinline__ int64_t col_of(TI d, int64_t row);
-template <> __device__ __forceinline__ int64_t col_of<int16_t>(int16_t d, int64_t row) { return row + d; }
-template <> __device__ __forceinline__ int64_t col_of<int32_t>(int32_t d, int64_t) { return d; }
+// Column of an entry from what the format stores for it: a 16-bit offset
+// from the row, a 32-bit column, or (slice-offset format) a 32-bit offset
+// shared by the 64 rows of a slice.  A shared offset can point outside the
+// matrix for a row that has no entry there (its value is zero); such a
+// column is replaced by the row's own.
+struct SOff {
+  int32_t d;
+};
+template <class TI> __device__ __forceinline__ int64_t col_of(TI d, int64_t row, int64_t n);
+template <> __device__ __forceinline__ int64_t col_of<int16_t>(int16_t d, int64_t row, int64_t) {
+  return row + d;
+}
+template <> __device__ __forceinline__ int64_t col_of<int32_t>(int32_t d, int64_t, int64_t) { return d; }
+template <> __device__ __forceinline__ int64_t col_of<SOff>(SOff d, int64_t row, int64_t n) {
+  const int64_t c = row + d.d;
+  return (uint64_t)c < (uint64_t)n ? c : row;
+}
+
+// What the format stores for position k of the row whose first element is
+// e0 (e0 = slice base + lane; the slice-offset table has one row of the
+// common width per slice, at e0 / 64).  idx_wave: the position is the same
+// for every row of the slice, so the table read is one wave-uniform load.
+template <class TI> __device__ __forceinline__ TI idx_lane(const TI* idx, uint32_t e0, int k) {
+  return idx[e0 + (uint32_t)k * 64];
+}
+template <> __device__ __forceinline__ SOff idx_lane<SOff>(const SOff* idx, uint32_t e0, int k) {
+  return idx[(e0 >> 6) + (uint32_t)k];
+}
+template <class TI> __device__ __forceinline__ TI idx_wave(const TI* idx, uint32_t e0, int k) {
+  return idx_lane<TI>(idx, e0, k);
+}
+template <> __device__ __forceinline__ SOff idx_wave<SOff>(const SOff* idx, uint32_t e0, int k) {
+  // every lane of a real row computes the same position; a missing row's
+  // own position is also inside the table, so any lane's value is safe
+  const uint32_t j = (uint32_t)__builtin_amdgcn_readfirstlane((int)((e0 >> 6) + (uint32_t)k));
+  return idx[j];
+}
 
 // The KR rows of one lane: row index, first element of the row in the SELL
 // arrays, slice width, and whether the row exists.  A missing row (past n or
@@ -40,6 +74,7 @@ template <> __device__ __forceinline__ int64_t col_of<int32_t>(int32_t d, int64_
 // index, so no offset load precedes the entry loads.
 struct RowSlot {
   int64_t row;
+  int64_t n;
   uint32_t e0;
   int w;
   bool ok;
@@ -76,6 +111,7 @@ __device__ __forceinline__ void make_slots(const SellDesc& A, int64_t gw, int la
     const bool ok = slice < A.ns && row < A.n;
     s[r].ok = ok;
     s[r].row = ok ? row : 0;
+    s[r].n = A.n;
     s[r].e0 = ok ? o0[r] + (uint32_t)lane : 0u;
     s[r].w = ok ? w[r] : 0;
   }
@@ -120,14 +156,14 @@ __device__ __forceinline__ void rows_sum(const TV* __restrict__ val, const TI* _
       for (int u = 0; u < U; u++) {
         const int k = max(min(lo[r] + i0 + u, hi[r] - 1), 0);
         v[r][u] = val[s[r].e0 + (uint32_t)k * 64];
-        d[r][u] = idx[s[r].e0 + (uint32_t)k * 64];
+        d[r][u] = idx_wave<TI>(idx, s[r].e0, k);
       }
     }
     Q xv[KR][U];
 #pragma unroll
     for (int r = 0; r < KR; r++) {
 #pragma unroll
-      for (int u = 0; u < U; u++) xv[r][u] = x(col_of<TI>(d[r][u], s[r].row));
+      for (int u = 0; u < U; u++) xv[r][u] = x(col_of<TI>(d[r][u], s[r].row, s[r].n));
     }
     if (i0 == 0) init(acc);
 #pragma unroll
@@ -249,7 +285,9 @@ template <class F> static hipError_t with_type(int t, F&& f) {
   }
   return hipErrorInvalidValue;
 }
+// idx16: 0 = 32-bit columns, 1 = 16-bit offsets, 2 = offsets per slice
 template <class F> static hipError_t with_idx(int idx16, F&& f) {
+  if (idx16 == 2) return f((SOff*)nullptr);
   return idx16 ? f((int16_t*)nullptr) : f((int32_t*)nullptr);
 }
 #define TYPE_OF(p) typename std::remove_pointer<decltype(p)>::type

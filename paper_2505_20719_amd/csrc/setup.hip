@@ -93,6 +93,67 @@ hipError_t fill_kd(hipStream_t st, int64_t n, uint16_t* kd, int v) {
   return hipGetLastError();
 }
 
+// The sorted union of the column offsets c - i (c != i) over the rows of
+// slice sl, one thread per slice: uni[sl * kSliceUnion ...], lc | uc << 16
+// (counts below and above the diagonal) in luc[sl], or 0xFFFFFFFF when the
+// union has more than kSliceUnion offsets.
+__global__ void k_slice_union(int64_t n, const int32_t* __restrict__ rp, const int32_t* __restrict__ ci,
+                              int32_t* __restrict__ uni, uint32_t* __restrict__ luc) {
+  const int64_t sl = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (sl >= n_slices(n)) return;
+  int32_t* u = uni + sl * kSliceUnion;
+  int cnt = 0;
+  for (int64_t r = sl * 64; r < sl * 64 + 64 && r < n; r++) {
+    for (int64_t k = rp[r]; k < rp[r + 1]; k++) {
+      const int32_t d = (int32_t)((int64_t)ci[k] - r);
+      if (d == 0) continue;
+      int pos = 0;
+      while (pos < cnt && u[pos] < d) pos++;
+      if (pos < cnt && u[pos] == d) continue;
+      if (cnt == kSliceUnion) {
+        luc[sl] = 0xFFFFFFFFu;
+        return;
+      }
+      for (int q = cnt; q > pos; q--) u[q] = u[q - 1];
+      u[pos] = d;
+      cnt++;
+    }
+  }
+  int lc = 0;
+  while (lc < cnt && u[lc] < 0) lc++;
+  luc[sl] = (uint32_t)lc | ((uint32_t)(cnt - lc) << 16);
+}
+
+hipError_t slice_union(hipStream_t st, int64_t n, const int32_t* rp, const int32_t* ci, int32_t* uni,
+                       uint32_t* luc) {
+  const int64_t ns = n_slices(n);
+  hipLaunchKernelGGL(k_slice_union, dim3((unsigned)((ns + 127) / 128)), dim3(128), 0, st, n, rp, ci, uni,
+                     luc);
+  return hipGetLastError();
+}
+
+// Row sl of the slice-offset table (common width w, diagonal at kdp): the
+// slice's lower offsets end at kdp - 1, its upper ones start at kdp + 1,
+// every other position holds offset 0 (no entry).
+__global__ void k_slice_table(int64_t ns, const int32_t* __restrict__ uni, const uint32_t* __restrict__ luc,
+                              int w, int kdp, int32_t* __restrict__ tab) {
+  const int64_t sl = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (sl >= ns) return;
+  const int lc = (int)(luc[sl] & 0xFFFFu), uc = (int)(luc[sl] >> 16);
+  const int32_t* u = uni + sl * kSliceUnion;
+  int32_t* t = tab + sl * w;
+  for (int p = 0; p < w; p++) t[p] = 0;
+  for (int q = 0; q < lc; q++) t[kdp - lc + q] = u[q];
+  for (int q = 0; q < uc; q++) t[kdp + 1 + q] = u[lc + q];
+}
+
+hipError_t slice_table(hipStream_t st, int64_t ns, const int32_t* uni, const uint32_t* luc, int w, int kdp,
+                       int32_t* tab) {
+  hipLaunchKernelGGL(k_slice_table, dim3((unsigned)((ns + 255) / 256)), dim3(256), 0, st, ns, uni, luc, w,
+                     kdp, tab);
+  return hipGetLastError();
+}
+
 template <class T> __device__ __forceinline__ void put(void* p, uint32_t e, double v, int tag,
                                                        int mask, int* bad) {
   if (!p) return;
@@ -115,12 +176,24 @@ __global__ void k_to_sell(int64_t n, const int32_t* __restrict__ rp, const int32
   const int64_t lo = rp[i];
   const int L = len[i];
   const double si = s[i];
-  // position p holds CSR entry p - shift (padding outside [0, L))
+  // position p holds CSR entry p - shift (padding outside [0, L)); with
+  // offsets per slice, the entry whose column is i + soff[p] when the row
+  // has one (the real offsets ascend with p, so one walk finds them all)
   const int shift = dkd >= 0 ? dkd - (int)kd[i] : 0;
+  const int32_t* so = o.soff ? o.soff + sl * w : nullptr;
+  int walk = 0;
   int bad = 0;
   for (int p = 0; p < w; p++) {
     const uint32_t e = base + (uint32_t)p * 64;
-    const int k = p - shift;
+    int k = p - shift;
+    if (so) {
+      k = -1;
+      if (so[p] != 0 || p == dkd) {
+        const int64_t want = i + so[p];
+        while (walk < L && ci[lo + walk] < want) walk++;
+        if (walk < L && ci[lo + walk] == want) k = walk;
+      }
+    }
     int64_t c = i;
     double a = 0.0, ah = 0.0, mvv = 0.0;
     if (k >= 0 && k < L) {
@@ -141,10 +214,13 @@ __global__ void k_to_sell(int64_t n, const int32_t* __restrict__ rp, const int32
         if (c > i) mvv = (-ah / o.alpha) / o.alpha;
       }
     }
-    if (o.idx16)
+    if (o.soff) {
+      // no per-entry index
+    } else if (o.idx16) {
       ((int16_t*)o.idx)[e] = (int16_t)(c - i);
-    else
+    } else {
       ((int32_t*)o.idx)[e] = (int32_t)c;
+    }
     o.a64[e] = a;
     put<double>(o.ah[T64], e, ah, T64, o.range_mask, &bad);
     put<float>(o.ah[T32], e, ah, T32, o.range_mask, &bad);
@@ -182,24 +258,36 @@ hipError_t m_diag(hipStream_t st, double alpha, double* out) {
 
 template <class T>
 __global__ void k_sell_to_csr(int64_t n, const int32_t* __restrict__ rp, const uint32_t* __restrict__ off,
-                              const uint16_t* __restrict__ kdt, int dkd, const T* __restrict__ v,
+                              const uint16_t* __restrict__ kdt, int dkd, const int32_t* __restrict__ ci,
+                              const int32_t* __restrict__ soff, const T* __restrict__ v,
                               double* __restrict__ out) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   const int shift = kdt ? dkd - (int)kdt[i] : 0;
-  const uint32_t base = off[i / 64] + (uint32_t)(i % 64);
-  for (int64_t k = rp[i]; k < rp[i + 1]; k++)
-    out[k] = widen<double>(v[base + (uint32_t)(k - rp[i] + shift) * 64]);
+  const int64_t sl = i / 64;
+  const uint32_t base = off[sl] + (uint32_t)(i % 64);
+  const int w = (int)((off[sl + 1] - off[sl]) / 64);
+  for (int64_t k = rp[i]; k < rp[i + 1]; k++) {
+    int p = (int)(k - rp[i]) + shift;
+    if (soff) {
+      const int64_t d = (int64_t)ci[k] - i;
+      p = dkd;
+      for (int q = 0; q < w && d != 0; q++)
+        if (soff[sl * w + q] == d) p = q;
+    }
+    out[k] = widen<double>(v[base + (uint32_t)p * 64]);
+  }
 }
 
 hipError_t sell_to_csr_values(hipStream_t st, int64_t n, const int32_t* rp, const uint32_t* off,
-                              const uint16_t* kdt, int dkd, const void* v, int t, double* out) {
+                              const uint16_t* kdt, int dkd, const int32_t* ci, const int32_t* soff,
+                              const void* v, int t, double* out) {
   const dim3 g((unsigned)((n + 255) / 256)), b(256);
   switch (t) {
-    case T64: hipLaunchKernelGGL(k_sell_to_csr<double>, g, b, 0, st, n, rp, off, kdt, dkd, (const double*)v, out); break;
-    case T32: hipLaunchKernelGGL(k_sell_to_csr<float>, g, b, 0, st, n, rp, off, kdt, dkd, (const float*)v, out); break;
-    case T16: hipLaunchKernelGGL(k_sell_to_csr<f16>, g, b, 0, st, n, rp, off, kdt, dkd, (const f16*)v, out); break;
-    case TB16: hipLaunchKernelGGL(k_sell_to_csr<bf16>, g, b, 0, st, n, rp, off, kdt, dkd, (const bf16*)v, out); break;
+    case T64: hipLaunchKernelGGL(k_sell_to_csr<double>, g, b, 0, st, n, rp, off, kdt, dkd, ci, soff, (const double*)v, out); break;
+    case T32: hipLaunchKernelGGL(k_sell_to_csr<float>, g, b, 0, st, n, rp, off, kdt, dkd, ci, soff, (const float*)v, out); break;
+    case T16: hipLaunchKernelGGL(k_sell_to_csr<f16>, g, b, 0, st, n, rp, off, kdt, dkd, ci, soff, (const f16*)v, out); break;
+    case TB16: hipLaunchKernelGGL(k_sell_to_csr<bf16>, g, b, 0, st, n, rp, off, kdt, dkd, ci, soff, (const bf16*)v, out); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
@@ -209,7 +297,7 @@ hipError_t sell_to_csr_values(hipStream_t st, int64_t n, const int32_t* rp, cons
 // host driver of the set-up kernels
 // ---------------------------------------------------------------------------
 f3r_status build_matrix(hipStream_t st, const f3r_csr* A, const f3r_params* p, const bool need_in[4],
-                        DevAllocs& al, MatrixDev& m) {
+                        DevAllocs& al, MatrixDev& m, bool allow_slice) {
   if (!A || !A->row_ptr || !A->col_idx || !A->val || A->n <= 0 || A->nnz < A->n) return F3R_ERR_ARG;
   if (A->n >= ((int64_t)1 << 31) - 64 || A->nnz >= ((int64_t)1 << 31)) return F3R_ERR_ARG;
   if (A->row_ptr[0] != 0 || A->row_ptr[A->n] != A->nnz) return F3R_ERR_MATRIX;
@@ -260,14 +348,56 @@ f3r_status build_matrix(hipStream_t st, const f3r_csr* A, const f3r_params* p, c
   const uint64_t dw = (uint64_t)dkd + 1 + dup;
   const uint64_t dacc = (uint64_t)ns * 64 * dw;
   const bool dfits = dacc < 0xFFFFFFF0ull;
-  bool diag = false;
+  const bool ilu = p->m_kind == F3R_M_ILU;
+  // the slice-offset format: union of each slice's column offsets (it has
+  // no per-row pattern, which ILU(0) needs)
+  const bool try_slice = (p->layout == F3R_LAYOUT_SLICE || (p->layout == F3R_LAYOUT_AUTO && allow_slice)) && !ilu;
+  if (p->layout == F3R_LAYOUT_SLICE && (!allow_slice || ilu)) return F3R_ERR_ARG;
+  int32_t* uni = nullptr;
+  uint32_t* lucd = nullptr;
+  uint64_t sw = 0, skd = 0, sacc = 0;
+  bool sfits = false;
+  if (try_slice) {
+    uni = (int32_t*)al.get((size_t)ns * kSliceUnion * 4);
+    lucd = (uint32_t*)al.get((size_t)ns * 4);
+    HIPCHK(slice_union(st, n, m.rp, ci, uni, lucd));
+    std::vector<uint32_t> luc((size_t)ns);
+    HIPCHK(hipMemcpyAsync(luc.data(), lucd, (size_t)ns * 4, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    uint64_t lmax = 0, umax = 0;
+    bool over = false;
+    for (int64_t sidx = 0; sidx < ns; sidx++) {
+      const uint32_t v = luc[(size_t)sidx];
+      if (v == 0xFFFFFFFFu) {
+        over = true;
+        break;
+      }
+      lmax = std::max<uint64_t>(lmax, v & 0xFFFFu);
+      umax = std::max<uint64_t>(umax, v >> 16);
+    }
+    skd = lmax;
+    sw = lmax + 1 + umax;
+    sacc = (uint64_t)ns * 64 * sw;
+    sfits = !over && sacc < 0xFFFFFFF0ull;
+  }
+  bool diag = false, slice = false;
   if (p->layout == F3R_LAYOUT_DIAG) {
     if (!dfits) return F3R_ERR_ARG;
     diag = true;
+  } else if (p->layout == F3R_LAYOUT_SLICE) {
+    if (!sfits) return F3R_ERR_ARG;
+    slice = true;
   } else if (p->layout == F3R_LAYOUT_AUTO) {
     diag = dfits && dacc * 100 <= acc * 103;
+    // no index bytes: taken when it stores at most 25 % more entries than
+    // the better of the other two (the fp64 level still moves fewer bytes)
+    slice = sfits && sacc * 100 <= std::min(acc, diag ? dacc : acc) * 125;
+    if (slice) diag = false;
   }
-  if (diag) {
+  if (slice) {
+    for (int64_t sidx = 0; sidx <= ns; sidx++) off[(size_t)sidx] = (uint32_t)((uint64_t)sidx * 64 * sw);
+    acc = sacc;
+  } else if (diag) {
     for (int64_t sidx = 0; sidx <= ns; sidx++) off[(size_t)sidx] = (uint32_t)((uint64_t)sidx * 64 * dw);
     acc = dacc;
   }
@@ -275,11 +405,21 @@ f3r_status build_matrix(hipStream_t st, const f3r_csr* A, const f3r_params* p, c
   uint32_t* offd = (uint32_t*)al.get((size_t)(ns + 1) * 4);
   HIPCHK(hipMemcpyAsync(offd, off.data(), (size_t)(ns + 1) * 4, hipMemcpyHostToDevice, st));
   SellOut so;
-  so.idx16 = (hflags & SF_IDX32) ? 0 : 1;
-  so.idx = al.get((size_t)acc * (so.idx16 ? 2 : 4));
+  int32_t* stab = nullptr;
+  if (slice) {
+    stab = (int32_t*)al.get((size_t)ns * sw * 4);
+    HIPCHK(slice_table(st, ns, uni, lucd, (int)sw, (int)skd, stab));
+    so.soff = stab;
+    so.idx16 = 2;
+    so.idx = nullptr;
+  } else {
+    so.idx16 = (hflags & SF_IDX32) ? 0 : 1;
+    so.idx = al.get((size_t)acc * (so.idx16 ? 2 : 4));
+  }
+  if (uni) al.release(uni);
+  if (lucd) al.release(lucd);
   so.a64 = (double*)al.get((size_t)acc * 8);
   so.alpha = p->alpha;
-  const bool ilu = p->m_kind == F3R_M_ILU;
   if (ilu && (p->ilu_blocks < 1 || p->ilu_blocks > n)) return F3R_ERR_ARG;
   so.ilu_blocks = ilu ? p->ilu_blocks : 0;
   // M reads the matrix values when it is the alpha = 1 truncated inverse
@@ -301,9 +441,20 @@ f3r_status build_matrix(hipStream_t st, const f3r_csr* A, const f3r_params* p, c
   for (int t = 0; t < 4; t++)
     if (need[t]) so.ah[t] = al.get((size_t)acc * type_size(t));
   so.range_mask = mask;
-  HIPCHK(to_sell(st, n, m.rp, ci, val, m.s, offd, len, kd, diag ? (int)dkd : -1, so, flags));
+  HIPCHK(to_sell(st, n, m.rp, ci, val, m.s, offd, len, kd, diag ? (int)dkd : (slice ? (int)skd : -1), so,
+                 flags));
   uint16_t* kdk = kd;
-  if (diag) {
+  if (slice) {
+    // every row's diagonal at the common position; the columns stay for
+    // reading values back in CSR order
+    kdk = (uint16_t*)al.get((size_t)n * 2);
+    HIPCHK(fill_kd(st, n, kdk, (int)skd));
+    std::fill(kdrh.begin(), kdrh.end(), (uint32_t)(skd | (skd << 16)));
+    HIPCHK(hipMemcpyAsync(kdr, kdrh.data(), (size_t)ns * 4, hipMemcpyHostToDevice, st));
+    m.ci = ci;
+    m.A.dell_w = (int)sw;
+    m.A.dell_kd = (int)skd;
+  } else if (diag) {
     // the kernels see the common diagonal position; the true one is kept
     // for reading values back in CSR order
     kdk = (uint16_t*)al.get((size_t)n * 2);
@@ -328,7 +479,7 @@ f3r_status build_matrix(hipStream_t st, const f3r_csr* A, const f3r_params* p, c
   m.A.n = n;
   m.A.ns = ns;
   m.A.off = offd;
-  m.A.idx = so.idx;
+  m.A.idx = slice ? (const void*)stab : so.idx;
   m.A.idx16 = so.idx16;
   m.A.kd = kdk;
   m.A.kdr = kdr;
@@ -382,8 +533,9 @@ f3r_status build_matrix(hipStream_t st, const f3r_csr* A, const f3r_params* p, c
     if (hflags & SF_MATRIX) return F3R_ERR_MATRIX;
     if (hflags & SF_RANGE) return F3R_ERR_RANGE;
   }
-  // the CSR copies are no longer needed
-  al.release(ci);
+  // the CSR copies are no longer needed (the slice-offset format keeps the
+  // columns for reading values back)
+  if (!slice) al.release(ci);
   al.release(val);
   al.release(len);
   al.release(wdev);

@@ -24,7 +24,7 @@ USE_X0, PERSIST_WEIGHTS, NO_GRAPH, BATCH_LOCKSTEP = 1, 2, 4, 8
 MAX_LEVELS = 8
 
 OK, NOT_CONVERGED = 0, 1
-LAYOUT_AUTO, LAYOUT_SELL, LAYOUT_DIAG = 0, 1, 2  # device matrix formats
+LAYOUT_AUTO, LAYOUT_SELL, LAYOUT_DIAG, LAYOUT_SLICE = 0, 1, 2, 3  # device matrix formats
 M_SGS, M_ILU = 0, 1  # primary preconditioner: two-sweep truncated inverse, block-Jacobi ILU(0)
 CG, BICGSTAB = 0, 1  # comparison solvers of Sec. 5
 ERR_ARG, ERR_MATRIX, ERR_RANGE, ERR_NOMEM, ERR_DEVICE, ERR_BREAKDOWN = -1, -2, -3, -4, -5, -6

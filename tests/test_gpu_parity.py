@@ -53,8 +53,12 @@ MATS = {
 }
 
 
-# both device formats: SELL (1) and diagonal-aligned (2)
-LAYOUTS = [1, 2]
+# the device formats: SELL (1), diagonal-aligned (2) and diagonal-aligned
+# with offsets per slice (3); the 3x3-block elasticity matrix has more than
+# 64 column offsets per slice, so it has no slice-offset form (refused, see
+# test_slice_layout_refused)
+LAYOUTS = [1, 2, 3]
+CASES = [(n, lay) for n in MATS for lay in LAYOUTS if not (n == "elastic_6" and lay == 3)]
 
 
 def params_of(variant=0, layout=0):
@@ -71,8 +75,7 @@ def pair(name, variant=0, layout=0):
     return A, g, o
 
 
-@pytest.mark.parametrize("layout", LAYOUTS)
-@pytest.mark.parametrize("name", list(MATS))
+@pytest.mark.parametrize("name,layout", CASES)
 def test_setup_bit_exact(name, layout):
     A, g, o = pair(name, 0, layout)
     assert np.array_equal(g.debug_scaling(), o.scaling())
@@ -82,8 +85,7 @@ def test_setup_bit_exact(name, layout):
     assert np.array_equal(g.debug_level_values(O.BF16), o.level_values(O.BF16))
 
 
-@pytest.mark.parametrize("layout", LAYOUTS)
-@pytest.mark.parametrize("name", list(MATS))
+@pytest.mark.parametrize("name,layout", CASES)
 def test_level_spmv_bit_exact(name, layout):
     A, g, o = pair(name, 0, layout)
     rs = np.random.default_rng(3)
@@ -96,8 +98,7 @@ def test_level_spmv_bit_exact(name, layout):
     assert np.array_equal(host(g.debug_spmv(3, dev(x16))), o.spmv(x16, 1, O.F16, O.F32, O.F32))
 
 
-@pytest.mark.parametrize("layout", LAYOUTS)
-@pytest.mark.parametrize("name", list(MATS))
+@pytest.mark.parametrize("name,layout", CASES)
 def test_m_apply_bit_exact(name, layout):
     A, g, o = pair(name, 0, layout)
     r = np.random.default_rng(4).uniform(-1, 1, A.n)
@@ -124,6 +125,39 @@ def test_m_apply_bit_exact(name, layout):
     assert np.array_equal(host(g13.debug_apply_m(O.F16, dev(r16))), o13.apply_m(r16, O.F16, O.F32))
     g13.close()
     o13.close()
+
+
+def test_slice_layout_refused():
+    # more than 64 offsets per slice, ILU(0) (which needs every row's own
+    # pattern) and the batch calls: F3R_ERR_ARG; the automatic choice then
+    # takes another format
+    PP = P()
+    A = MATS["elastic_6"]()
+    with pytest.raises(PP.F3RError) as e:
+        PP.Solver(A.row_ptr, A.col_idx, A.val, params_of(0, PP.LAYOUT_SLICE))
+    assert e.value.status == PP.ERR_ARG
+    g = PP.Solver(A.row_ptr, A.col_idx, A.val, params_of(0, PP.LAYOUT_AUTO))
+    b = torch.ones(A.n, dtype=torch.float64, device="cuda")
+    _, info = g.solve(b)
+    assert info.layout in (PP.LAYOUT_SELL, PP.LAYOUT_DIAG) and info.idx_bits in (16, 32)
+    g.close()
+    B = MATS["poisson2d_64"]()
+    p = params_of(0, PP.LAYOUT_SLICE)
+    p.m_kind, p.ilu_blocks = PP.M_ILU, 4
+    with pytest.raises(PP.F3RError):
+        PP.Solver(B.row_ptr, B.col_idx, B.val, p)
+    p.layout = PP.LAYOUT_AUTO
+    g = PP.Solver(B.row_ptr, B.col_idx, B.val, p)
+    _, info = g.solve(torch.ones(B.n, dtype=torch.float64, device="cuda"))
+    assert info.status == 0 and info.layout == PP.LAYOUT_DIAG
+    g.close()
+    with pytest.raises(PP.F3RError):
+        PP.BatchSolver([(B.row_ptr, B.col_idx, B.val)] * 2, params_of(0, PP.LAYOUT_SLICE))
+    # a stencil: the automatic choice is the slice-offset form, no index bits
+    g = PP.Solver(B.row_ptr, B.col_idx, B.val, params_of(0, PP.LAYOUT_AUTO))
+    _, info = g.solve(torch.ones(B.n, dtype=torch.float64, device="cuda"))
+    assert info.layout == PP.LAYOUT_SLICE and info.idx_bits == 0
+    g.close()
 
 
 @pytest.mark.parametrize("name", ["poisson2d_64", "convdiff_12", "poisson3d_30"])
@@ -208,12 +242,14 @@ def test_end_to_end_poisson2d(variant):
 def test_end_to_end_other_structures(name):
     A, g, o, b, xg, ig, xo, io = _solve_pair(name, 0)
     assert ig.status == 0 and io.status == 0
-    # the other device format gives bitwise the same solve
-    other = P().LAYOUT_SELL if ig.layout == P().LAYOUT_DIAG else P().LAYOUT_DIAG
-    g2 = P().Solver(A.row_ptr, A.col_idx, A.val, params_of(0, other))
-    x2, i2 = g2.solve(dev(b))
-    assert i2.layout == other and np.array_equal(host(x2), xg) and i2.outer_iters == ig.outer_iters
-    g2.close()
+    # the other device formats give bitwise the same solve
+    for other in (P().LAYOUT_SELL, P().LAYOUT_DIAG, P().LAYOUT_SLICE):
+        if other == ig.layout or (name == "elastic_6" and other == P().LAYOUT_SLICE):
+            continue
+        g2 = P().Solver(A.row_ptr, A.col_idx, A.val, params_of(0, other))
+        x2, i2 = g2.solve(dev(b))
+        assert i2.layout == other and np.array_equal(host(x2), xg) and i2.outer_iters == ig.outer_iters
+        g2.close()
     D = A.to_scipy()
     rg = np.linalg.norm(b - D @ xg) / np.linalg.norm(b)
     assert rg < 1e-10
@@ -299,7 +335,7 @@ def test_autotuned_shapes_change_time_not_results():
     A = MATS["poisson3d_30"]()
     xs, b = W.rhs(A, "poisson3d_30")
     ref = None
-    cases = [(kr, ch, lay) for lay in (0, 1, 2)
+    cases = [(kr, ch, lay) for lay in (0, 1, 2, 3)
              for kr, ch in ((0, 0), (-1, 0), (1, 0), (2, 0), (4, 0), (2, 3), (4, 3))]
     for kr, ch, lay in cases:
         prm = PP.params_default(0)
@@ -308,8 +344,8 @@ def test_autotuned_shapes_change_time_not_results():
         g = PP.Solver(A.row_ptr, A.col_idx, A.val, prm)
         x, info = g.solve(dev(b))
         assert info.status == 0
-        # the automatic choice takes the diagonal-aligned format for this stencil
-        assert info.layout == (lay if lay else PP.LAYOUT_DIAG)
+        # the automatic choice takes the slice-offset format for this stencil
+        assert info.layout == (lay if lay else PP.LAYOUT_SLICE)
         shapes = list(info.rows_per_lane)
         assert all(v in (1, 2, 4) for v in shapes)
         assert all(c in (3, 4, 8) for c in info.entry_chunk)
@@ -328,7 +364,7 @@ def test_autotuned_shapes_change_time_not_results():
         else:
             assert torch.equal(x, ref[0]) and np.array_equal(g.history(), ref[1])
         g.close()
-    for kr, ch, lay in ((3, 0, 0), (1, 3, 0), (2, 8, 0), (0, 0, 3), (0, 0, -1), (-2, 0, 0), (0, 4, 0),
+    for kr, ch, lay in ((3, 0, 0), (1, 3, 0), (2, 8, 0), (0, 0, 4), (0, 0, -1), (-2, 0, 0), (0, 4, 0),
                         (-1, 4, 0)):
         bad = PP.params_default(0)
         bad.rows_per_lane, bad.entry_chunk, bad.layout = kr, ch, lay
