@@ -17,6 +17,13 @@
 // precision, U's diagonal at r0 + q), inside the block's own CSR range
 // [rp[r0], rp[r1]); a level then reads its rows' entries with one
 // dependent load instead of walking the device format.
+//
+// When the block's part of the vector fits in LDS, the sweeps run from LDS
+// only: consecutive levels are grouped into windows of at most kIluWinPos
+// positions and kIluWinEnt entries (window w of block b: levels
+// wst[r0 + b + w] .. wst[r0 + b + w + 1]), each window's rows, entry
+// offsets, entries and level bounds are copied to LDS by the whole
+// workgroup, and its levels then read nothing from global memory.
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -26,6 +33,7 @@
 namespace f3r {
 
 constexpr int kIluThreads = 256;
+constexpr int kIluWinPos = 512, kIluWinEnt = 2048;
 
 struct IluDesc {
   int blocks = 0;
@@ -42,6 +50,11 @@ struct IluDesc {
   const void* val_lo[4] = {};    // per precision tag held by M
   const void* val_up[4] = {};
   const void* diag_up[4] = {};   // u_ii at each backward position
+  const int* wst_lo = nullptr;   // first level of each window, then the level count
+  const int* wst_up = nullptr;
+  const int* nwin_lo = nullptr;  // windows per block
+  const int* nwin_up = nullptr;
+  bool win = false;              // every level fits a window (host flag)
 };
 
 // Writable arrays of the schedule, filled at set-up.
@@ -53,6 +66,7 @@ struct IluBuild {
   void* val_lo[4] = {};
   void* val_up[4] = {};
   void* diag_up[4] = {};
+  int *wst_lo = nullptr, *wst_up = nullptr, *nwin_lo = nullptr, *nwin_up = nullptr;
 };
 
 // level schedules of both sweeps (A's pattern, in-block couplings only)
@@ -63,10 +77,12 @@ hipError_t ilu_schedule(hipStream_t st, const SellDesc& A, const IluBuild& b);
 // SF_RANGE in *flags
 hipError_t ilu_factor(hipStream_t st, const SellDesc& A, const IluBuild& b, double* v64,
                       void* const narrow[4], int* flags);
-// packs the factors (M's value arrays mv[t], device format) for the sweeps;
-// rp: CSR row pointers of A (bounds of each block's packed range)
+// packs the factors (M's value arrays mv[t], device format) for the sweeps
+// and groups the levels into LDS windows; rp: CSR row pointers of A
+// (bounds of each block's packed range); sets SF_ILU_NOWIN in *flags when a
+// level does not fit a window
 hipError_t ilu_pack(hipStream_t st, const SellDesc& A, const IluBuild& b, const int32_t* rp,
-                    const void* const mv[4]);
+                    const void* const mv[4], int* flags);
 
 // t = L^-1 r (input as in m_apply_w), y = U^-1 t in place of t with the
 // epilogue of m_apply_g applied to y

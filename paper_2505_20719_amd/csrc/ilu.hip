@@ -195,6 +195,198 @@ __global__ void k_ilu_pack_fill(SellDesc A, IluBuild b, const TM* __restrict__ m
   }
 }
 
+// Levels grouped greedily into windows of at most kIluWinPos positions and
+// kIluWinEnt entries, both sweeps (first thread of the block).
+__global__ void k_ilu_windows(SellDesc A, IluBuild b, int* flags) {
+  if (threadIdx.x != 0) return;
+  const int bk = blockIdx.x;
+  const int64_t r0 = blk_start(bk, A.n, b.blocks);
+  for (int dir = 0; dir < 2; dir++) {
+    const int* lptr = (dir == 0 ? b.lptr_lo : b.lptr_up) + r0 + bk;
+    const int* pk = (dir == 0 ? b.ptr_lo : b.ptr_up) + r0 + bk;
+    int* wst = (dir == 0 ? b.wst_lo : b.wst_up) + r0 + bk;
+    const int nl = (dir == 0 ? b.nlev_lo : b.nlev_up)[bk];
+    int w = 0, pos = 0, ent = 0, bad = 0;
+    wst[0] = 0;
+    for (int l = 0; l < nl; l++) {
+      const int pl = lptr[l + 1] - lptr[l];
+      const int el = pk[lptr[l + 1]] - pk[lptr[l]];
+      if (pl > kIluWinPos || el > kIluWinEnt) bad = 1;
+      if (pos + pl > kIluWinPos || ent + el > kIluWinEnt) {
+        wst[++w] = l;
+        pos = ent = 0;
+      }
+      pos += pl;
+      ent += el;
+    }
+    wst[w + 1] = nl;
+    (dir == 0 ? b.nwin_lo : b.nwin_up)[bk] = w + 1;
+    if (bad) atomicOr(flags, SF_ILU_NOWIN);
+  }
+}
+
+// LDS carve-up of the windowed sweeps: the block's vector, then the window
+// (rows as offsets from r0, entry offsets, level bounds, entry columns,
+// entry values, and U's diagonal for the backward sweep)
+struct WinLds {
+  int row, ptr, lev, col, val, du, total;
+};
+__host__ __device__ inline int al16(int x) { return (x + 15) & ~15; }
+__host__ __device__ inline WinLds win_lds(int rows_max, int stt, int stm) {
+  WinLds w;
+  int o = al16(rows_max * stt);
+  w.row = o;
+  o += al16(kIluWinPos * 4);
+  w.ptr = o;
+  o += al16((kIluWinPos + 1) * 4);
+  w.lev = o;
+  o += al16((kIluWinPos + 1) * 4);
+  w.col = o;
+  o += al16(kIluWinEnt * 4);
+  w.val = o;
+  o += al16(kIluWinEnt * stm);
+  w.du = o;
+  o += al16(kIluWinPos * stm);
+  w.total = o;
+  return w;
+}
+
+// One window of sweep data into LDS (every thread, then a barrier).
+template <class TM>
+__device__ __forceinline__ void load_window(const int* rows, const int* pk, const int* lptr, const int* col,
+                                            const TM* val, const TM* du, int64_t r0, int la, int lb, int qa,
+                                            int qb, int ea, int eb, int* wrow, int* wptr, int* wlev, int* wcol,
+                                            TM* wval, TM* wdu) {
+  for (int q = qa + (int)threadIdx.x; q < qb; q += kIluThreads) {
+    wrow[q - qa] = (int)(rows[r0 + q] - r0);
+    wptr[q - qa] = pk[q] - ea;
+    if (du) wdu[q - qa] = du[r0 + q];
+  }
+  for (int l = la + (int)threadIdx.x; l <= lb; l += kIluThreads) wlev[l - la] = lptr[l] - qa;
+  if (threadIdx.x == 0) wptr[qb - qa] = eb - ea;
+  for (int e = ea + (int)threadIdx.x; e < eb; e += kIluThreads) {
+    wcol[e - ea] = col[e];
+    wval[e - ea] = val[e];
+  }
+  __syncthreads();
+}
+
+// t = L^-1 r from LDS: the input is first placed in the block's LDS vector
+// (each loader returns values of the vector type, so this is exact), every
+// level then reads and writes LDS only.
+template <class TM, class TT, class Q, class LD>
+__global__ __launch_bounds__(kIluThreads) void k_ilu_fwd_win(SellDesc A, IluDesc D, const TM* __restrict__ vl,
+                                                             LD ld, TT* __restrict__ t, const int* stop,
+                                                             int64_t* cntr, WinLds L) {
+  extern __shared__ __align__(16) unsigned char ilu_lds[];
+  if (cntr && blockIdx.x == 0 && threadIdx.x == 0) *cntr += 1;
+  if (read_flag(stop)) return;
+  const int bk = blockIdx.x;
+  const int64_t r0 = blk_start(bk, A.n, D.blocks), r1 = blk_start(bk + 1, A.n, D.blocks);
+  const int rows = (int)(r1 - r0);
+  TT* tl = reinterpret_cast<TT*>(ilu_lds);
+  int* wrow = reinterpret_cast<int*>(ilu_lds + L.row);
+  int* wptr = reinterpret_cast<int*>(ilu_lds + L.ptr);
+  int* wlev = reinterpret_cast<int*>(ilu_lds + L.lev);
+  int* wcol = reinterpret_cast<int*>(ilu_lds + L.col);
+  TM* wval = reinterpret_cast<TM*>(ilu_lds + L.val);
+  ld.at_sys(0, A.sys);
+  ld.init();
+#pragma unroll 4
+  for (int i = threadIdx.x; i < rows; i += kIluThreads) tl[i] = round_to<TT>(ld(r0 + i));
+  const int* lptr = D.lptr_lo + r0 + bk;
+  const int* pk = D.ptr_lo + r0 + bk;
+  const int* wst = D.wst_lo + r0 + bk;
+  const int nw = D.nwin_lo[bk];
+  for (int w = 0; w < nw; w++) {
+    const int la = wst[w], lb = wst[w + 1];
+    const int qa = lptr[la], qb = lptr[lb];
+    __syncthreads();  // the previous window's levels (or the input) are done
+    load_window<TM>(D.rows_lo, pk, lptr, D.col_lo, vl, nullptr, r0, la, lb, qa, qb, pk[qa], pk[qb], wrow,
+                    wptr, wlev, wcol, wval, nullptr);
+    for (int l = 0; l < lb - la; l++) {
+      const int q1 = wlev[l + 1];
+      for (int q = wlev[l] + (int)threadIdx.x; q < q1; q += kIluThreads) {
+        const int i = wrow[q];
+        Q acc = widen<Q>(tl[i]);
+        const int p1 = wptr[q + 1];
+        for (int p = wptr[q]; p < p1; p++) acc = acc - widen<Q>(wval[p]) * widen<Q>(tl[wcol[p]]);
+        tl[i] = round_to<TT>(acc);
+      }
+      __syncthreads();
+    }
+  }
+  for (int i = threadIdx.x; i < rows; i += kIluThreads) t[r0 + i] = tl[i];
+}
+
+// y = U^-1 t from LDS, in place of t; the epilogue is a separate pass over
+// all rows (k_ilu_epi), so no level waits for its loads.
+template <class TM, class TT, class Q>
+__global__ __launch_bounds__(kIluThreads) void k_ilu_bwd_win(SellDesc A, IluDesc D, const TM* __restrict__ vu,
+                                                             const TM* __restrict__ du, TT* __restrict__ t,
+                                                             const int* stop, WinLds L) {
+  extern __shared__ __align__(16) unsigned char ilu_lds[];
+  if (read_flag(stop)) return;
+  const int bk = blockIdx.x;
+  const int64_t r0 = blk_start(bk, A.n, D.blocks), r1 = blk_start(bk + 1, A.n, D.blocks);
+  const int rows = (int)(r1 - r0);
+  TT* tl = reinterpret_cast<TT*>(ilu_lds);
+  int* wrow = reinterpret_cast<int*>(ilu_lds + L.row);
+  int* wptr = reinterpret_cast<int*>(ilu_lds + L.ptr);
+  int* wlev = reinterpret_cast<int*>(ilu_lds + L.lev);
+  int* wcol = reinterpret_cast<int*>(ilu_lds + L.col);
+  TM* wval = reinterpret_cast<TM*>(ilu_lds + L.val);
+  TM* wdu = reinterpret_cast<TM*>(ilu_lds + L.du);
+#pragma unroll 4
+  for (int i = threadIdx.x; i < rows; i += kIluThreads) tl[i] = t[r0 + i];
+  const int* lptr = D.lptr_up + r0 + bk;
+  const int* pk = D.ptr_up + r0 + bk;
+  const int* wst = D.wst_up + r0 + bk;
+  const int nw = D.nwin_up[bk];
+  for (int w = 0; w < nw; w++) {
+    const int la = wst[w], lb = wst[w + 1];
+    const int qa = lptr[la], qb = lptr[lb];
+    __syncthreads();
+    load_window<TM>(D.rows_up, pk, lptr, D.col_up, vu, du, r0, la, lb, qa, qb, pk[qa], pk[qb], wrow, wptr,
+                    wlev, wcol, wval, wdu);
+    for (int l = 0; l < lb - la; l++) {
+      const int q1 = wlev[l + 1];
+      for (int q = wlev[l] + (int)threadIdx.x; q < q1; q += kIluThreads) {
+        const int i = wrow[q];
+        Q acc = widen<Q>(tl[i]);
+        const int p1 = wptr[q + 1];
+        for (int p = wptr[q]; p < p1; p++) acc = acc - widen<Q>(wval[p]) * widen<Q>(tl[wcol[p]]);
+        tl[i] = round_to<TT>(acc / widen<Q>(wdu[q]));
+      }
+      __syncthreads();
+    }
+  }
+  for (int i = threadIdx.x; i < rows; i += kIluThreads) t[r0 + i] = tl[i];
+}
+
+// the G sweep's epilogue over y = t, four rows per thread
+template <class TT, class EPI>
+__global__ __launch_bounds__(256) void k_ilu_epi(SellDesc A, const TT* __restrict__ t, EPI epi,
+                                                 const int* stop) {
+  if (read_flag(stop)) return;
+  epi.at_sys(0, A.sys);
+  epi.init();
+  const int64_t base = ((int64_t)blockIdx.x * 256 * 4) + threadIdx.x;
+  TT y[4];
+#pragma unroll
+  for (int k = 0; k < 4; k++) {
+    const int64_t i = base + (int64_t)k * 256;
+    const int64_t ic = i < A.n ? i : A.n - 1;
+    epi.prefetch(k, ic);
+    y[k] = t[ic];
+  }
+#pragma unroll
+  for (int k = 0; k < 4; k++) {
+    const int64_t i = base + (int64_t)k * 256;
+    if (i < A.n) epi(k, i, y[k]);
+  }
+}
+
 // The block's part of t lives in LDS when it fits (lds = true): a level
 // then reads the previous levels' results from LDS instead of L2, and the
 // block copies its rows to t once at the end.
@@ -302,7 +494,7 @@ hipError_t ilu_factor(hipStream_t st, const SellDesc& A, const IluBuild& b, doub
 }
 
 hipError_t ilu_pack(hipStream_t st, const SellDesc& A, const IluBuild& b, const int32_t* rp,
-                    const void* const mv[4]) {
+                    const void* const mv[4], int* flags) {
   hipError_t e = with_idx(A.idx16, [&](auto pi) {
     using TI = TYPE_OF(pi);
     hipLaunchKernelGGL((k_ilu_pack_ptr<TI>), dim3((unsigned)b.blocks), dim3(64), 0, st, A, b, rp);
@@ -325,7 +517,8 @@ hipError_t ilu_pack(hipStream_t st, const SellDesc& A, const IluBuild& b, const 
     if (e != hipSuccess) return e;
     first = 0;
   }
-  return hipSuccess;
+  hipLaunchKernelGGL(k_ilu_windows, dim3((unsigned)b.blocks), dim3(64), 0, st, A, b, flags);
+  return hipGetLastError();
 }
 
 // LDS bytes for the largest block's part of a vector of type tt, or 0 when
@@ -342,50 +535,48 @@ hipError_t ilu_apply_fwd(hipStream_t st, const SellDesc& A, const void* mv, int 
   const dim3 grid((unsigned)D.blocks), blk(kIluThreads);
   const size_t lb = lds_bytes(A, D.blocks, tt);
   if (!mv || tm < 0 || tm > 3 || !D.val_lo[tm]) return hipErrorInvalidValue;
+  const int rows_max = (int)((A.n + D.blocks - 1) / D.blocks + 1);
   return with_type(tm, [&](auto pm) {
     using TM = TYPE_OF(pm);
     const TM* vl = (const TM*)D.val_lo[tm];
     return with_type(tt, [&](auto pt) -> hipError_t {
-        using TT = TYPE_OF(pt);
-        if constexpr (!ok_m<TM, TT>()) {
-          return hipErrorInvalidValue;
-        } else {
-          using Q = wider_t<TM, TT>;
-          if (in.s) {
-            if (in.type != T64 || !is_dbl<TT>::value) return hipErrorInvalidValue;
-            LdSBasis<TT, Q> ld{(const double*)in.raw, in.scale, in.s, in.cur, in.stride, 0.0};
-            if (lb)
-              hipLaunchKernelGGL((k_ilu_fwd<TM, TT, Q, LdSBasis<TT, Q>, true>), grid, blk, lb, st, A, D,
-                                 vl, ld, (TT*)t, stop, cntr);
-            else
-              hipLaunchKernelGGL((k_ilu_fwd<TM, TT, Q, LdSBasis<TT, Q>, false>), grid, blk, 0, st, A, D,
-                                 vl, ld, (TT*)t, stop, cntr);
-            return hipGetLastError();
-          }
-          if (!in.scale) {
-            if (in.type != tt) return hipErrorInvalidValue;
-            LdVec<TT, Q> ld{(const TT*)in.raw};
-            if (lb)
-              hipLaunchKernelGGL((k_ilu_fwd<TM, TT, Q, LdVec<TT, Q>, true>), grid, blk, lb, st, A, D,
-                                 vl, ld, (TT*)t, stop, cntr);
-            else
-              hipLaunchKernelGGL((k_ilu_fwd<TM, TT, Q, LdVec<TT, Q>, false>), grid, blk, 0, st, A, D,
-                                 vl, ld, (TT*)t, stop, cntr);
-            return hipGetLastError();
-          }
-          return with_type(in.type, [&](auto pin) -> hipError_t {
-            using TIN = TYPE_OF(pin);
-            using QQ = wider_t<TIN, Q>;
-            LdBasis<TIN, TT, QQ> ld{(const TIN*)in.raw, in.scale, in.cur, in.stride, 0.0};
-            if (lb)
-              hipLaunchKernelGGL((k_ilu_fwd<TM, TT, QQ, LdBasis<TIN, TT, QQ>, true>), grid, blk, lb,
-                                 st, A, D, vl, ld, (TT*)t, stop, cntr);
-            else
-              hipLaunchKernelGGL((k_ilu_fwd<TM, TT, QQ, LdBasis<TIN, TT, QQ>, false>), grid, blk, 0,
-                                 st, A, D, vl, ld, (TT*)t, stop, cntr);
-            return hipGetLastError();
-          });
+      using TT = TYPE_OF(pt);
+      if constexpr (!ok_m<TM, TT>()) {
+        return hipErrorInvalidValue;
+      } else {
+        const WinLds wl = win_lds(rows_max, (int)sizeof(TT), (int)sizeof(TM));
+        const bool win = D.win && wl.total <= 65536;
+        // windowed LDS sweep when the block vector and a window fit, else
+        // the LDS vector alone, else the global vector
+        auto go = [&](auto ld, auto qtag) -> hipError_t {
+          using LDT = decltype(ld);
+          using QQ = TYPE_OF(qtag);
+          if (win)
+            hipLaunchKernelGGL((k_ilu_fwd_win<TM, TT, QQ, LDT>), grid, blk, (size_t)wl.total, st, A, D, vl, ld,
+                               (TT*)t, stop, cntr, wl);
+          else if (lb)
+            hipLaunchKernelGGL((k_ilu_fwd<TM, TT, QQ, LDT, true>), grid, blk, lb, st, A, D, vl, ld, (TT*)t,
+                               stop, cntr);
+          else
+            hipLaunchKernelGGL((k_ilu_fwd<TM, TT, QQ, LDT, false>), grid, blk, 0, st, A, D, vl, ld, (TT*)t,
+                               stop, cntr);
+          return hipGetLastError();
+        };
+        using Q = wider_t<TM, TT>;
+        if (in.s) {
+          if (in.type != T64 || !is_dbl<TT>::value) return hipErrorInvalidValue;
+          return go(LdSBasis<TT, Q>{(const double*)in.raw, in.scale, in.s, in.cur, in.stride, 0.0}, (Q*)nullptr);
         }
+        if (!in.scale) {
+          if (in.type != tt) return hipErrorInvalidValue;
+          return go(LdVec<TT, Q>{(const TT*)in.raw}, (Q*)nullptr);
+        }
+        return with_type(in.type, [&](auto pin) -> hipError_t {
+          using TIN = TYPE_OF(pin);
+          using QQ = wider_t<TIN, Q>;
+          return go(LdBasis<TIN, TT, QQ>{(const TIN*)in.raw, in.scale, in.cur, in.stride, 0.0}, (QQ*)nullptr);
+        });
+      }
     });
   });
 }
@@ -398,55 +589,44 @@ hipError_t ilu_apply_bwd(hipStream_t st, const SellDesc& A, const void* mv, int 
   const dim3 g((unsigned)D.blocks), b(kIluThreads);
   const size_t lb = lds_bytes(A, D.blocks, tt);
   if (!mv || tm < 0 || tm > 3 || !D.val_up[tm] || !D.diag_up[tm]) return hipErrorInvalidValue;
+  const int rows_max = (int)((A.n + D.blocks - 1) / D.blocks + 1);
   return with_type(tm, [&](auto pm) {
     using TM = TYPE_OF(pm);
     const TM* vu = (const TM*)D.val_up[tm];
     const TM* du = (const TM*)D.diag_up[tm];
     return with_type(tt, [&](auto pt) -> hipError_t {
-        using TT = TYPE_OF(pt);
-        if constexpr (!ok_m<TM, TT>()) {
-          return hipErrorInvalidValue;
-        } else {
-          using Q = wider_t<TM, TT>;
-          if (mode == 0) {
-            EpiStore<TT, Q> ep{(TT*)out, fbflag};
-            if (lb)
-              hipLaunchKernelGGL((k_ilu_bwd<TM, TT, Q, EpiStore<TT, Q>, true>), g, b, lb, st, A, D,
-                                 vu, du, (TT*)t, ep, stop);
-            else
-              hipLaunchKernelGGL((k_ilu_bwd<TM, TT, Q, EpiStore<TT, Q>, false>), g, b, 0, st, A, D,
-                                 vu, du, (TT*)t, ep, stop);
-          } else if (mode == 1) {
-            EpiZ1<TT, Q> ep{(TT*)out, omega, fbflag, (Q)0};
-            if (lb)
-              hipLaunchKernelGGL((k_ilu_bwd<TM, TT, Q, EpiZ1<TT, Q>, true>), g, b, lb, st, A, D,
-                                 vu, du, (TT*)t, ep, stop);
-            else
-              hipLaunchKernelGGL((k_ilu_bwd<TM, TT, Q, EpiZ1<TT, Q>, false>), g, b, 0, st, A, D,
-                                 vu, du, (TT*)t, ep, stop);
-          } else if (mode == 2) {
-            EpiZK<TT, Q> ep{(TT*)out, (const TT*)zprev, omega, fbflag, (Q)0};
-            if (lb)
-              hipLaunchKernelGGL((k_ilu_bwd<TM, TT, Q, EpiZK<TT, Q>, true>), g, b, lb, st, A, D,
-                                 vu, du, (TT*)t, ep, stop);
-            else
-              hipLaunchKernelGGL((k_ilu_bwd<TM, TT, Q, EpiZK<TT, Q>, false>), g, b, 0, st, A, D,
-                                 vu, du, (TT*)t, ep, stop);
+      using TT = TYPE_OF(pt);
+      if constexpr (!ok_m<TM, TT>()) {
+        return hipErrorInvalidValue;
+      } else {
+        using Q = wider_t<TM, TT>;
+        const WinLds wl = win_lds(rows_max, (int)sizeof(TT), (int)sizeof(TM));
+        const bool win = D.win && wl.total <= 65536;
+        auto go = [&](auto ep) -> hipError_t {
+          using EPI = decltype(ep);
+          if (win) {
+            hipLaunchKernelGGL((k_ilu_bwd_win<TM, TT, Q>), g, b, (size_t)wl.total, st, A, D, vu, du, (TT*)t,
+                               stop, wl);
+            hipError_t e = hipGetLastError();
+            if (e != hipSuccess) return e;
+            const unsigned ge = (unsigned)((A.n + 1023) / 1024);
+            hipLaunchKernelGGL((k_ilu_epi<TT, EPI>), dim3(ge), dim3(256), 0, st, A, (const TT*)t, ep, stop);
+          } else if (lb) {
+            hipLaunchKernelGGL((k_ilu_bwd<TM, TT, Q, EPI, true>), g, b, lb, st, A, D, vu, du, (TT*)t, ep, stop);
           } else {
-            if constexpr (!is_dbl<TT>::value) {
-              return hipErrorInvalidValue;
-            } else {
-              EpiS64 ep{(double*)out, s, fbflag, cur, A.n};
-              if (lb)
-                hipLaunchKernelGGL((k_ilu_bwd<TM, TT, Q, EpiS64, true>), g, b, lb, st, A, D,
-                                   vu, du, (TT*)t, ep, stop);
-              else
-                hipLaunchKernelGGL((k_ilu_bwd<TM, TT, Q, EpiS64, false>), g, b, 0, st, A, D,
-                                   vu, du, (TT*)t, ep, stop);
-            }
+            hipLaunchKernelGGL((k_ilu_bwd<TM, TT, Q, EPI, false>), g, b, 0, st, A, D, vu, du, (TT*)t, ep, stop);
           }
           return hipGetLastError();
+        };
+        if (mode == 0) return go(EpiStore<TT, Q>{(TT*)out, fbflag});
+        if (mode == 1) return go(EpiZ1<TT, Q>{(TT*)out, omega, fbflag, (Q)0});
+        if (mode == 2) return go(EpiZK<TT, Q>{(TT*)out, (const TT*)zprev, omega, fbflag, (Q)0});
+        if constexpr (!is_dbl<TT>::value) {
+          return hipErrorInvalidValue;
+        } else {
+          return go(EpiS64{(double*)out, s, fbflag, cur, A.n});
         }
+      }
     });
   });
 }

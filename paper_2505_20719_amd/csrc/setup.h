@@ -13,6 +13,7 @@ enum SetupFlags {
   SF_IDX32 = 2,     // some |col - row| does not fit in int16
   SF_LONGROW = 4,   // a row has more than 65535 entries
   SF_RANGE = 8,     // a narrow copy that is used overflowed (inf)
+  SF_ILU_NOWIN = 16,  // an ILU level exceeds an LDS window (not an error)
 };
 
 // Per row: checks, kd = position of the diagonal, len = row length,

@@ -510,7 +510,11 @@ f3r_status build_matrix(hipStream_t st, const f3r_csr* A, const f3r_params* p, c
       ib.val_up[t] = al.get((size_t)nnz * type_size(t));
       ib.diag_up[t] = al.get((size_t)n * type_size(t));
     }
-    HIPCHK(ilu_pack(st, m.A, ib, m.rp, so.mv));
+    ib.wst_lo = (int*)al.get((size_t)lp * sizeof(int));
+    ib.wst_up = (int*)al.get((size_t)lp * sizeof(int));
+    ib.nwin_lo = (int*)al.get((size_t)p->ilu_blocks * sizeof(int));
+    ib.nwin_up = (int*)al.get((size_t)p->ilu_blocks * sizeof(int));
+    HIPCHK(ilu_pack(st, m.A, ib, m.rp, so.mv, flags));
     al.release(ib.lev);
     m.ilu.blocks = ib.blocks;
     m.ilu.rows_lo = ib.rows_lo;
@@ -523,6 +527,10 @@ f3r_status build_matrix(hipStream_t st, const f3r_csr* A, const f3r_params* p, c
     m.ilu.ptr_up = ib.ptr_up;
     m.ilu.col_lo = ib.col_lo;
     m.ilu.col_up = ib.col_up;
+    m.ilu.wst_lo = ib.wst_lo;
+    m.ilu.wst_up = ib.wst_up;
+    m.ilu.nwin_lo = ib.nwin_lo;
+    m.ilu.nwin_up = ib.nwin_up;
     for (int t = 0; t < 4; t++) {
       m.ilu.val_lo[t] = ib.val_lo[t];
       m.ilu.val_up[t] = ib.val_up[t];
@@ -532,6 +540,7 @@ f3r_status build_matrix(hipStream_t st, const f3r_csr* A, const f3r_params* p, c
     HIPCHK(hipStreamSynchronize(st));
     if (hflags & SF_MATRIX) return F3R_ERR_MATRIX;
     if (hflags & SF_RANGE) return F3R_ERR_RANGE;
+    m.ilu.win = !(hflags & SF_ILU_NOWIN);
   }
   // the CSR copies are no longer needed (the slice-offset format keeps the
   // columns for reading values back)
