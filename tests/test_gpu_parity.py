@@ -127,6 +127,67 @@ def test_m_apply_bit_exact(name, layout):
     o13.close()
 
 
+def _random_banded(n, band, density, seed):
+    """Nonsymmetric random matrix with entries only within +-band of the
+    diagonal (so a slice's offsets fit the slice-offset format), a full
+    diagonal dominating each row, sorted CSR."""
+    import scipy.sparse as sp
+    from workloads.matrices import CSR
+    rs = np.random.default_rng(seed)
+    rows, cols = [], []
+    for i in range(n):
+        lo, hi = max(0, i - band), min(n, i + band + 1)
+        c = np.nonzero(rs.random(hi - lo) < density)[0] + lo
+        rows += [i] * len(c)
+        cols += list(c)
+    M = sp.csr_matrix((rs.standard_normal(len(rows)), (rows, cols)), shape=(n, n)).tolil()
+    rowsum = np.abs(M.toarray()).sum(axis=1)
+    for i in range(n):
+        M[i, i] = 1.5 * rowsum[i] + 1.0
+    M = M.tocsr()
+    M.sort_indices()
+    return CSR(n, M.indptr.astype(np.int32), M.indices.astype(np.int32), M.data.astype(np.float64), "band")
+
+
+def test_slice_layout_irregular_pattern_bit_exact():
+    # rows of one slice with different patterns: most table positions of a
+    # row hold no entry (value 0), and near the first and last rows some
+    # offsets point outside the matrix (replaced by the row's own column);
+    # n = 3000 leaves a ragged last slice.  Set-up copies, every level SpMV
+    # and M match the oracle bit for bit, and the solve is bitwise the one
+    # of the other two formats.
+    PP = P()
+    A = _random_banded(3000, 24, 0.15, seed=21)
+    b = np.random.default_rng(22).uniform(-1, 1, A.n)
+    o = O.Oracle(A.row_ptr, A.col_idx, A.val, O.default_params(O.FP16_F3R))
+    g = PP.Solver(A.row_ptr, A.col_idx, A.val, params_of(0, PP.LAYOUT_SLICE))
+    print("[case] banded n=3000 slice layout", flush=True)
+    assert np.array_equal(g.debug_scaling(), o.scaling())
+    for pr in (O.F64, O.F32, O.F16):
+        assert np.array_equal(g.debug_level_values(pr), o.level_values(pr)), pr
+    x = np.random.default_rng(3).uniform(-1, 1, A.n)
+    assert np.array_equal(host(g.debug_spmv(0, dev(x))), o.spmv(x, scaled=0))
+    x32 = O.round_to(O.F32, x)
+    assert np.array_equal(host(g.debug_spmv(1, dev(x32))), o.spmv(x32, 1, O.F32, O.F32, O.F32))
+    x16 = O.round_to(O.F16, x)
+    assert np.array_equal(host(g.debug_spmv(2, dev(x16))), o.spmv(x16, 1, O.F16, O.F32, O.F32))
+    assert np.array_equal(host(g.debug_apply_m(O.F16, dev(x16))), o.apply_m(x16, O.F16, O.F32))
+    xs, infos = [], []
+    for lay in (PP.LAYOUT_SLICE, PP.LAYOUT_DIAG, PP.LAYOUT_SELL):
+        gl = g if lay == PP.LAYOUT_SLICE else PP.Solver(A.row_ptr, A.col_idx, A.val, params_of(0, lay))
+        xl, il = gl.solve(dev(b), tol=1e-10)
+        assert il.status == 0 and il.layout == lay
+        xs.append(host(xl))
+        infos.append(il)
+        gl.close()
+    assert infos[0].idx_bits == 0
+    assert all(np.array_equal(xs[0], xv) for xv in xs[1:])
+    assert len({i.outer_iters for i in infos}) == 1
+    xo, io = o.solve(b, 1e-10)
+    assert abs(infos[0].outer_iters - io.outer_iters) <= 1
+    o.close()
+
+
 def test_slice_layout_refused():
     # more than 64 offsets per slice, ILU(0) (which needs every row's own
     # pattern) and the batch calls: F3R_ERR_ARG; the automatic choice then
