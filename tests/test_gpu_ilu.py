@@ -162,3 +162,46 @@ def test_ilu_fullsize_poisson3d_128():
     r = np.linalg.norm(b - A.to_scipy() @ host(x)) / np.linalg.norm(b)
     assert info.status == 0 and r < 1e-10 and np.isclose(r, info.relres_true, rtol=1e-6)
     assert info.outer_iters <= 5
+
+
+def _upper_bidiagonal(n):
+    # 4 on the diagonal, -1 at (i, i+1): no row depends on an earlier one
+    # in the forward sweep, so its single level holds every row of a block
+    from workloads.matrices import CSR
+    rp, ci, val = [0], [], []
+    for i in range(n):
+        ci.append(i)
+        val.append(4.0)
+        if i + 1 < n:
+            ci.append(i + 1)
+            val.append(-1.0)
+        rp.append(len(ci))
+    return CSR(n, np.array(rp, np.int32), np.array(ci, np.int32), np.array(val), f"ubi{n}")
+
+
+@pytest.mark.parametrize("case", ["wide_level", "large_block"])
+def test_sweep_variants_bit_exact(case):
+    # the sweeps without LDS windows: a level wider than a window (the
+    # vector alone in LDS) and a block whose vector exceeds the LDS the
+    # sweeps take (fp64, 22,500 rows: the vector in global memory); one
+    # application of M bit-exact against the oracle in fp16 and fp64
+    if case == "wide_level":
+        A, blocks = _upper_bidiagonal(4096), 2
+    else:
+        A, blocks = W.poisson2d(150), 1
+    r = np.random.default_rng(8).uniform(-1, 1, A.n)
+    for variant in (0, 2):
+        p = P().params_default(variant)
+        p.m_kind, p.ilu_blocks = P().M_ILU, blocks
+        q = O.default_params(ORACLE_VARIANT[variant])
+        q.m_kind, q.ilu_blocks = O.M_ILU, blocks
+        print(f"[case] ilu sweep variant {case} n={A.n} blocks={blocks} variant={variant}", flush=True)
+        g = P().Solver(A.row_ptr, A.col_idx, A.val, p)
+        o = O.Oracle(A.row_ptr, A.col_idx, A.val, q)
+        if variant == 0:
+            r16 = O.round_to(O.F16, r)
+            assert np.array_equal(host(g.debug_apply_m(O.F16, dev(r16))), o.apply_m(r16, O.F16, O.F32))
+        else:
+            assert np.array_equal(host(g.debug_apply_m(O.F64, dev(r))), o.apply_m(r, O.F64, O.F64))
+        g.close()
+        o.close()
