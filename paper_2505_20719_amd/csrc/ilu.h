@@ -19,8 +19,9 @@
 // dependent load instead of walking the device format.
 //
 // When the block's part of the vector fits in LDS, the sweeps run from LDS
-// only: consecutive levels are grouped into windows of at most kIluWinPos
-// positions and kIluWinEnt entries (window w of block b: levels
+// only: consecutive levels are grouped into windows of at most win_pos
+// positions and win_ent entries, sized at set-up from the LDS a workgroup
+// may take (window w of block b: levels
 // wst[r0 + b + w] .. wst[r0 + b + w + 1]), each window's rows, entry
 // offsets, entries and level bounds are copied to LDS by the whole
 // workgroup, and its levels then read nothing from global memory.
@@ -33,7 +34,10 @@
 namespace f3r {
 
 constexpr int kIluThreads = 256;
-constexpr int kIluWinPos = 512, kIluWinEnt = 2048;
+// set-up: window capacities for a device whose workgroups may take
+// lds_max bytes of LDS and that has cus compute units (the block vector in
+// fp16 plus one window fit in each workgroup's share)
+void ilu_window_size(int64_t n, int blocks, int lds_max, int cus, int* win_pos, int* win_ent);
 
 struct IluDesc {
   int blocks = 0;
@@ -55,6 +59,8 @@ struct IluDesc {
   const int* nwin_lo = nullptr;  // windows per block
   const int* nwin_up = nullptr;
   bool win = false;              // every level fits a window (host flag)
+  int win_pos = 0, win_ent = 0;  // window capacities (positions, entries)
+  int lds_max = 65536;           // LDS bytes a workgroup may take
 };
 
 // Writable arrays of the schedule, filled at set-up.
@@ -67,6 +73,7 @@ struct IluBuild {
   void* val_up[4] = {};
   void* diag_up[4] = {};
   int *wst_lo = nullptr, *wst_up = nullptr, *nwin_lo = nullptr, *nwin_up = nullptr;
+  int win_pos = 0, win_ent = 0;
 };
 
 // level schedules of both sweeps (A's pattern, in-block couplings only)

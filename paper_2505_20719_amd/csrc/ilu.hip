@@ -195,8 +195,8 @@ __global__ void k_ilu_pack_fill(SellDesc A, IluBuild b, const TM* __restrict__ m
   }
 }
 
-// Levels grouped greedily into windows of at most kIluWinPos positions and
-// kIluWinEnt entries, both sweeps (first thread of the block).
+// Levels grouped greedily into windows of at most win_pos positions and
+// win_ent entries, both sweeps (first thread of the block).
 __global__ void k_ilu_windows(SellDesc A, IluBuild b, int* flags) {
   if (threadIdx.x != 0) return;
   const int bk = blockIdx.x;
@@ -211,8 +211,8 @@ __global__ void k_ilu_windows(SellDesc A, IluBuild b, int* flags) {
     for (int l = 0; l < nl; l++) {
       const int pl = lptr[l + 1] - lptr[l];
       const int el = pk[lptr[l + 1]] - pk[lptr[l]];
-      if (pl > kIluWinPos || el > kIluWinEnt) bad = 1;
-      if (pos + pl > kIluWinPos || ent + el > kIluWinEnt) {
+      if (pl > b.win_pos || el > b.win_ent) bad = 1;
+      if (pos + pl > b.win_pos || ent + el > b.win_ent) {
         wst[++w] = l;
         pos = ent = 0;
       }
@@ -232,21 +232,21 @@ struct WinLds {
   int row, ptr, lev, col, val, du, total;
 };
 __host__ __device__ inline int al16(int x) { return (x + 15) & ~15; }
-__host__ __device__ inline WinLds win_lds(int rows_max, int stt, int stm) {
+__host__ __device__ inline WinLds win_lds(int rows_max, int stt, int stm, int pos, int ent) {
   WinLds w;
   int o = al16(rows_max * stt);
   w.row = o;
-  o += al16(kIluWinPos * 4);
+  o += al16(pos * 4);
   w.ptr = o;
-  o += al16((kIluWinPos + 1) * 4);
+  o += al16((pos + 1) * 4);
   w.lev = o;
-  o += al16((kIluWinPos + 1) * 4);
+  o += al16((pos + 1) * 4);
   w.col = o;
-  o += al16(kIluWinEnt * 4);
+  o += al16(ent * 4);
   w.val = o;
-  o += al16(kIluWinEnt * stm);
+  o += al16(ent * stm);
   w.du = o;
-  o += al16(kIluWinPos * stm);
+  o += al16(pos * stm);
   w.total = o;
   return w;
 }
@@ -523,17 +523,39 @@ hipError_t ilu_pack(hipStream_t st, const SellDesc& A, const IluBuild& b, const 
 
 // LDS bytes for the largest block's part of a vector of type tt, or 0 when
 // it does not fit in the 64 KB a workgroup may take
-static size_t lds_bytes(const SellDesc& A, int blocks, int tt) {
+static size_t lds_bytes(const SellDesc& A, int blocks, int tt, int lds_max) {
   const int64_t rows = (A.n + blocks - 1) / blocks + 1;
   const size_t bytes = (size_t)rows * type_size(tt);
-  return bytes <= 65536 ? bytes : 0;
+  return bytes <= (size_t)lds_max ? bytes : 0;
+}
+
+void ilu_window_size(int64_t n, int blocks, int lds_max, int cus, int* win_pos, int* win_ent) {
+  // the workgroups that share a compute unit share its LDS; per position
+  // 14 bytes (row, entry offset, level bound, fp16 diagonal), per entry 6
+  // (column, fp16 value), about four entries per position; no window needs
+  // more positions than its block has rows
+  // (at most 8 workgroups of kIluThreads threads fit a compute unit's 32
+  // wave slots)
+  int64_t per_cu = cus > 0 ? (blocks + cus - 1) / cus : 1;
+  per_cu = per_cu < 1 ? 1 : (per_cu > 8 ? 8 : per_cu);
+  const int64_t lds = (int64_t)lds_max / per_cu;
+  const int64_t rows = (n + blocks - 1) / blocks + 1;
+  const int64_t budget = lds - al16((int)(rows * 2)) - 1024;
+  int64_t pos = budget > 0 ? budget / (14 + 4 * 6) : 0;
+  const int64_t cap = (rows + 63) & ~(int64_t)63;
+  pos = pos > cap ? cap : pos;
+  pos = pos > 4096 ? 4096 : pos;
+  pos &= ~(int64_t)63;
+  pos = pos < 64 ? 64 : pos;
+  *win_pos = (int)pos;
+  *win_ent = (int)(4 * pos);
 }
 
 hipError_t ilu_apply_fwd(hipStream_t st, const SellDesc& A, const void* mv, int tm, const Basis& in,
                          void* t, int tt, const int* stop, int64_t* cntr) {
   const IluDesc D = *A.ilu;
   const dim3 grid((unsigned)D.blocks), blk(kIluThreads);
-  const size_t lb = lds_bytes(A, D.blocks, tt);
+  const size_t lb = lds_bytes(A, D.blocks, tt, D.lds_max);
   if (!mv || tm < 0 || tm > 3 || !D.val_lo[tm]) return hipErrorInvalidValue;
   const int rows_max = (int)((A.n + D.blocks - 1) / D.blocks + 1);
   return with_type(tm, [&](auto pm) {
@@ -544,8 +566,8 @@ hipError_t ilu_apply_fwd(hipStream_t st, const SellDesc& A, const void* mv, int 
       if constexpr (!ok_m<TM, TT>()) {
         return hipErrorInvalidValue;
       } else {
-        const WinLds wl = win_lds(rows_max, (int)sizeof(TT), (int)sizeof(TM));
-        const bool win = D.win && wl.total <= 65536;
+        const WinLds wl = win_lds(rows_max, (int)sizeof(TT), (int)sizeof(TM), D.win_pos, D.win_ent);
+        const bool win = D.win && wl.total <= D.lds_max;
         // windowed LDS sweep when the block vector and a window fit, else
         // the LDS vector alone, else the global vector
         auto go = [&](auto ld, auto qtag) -> hipError_t {
@@ -587,7 +609,7 @@ hipError_t ilu_apply_bwd(hipStream_t st, const SellDesc& A, const void* mv, int 
   if (mode != 3 && tout != tt) return hipErrorInvalidValue;
   const IluDesc D = *A.ilu;
   const dim3 g((unsigned)D.blocks), b(kIluThreads);
-  const size_t lb = lds_bytes(A, D.blocks, tt);
+  const size_t lb = lds_bytes(A, D.blocks, tt, D.lds_max);
   if (!mv || tm < 0 || tm > 3 || !D.val_up[tm] || !D.diag_up[tm]) return hipErrorInvalidValue;
   const int rows_max = (int)((A.n + D.blocks - 1) / D.blocks + 1);
   return with_type(tm, [&](auto pm) {
@@ -600,8 +622,8 @@ hipError_t ilu_apply_bwd(hipStream_t st, const SellDesc& A, const void* mv, int 
         return hipErrorInvalidValue;
       } else {
         using Q = wider_t<TM, TT>;
-        const WinLds wl = win_lds(rows_max, (int)sizeof(TT), (int)sizeof(TM));
-        const bool win = D.win && wl.total <= 65536;
+        const WinLds wl = win_lds(rows_max, (int)sizeof(TT), (int)sizeof(TM), D.win_pos, D.win_ent);
+        const bool win = D.win && wl.total <= D.lds_max;
         auto go = [&](auto ep) -> hipError_t {
           using EPI = decltype(ep);
           if (win) {

@@ -510,6 +510,12 @@ f3r_status build_matrix(hipStream_t st, const f3r_csr* A, const f3r_params* p, c
       ib.val_up[t] = al.get((size_t)nnz * type_size(t));
       ib.diag_up[t] = al.get((size_t)n * type_size(t));
     }
+    // LDS a workgroup may take (gfx950: 160 KB) sizes the sweep windows
+    int dev = 0, lds_max = 65536, cus = 1;
+    HIPCHK(hipGetDevice(&dev));
+    HIPCHK(hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
+    HIPCHK(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+    ilu_window_size(n, p->ilu_blocks, lds_max, cus, &ib.win_pos, &ib.win_ent);
     ib.wst_lo = (int*)al.get((size_t)lp * sizeof(int));
     ib.wst_up = (int*)al.get((size_t)lp * sizeof(int));
     ib.nwin_lo = (int*)al.get((size_t)p->ilu_blocks * sizeof(int));
@@ -541,6 +547,9 @@ f3r_status build_matrix(hipStream_t st, const f3r_csr* A, const f3r_params* p, c
     if (hflags & SF_MATRIX) return F3R_ERR_MATRIX;
     if (hflags & SF_RANGE) return F3R_ERR_RANGE;
     m.ilu.win = !(hflags & SF_ILU_NOWIN);
+    m.ilu.win_pos = ib.win_pos;
+    m.ilu.win_ent = ib.win_ent;
+    m.ilu.lds_max = lds_max;
   }
   // the CSR copies are no longer needed (the slice-offset format keeps the
   // columns for reading values back)
