@@ -61,6 +61,7 @@ struct IluDesc {
   bool win = false;              // every level fits a window (host flag)
   int win_pos = 0, win_ent = 0;  // window capacities (positions, entries)
   int lds_max = 65536;           // LDS bytes a workgroup may take
+  bool chunk = false;            // long rows: entries summed four at a time
 };
 
 // Writable arrays of the schedule, filled at set-up.

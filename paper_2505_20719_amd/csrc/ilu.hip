@@ -230,6 +230,7 @@ __global__ void k_ilu_windows(SellDesc A, IluBuild b, int* flags) {
 // entry values, and U's diagonal for the backward sweep)
 struct WinLds {
   int row, ptr, lev, col, val, du, total;
+  int ent;  // entry capacity of the window
 };
 __host__ __device__ inline int al16(int x) { return (x + 15) & ~15; }
 __host__ __device__ inline WinLds win_lds(int rows_max, int stt, int stm, int pos, int ent) {
@@ -248,7 +249,39 @@ __host__ __device__ inline WinLds win_lds(int rows_max, int stt, int stm, int po
   w.du = o;
   o += al16(pos * stm);
   w.total = o;
+  w.ent = ent;
   return w;
+}
+
+// acc minus the sum over the row's window entries [p0, p1) of val * t[col],
+// in entry order, four at a time: the four columns and values are read
+// together, then the four vector values, then the differences are formed in
+// order; positions past p1 (still inside the window arrays) are masked and
+// read column 0.  Taken for long rows (27-point stencils: 13 entries per
+// sweep row); rows of three entries are faster one entry at a time.
+template <class Q, class TM, class TT>
+__device__ __forceinline__ Q row_sub(Q acc, int p0, int p1, const int* wcol, const TM* wval, const TT* tl,
+                                     int ent) {
+  for (int p = p0; p < p1; p += 4) {
+    int c[4];
+    TM v[4];
+#pragma unroll
+    for (int u = 0; u < 4; u++) {
+      const int pu = min(p + u, ent - 1);
+      const int cw = wcol[pu];
+      c[u] = p + u < p1 ? cw : 0;
+      v[u] = wval[pu];
+    }
+    TT x[4];
+#pragma unroll
+    for (int u = 0; u < 4; u++) x[u] = tl[c[u]];
+#pragma unroll
+    for (int u = 0; u < 4; u++) {
+      const Q t = acc - widen<Q>(v[u]) * widen<Q>(x[u]);
+      acc = p + u < p1 ? t : acc;
+    }
+  }
+  return acc;
 }
 
 // One window of sweep data into LDS (every thread, then a barrier).
@@ -274,7 +307,7 @@ __device__ __forceinline__ void load_window(const int* rows, const int* pk, cons
 // t = L^-1 r from LDS: the input is first placed in the block's LDS vector
 // (each loader returns values of the vector type, so this is exact), every
 // level then reads and writes LDS only.
-template <class TM, class TT, class Q, class LD>
+template <class TM, class TT, class Q, class LD, bool CH>
 __global__ __launch_bounds__(kIluThreads) void k_ilu_fwd_win(SellDesc A, IluDesc D, const TM* __restrict__ vl,
                                                              LD ld, TT* __restrict__ t, const int* stop,
                                                              int64_t* cntr, WinLds L) {
@@ -309,8 +342,12 @@ __global__ __launch_bounds__(kIluThreads) void k_ilu_fwd_win(SellDesc A, IluDesc
       for (int q = wlev[l] + (int)threadIdx.x; q < q1; q += kIluThreads) {
         const int i = wrow[q];
         Q acc = widen<Q>(tl[i]);
-        const int p1 = wptr[q + 1];
-        for (int p = wptr[q]; p < p1; p++) acc = acc - widen<Q>(wval[p]) * widen<Q>(tl[wcol[p]]);
+        if constexpr (CH) {
+          acc = row_sub<Q>(acc, wptr[q], wptr[q + 1], wcol, wval, tl, L.ent);
+        } else {
+          const int p1 = wptr[q + 1];
+          for (int p = wptr[q]; p < p1; p++) acc = acc - widen<Q>(wval[p]) * widen<Q>(tl[wcol[p]]);
+        }
         tl[i] = round_to<TT>(acc);
       }
       __syncthreads();
@@ -321,7 +358,7 @@ __global__ __launch_bounds__(kIluThreads) void k_ilu_fwd_win(SellDesc A, IluDesc
 
 // y = U^-1 t from LDS, in place of t; the epilogue is a separate pass over
 // all rows (k_ilu_epi), so no level waits for its loads.
-template <class TM, class TT, class Q>
+template <class TM, class TT, class Q, bool CH>
 __global__ __launch_bounds__(kIluThreads) void k_ilu_bwd_win(SellDesc A, IluDesc D, const TM* __restrict__ vu,
                                                              const TM* __restrict__ du, TT* __restrict__ t,
                                                              const int* stop, WinLds L) {
@@ -354,8 +391,12 @@ __global__ __launch_bounds__(kIluThreads) void k_ilu_bwd_win(SellDesc A, IluDesc
       for (int q = wlev[l] + (int)threadIdx.x; q < q1; q += kIluThreads) {
         const int i = wrow[q];
         Q acc = widen<Q>(tl[i]);
-        const int p1 = wptr[q + 1];
-        for (int p = wptr[q]; p < p1; p++) acc = acc - widen<Q>(wval[p]) * widen<Q>(tl[wcol[p]]);
+        if constexpr (CH) {
+          acc = row_sub<Q>(acc, wptr[q], wptr[q + 1], wcol, wval, tl, L.ent);
+        } else {
+          const int p1 = wptr[q + 1];
+          for (int p = wptr[q]; p < p1; p++) acc = acc - widen<Q>(wval[p]) * widen<Q>(tl[wcol[p]]);
+        }
         tl[i] = round_to<TT>(acc / widen<Q>(wdu[q]));
       }
       __syncthreads();
@@ -574,8 +615,12 @@ hipError_t ilu_apply_fwd(hipStream_t st, const SellDesc& A, const void* mv, int 
           using LDT = decltype(ld);
           using QQ = TYPE_OF(qtag);
           if (win)
-            hipLaunchKernelGGL((k_ilu_fwd_win<TM, TT, QQ, LDT>), grid, blk, (size_t)wl.total, st, A, D, vl, ld,
-                               (TT*)t, stop, cntr, wl);
+            if (D.chunk)
+              hipLaunchKernelGGL((k_ilu_fwd_win<TM, TT, QQ, LDT, true>), grid, blk, (size_t)wl.total, st, A, D,
+                                 vl, ld, (TT*)t, stop, cntr, wl);
+            else
+              hipLaunchKernelGGL((k_ilu_fwd_win<TM, TT, QQ, LDT, false>), grid, blk, (size_t)wl.total, st, A, D,
+                                 vl, ld, (TT*)t, stop, cntr, wl);
           else if (lb)
             hipLaunchKernelGGL((k_ilu_fwd<TM, TT, QQ, LDT, true>), grid, blk, lb, st, A, D, vl, ld, (TT*)t,
                                stop, cntr);
@@ -627,8 +672,12 @@ hipError_t ilu_apply_bwd(hipStream_t st, const SellDesc& A, const void* mv, int 
         auto go = [&](auto ep) -> hipError_t {
           using EPI = decltype(ep);
           if (win) {
-            hipLaunchKernelGGL((k_ilu_bwd_win<TM, TT, Q>), g, b, (size_t)wl.total, st, A, D, vu, du, (TT*)t,
-                               stop, wl);
+            if (D.chunk)
+              hipLaunchKernelGGL((k_ilu_bwd_win<TM, TT, Q, true>), g, b, (size_t)wl.total, st, A, D, vu, du,
+                                 (TT*)t, stop, wl);
+            else
+              hipLaunchKernelGGL((k_ilu_bwd_win<TM, TT, Q, false>), g, b, (size_t)wl.total, st, A, D, vu, du,
+                                 (TT*)t, stop, wl);
             hipError_t e = hipGetLastError();
             if (e != hipSuccess) return e;
             const unsigned ge = (unsigned)((A.n + 1023) / 1024);
