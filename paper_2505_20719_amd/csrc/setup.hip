@@ -550,7 +550,10 @@ f3r_status build_matrix(hipStream_t st, const f3r_csr* A, const f3r_params* p, c
     m.ilu.win_pos = ib.win_pos;
     m.ilu.win_ent = ib.win_ent;
     m.ilu.lds_max = lds_max;
-    m.ilu.chunk = nnz > 9 * n;  // more than four entries per sweep row on average
+    // more than four entries per sweep row on average, and at most four
+    // workgroups per compute unit (the chunked loop needs the registers that
+    // eight co-resident workgroups would not leave)
+    m.ilu.chunk = nnz > 9 * n && (int64_t)p->ilu_blocks <= 4 * (int64_t)cus;
   }
   // the CSR copies are no longer needed (the slice-offset format keeps the
   // columns for reading values back)
