@@ -55,21 +55,23 @@ class Info(C.Structure):
         return d
 
 
-_lib = None
+_libs: dict = {}
 _dp = np.ctypeslib.ndpointer(dtype=np.float64, flags="C_CONTIGUOUS")
 _ip = np.ctypeslib.ndpointer(dtype=np.int32, flags="C_CONTIGUOUS")
 _up = np.ctypeslib.ndpointer(dtype=np.uint16, flags="C_CONTIGUOUS")
 
 
-def lib():
-    """Load (building first if needed) the oracle shared library."""
-    global _lib
-    if _lib is not None:
-        return _lib
-    if not os.path.exists(LIB_PATH):
+def lib(path: str | None = None):
+    """Load (building first if needed) the oracle shared library.  `path`
+    names another build of the same source (the pin tests load copies with
+    a planted mistake to show that the pins catch it)."""
+    key = path or LIB_PATH
+    if key in _libs:
+        return _libs[key]
+    if path is None and not os.path.exists(LIB_PATH):
         from . import build as _b
         _b.build()
-    L = C.CDLL(LIB_PATH)
+    L = C.CDLL(key)
     H = C.c_void_p
     sig = {
         "or_f64_to_f16": (C.c_uint16, [C.c_double]),
@@ -107,12 +109,16 @@ def lib():
         "or_set_weights": (None, [H, C.c_int32, _dp, C.c_int64]),
         "or_history": (C.c_int64, [H, C.c_void_p, C.c_int64]),
         "or_last_cycle": (C.c_int32, [H, _dp, _dp, _dp, C.c_int32]),
+        "or_trace": (C.c_int32, [H, C.c_int32, C.c_int32]),
+        "or_rich_trace": (C.c_int32, [H, _dp, _dp, _dp, _dp, _dp, _dp, _dp]),
+        "or_level_cycle": (C.c_int32, [H, C.c_int32, _dp, _dp, _dp, _dp, _dp,
+                                       C.POINTER(C.c_double)]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)
         f.restype = res
         f.argtypes = args
-    _lib = L
+    _libs[key] = L
     return L
 
 
@@ -174,8 +180,9 @@ def decode_bf16(h) -> np.ndarray:
 class Oracle:
     """One set-up matrix with its nest parameters (or_setup / or_destroy)."""
 
-    def __init__(self, row_ptr, col_idx, val, params: Params | None = None):
-        self.L = lib()
+    def __init__(self, row_ptr, col_idx, val, params: Params | None = None,
+                 lib_path: str | None = None):
+        self.L = lib(lib_path)
         self.rp = np.ascontiguousarray(row_ptr, dtype=np.int32)
         self.ci = np.ascontiguousarray(col_idx, dtype=np.int32)
         self.val = np.ascontiguousarray(val, dtype=np.float64)
@@ -289,6 +296,49 @@ class Oracle:
         buf = np.empty(max(k, 1))
         self.L.or_history(self.h, buf.ctypes.data, k)
         return buf[:k].copy()
+
+    def trace(self, d, on=True):
+        """Record the stored intermediates of every later call of the
+        Richardson level d (see rich_trace)."""
+        st = self.L.or_trace(self.h, d, int(bool(on)))
+        if st != OK:
+            raise OracleError(st)
+
+    def rich_trace(self):
+        """Intermediates of the last traced Richardson call: dict with v (n),
+        r, tw, y, z, ta (steps x n) and the per-step scalars (updated, num,
+        den, omega', omega before, omega after, l, weight used)."""
+        n, m = self.n, 64
+        d = {k: np.zeros(m * n) for k in ("r", "tw", "y", "z", "ta")}
+        v = np.zeros(n)
+        sc = np.zeros(m * 8)
+        k = self.L.or_rich_trace(self.h, v, d["r"], d["tw"], d["y"], d["z"], d["ta"], sc)
+        out = {key: a[: k * n].reshape(k, n) for key, a in d.items()}
+        out["v"] = v
+        names = ("updated", "num", "den", "wp", "om_before", "om_after", "l", "w_used")
+        sc = sc[: k * 8].reshape(k, 8)
+        for i, nm in enumerate(names):
+            out[nm] = sc[:, i].copy()
+        out["steps"] = k
+        return out
+
+    def level_cycle(self, d, cap_m=64):
+        """Last invocation of the FGMRES level d: V ((m+1) x n), Z (m x n),
+        the Hessenberg matrix before rotations ((m+1) x m), the rotated g,
+        y and beta."""
+        n = self.n
+        V = np.zeros((cap_m + 1) * n)
+        Z = np.zeros(cap_m * n)
+        H = np.zeros((cap_m + 1) * cap_m)
+        g = np.zeros(cap_m + 1)
+        y = np.zeros(cap_m)
+        beta = C.c_double()
+        m = self.L.or_level_cycle(self.h, d, V, Z, H, g, y, C.byref(beta))
+        if m < 0:
+            raise OracleError(ERR_ARG)
+        return dict(V=V[: (m + 1) * n].reshape(m + 1, n), Z=Z[: m * n].reshape(m, n),
+                    H=H[: (m + 1) * m].reshape(m, m + 1).T, g=g[: m + 1].copy(),
+                    y=y[:m].copy(), beta=beta.value, m=m)
 
     def last_cycle(self, cap_m):
         n = self.n

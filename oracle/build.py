@@ -13,15 +13,17 @@ SRC = os.path.join(HERE, "f3r_oracle.c")
 LIB = os.path.join(HERE, "liboracle.so")
 
 
-def build(verbose: bool = False) -> str:
+def build(verbose: bool = False, src: str = SRC, out: str = LIB) -> str:
+    """Compile `src` (default: the oracle) into `out`.  The pin tests pass a
+    copy of the source with a planted mistake and a path of their own."""
     cmd = ["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-ffp-contract=off",
            "-fno-fast-math", "-frounding-math", "-Wall", "-Wextra",
-           "-Wno-unused-parameter", "-o", LIB + ".tmp", SRC, "-lm"]
+           "-Wno-unused-parameter", "-I", HERE, "-o", out + ".tmp", src, "-lm"]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.run(cmd, check=True)
-    os.replace(LIB + ".tmp", LIB)
-    return LIB
+    os.replace(out + ".tmp", out)
+    return out
 
 
 if __name__ == "__main__":

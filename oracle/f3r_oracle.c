@@ -51,7 +51,10 @@
  * unit-roundoff bound; M against its dense product; Richardson closed forms
  * and the GMRES(1) special case; FGMRES against dense LU and the flexible
  * Arnoldi relation; nest reductions (fp64-F3R with m2=m3=m4=1 equals
- * FGMRES(m1)+M); M-call counts; end-to-end residual certificates.
+ * FGMRES(m1)+M); M-call counts; end-to-end residual certificates; every
+ * stored intermediate of the narrow levels (Richardson in fp16/bf16, the
+ * fp32 FGMRES levels) within the rounding bound of its stage, recorded
+ * through or_trace / or_rich_trace / or_level_cycle (recording only).
  */
 #include "f3r_oracle.h"
 
@@ -175,7 +178,24 @@ typedef struct {
   int32_t m;
   double *V, *Z, *H, *Hraw, *cs, *sn, *g, *y, *w;
   double *tmp0, *tmp1, *tmp2, *tmp3, *tmp4; /* Richardson / scaling scratch */
+  double beta;   /* ||v|| of the level's last invocation (FGMRES) */
+  int32_t meff;  /* iterations of that invocation */
 } level_ws;
+
+/* Copies of every stored intermediate of one Richardson invocation, kept
+   only when tracing is switched on (or_trace); recording changes nothing
+   in the arithmetic. */
+typedef struct {
+  int32_t on, d, m, steps;
+  double* v;    /* the input rounded to the level's storage */
+  double* r;    /* m x n: r_{k-1} */
+  double* tw;   /* m x n: W r_{k-1} (the first of the two SpMVs of M) */
+  double* y;    /* m x n: M r_{k-1} */
+  double* z;    /* m x n: z_k */
+  double* ta;   /* m x n: A y on update steps (kept in the arithmetic precision) */
+  double sc[64][8]; /* per step: updated, num, den, omega', omega before,
+                       omega after, l, weight used */
+} rich_trace;
 
 struct or_handle {
   or_params p;
@@ -201,6 +221,7 @@ struct or_handle {
   double* hist;
   int64_t hist_len, hist_cap;
   int32_t last_m;
+  rich_trace tr;
 };
 
 int64_t or_n(const or_handle* h) { return h->n; }
@@ -291,6 +312,12 @@ void or_destroy(or_handle* h) {
     free(w->tmp4);
   }
   free(h->hist);
+  free(h->tr.v);
+  free(h->tr.r);
+  free(h->tr.tw);
+  free(h->tr.y);
+  free(h->tr.z);
+  free(h->tr.ta);
   free(h);
 }
 
@@ -703,6 +730,8 @@ static int fgmres_cycle(or_handle* h, int d, const double* vin, int m,
   *bad = 0;
   for (int64_t i = 0; i < n; i++) Vc(0)[i] = RND(p, vin[i]);
   double beta = nrm2(q, n, Vc(0));
+  W->beta = beta;
+  W->meff = 0;
   if (beta == 0.0) {
     for (int64_t i = 0; i < n; i++) out[i] = 0.0;
     skip_calls(h, d, m);
@@ -796,6 +825,7 @@ static int fgmres_cycle(or_handle* h, int d, const double* vin, int m,
     for (int j = 0; j < meff; j++) acc = RND(q, acc + RND(q, W->y[j] * Zc(j)[k]));
     out[k] = RND(p, acc);
   }
+  W->meff = meff;
   if (d == 0) h->last_m = meff;
   return meff;
 #undef Vc
@@ -825,6 +855,11 @@ static void richardson(or_handle* h, int d, const double* vin, double* out) {
     for (int k = 0; k < L->m; k++) om[k] = RND(q, h->p.omega_init);
   for (int64_t i = 0; i < n; i++) v[i] = RND(p, vin[i]);
   for (int64_t i = 0; i < n; i++) z[i] = 0.0; /* z_0 = 0 */
+  rich_trace* T = (h->tr.on && h->tr.d == d) ? &h->tr : NULL;
+  if (T) {
+    memcpy(T->v, v, (size_t)n * sizeof(double));
+    T->steps = 0;
+  }
   for (int k = 0; k < L->m; k++) {
     /* r_{k-1} = v - A z_{k-1}; r_0 = v without computation */
     if (k == 0) {
@@ -837,6 +872,8 @@ static void richardson(or_handle* h, int d, const double* vin, double* out) {
     /* y = M r_{k-1} (or the next level when R is not innermost) */
     apply_prec(h, d, r, y);
     int updated = 0;
+    double om_before = om[k], wp_used = 0.0, num_k = 0.0, den_k = 0.0;
+    int64_t l_k = 0;
     if (c > 0 && cn % c == 0) {
       /* omega'_k = (r, A M r) / (A M r, A M r), in fp32 (Sec. 4.3) */
       csr_mv(n, h->rp, h->ci, h->alev[L->pA], q, q, y, t);
@@ -844,15 +881,38 @@ static void richardson(or_handle* h, int d, const double* vin, double* out) {
       double num = dot(q, n, r, t);
       double den = dot(q, n, t, t);
       double wp = RND(q, num / den);
+      num_k = num;
+      den_k = den;
+      if (T) memcpy(T->ta + (int64_t)k * n, t, (size_t)n * sizeof(double));
       if (den > 0.0 && isfinite(wp)) {
         for (int64_t i = 0; i < n; i++) z[i] = RND(p, RND(q, z[i] + RND(q, wp * y[i])));
         int64_t l = cn / c;
         om[k] = RND(q, RND(q, RND(q, (double)l * om[k]) + wp) / (double)(l + 1));
         updated = 1;
+        wp_used = wp;
+        l_k = l;
       }
     }
-    if (!updated)
+    if (!updated) {
       for (int64_t i = 0; i < n; i++) z[i] = RND(p, RND(q, z[i] + RND(q, om[k] * y[i])));
+      wp_used = om[k];
+    }
+    if (T && k < 64) {
+      memcpy(T->r + (int64_t)k * n, r, (size_t)n * sizeof(double));
+      memcpy(T->tw + (int64_t)k * n, h->mtmp, (size_t)n * sizeof(double));
+      memcpy(T->y + (int64_t)k * n, y, (size_t)n * sizeof(double));
+      memcpy(T->z + (int64_t)k * n, z, (size_t)n * sizeof(double));
+      double* sc = T->sc[k];
+      sc[0] = updated;
+      sc[1] = num_k;
+      sc[2] = den_k;
+      sc[3] = updated ? wp_used : 0.0;
+      sc[4] = om_before;
+      sc[5] = om[k];
+      sc[6] = (double)l_k;
+      sc[7] = wp_used;
+      T->steps = k + 1;
+    }
   }
   h->cntr[d] = cn + 1;
   h->st.r_calls++;
@@ -1141,6 +1201,60 @@ int64_t or_history(const or_handle* h, double* buf, int64_t cap) {
   int64_t k = h->hist_len < cap ? h->hist_len : cap;
   if (buf) memcpy(buf, h->hist, (size_t)k * sizeof(double));
   return h->hist_len;
+}
+int32_t or_trace(or_handle* h, int32_t d, int32_t on) {
+  rich_trace* T = &h->tr;
+  free(T->v);
+  free(T->r);
+  free(T->tw);
+  free(T->y);
+  free(T->z);
+  free(T->ta);
+  memset(T, 0, sizeof(*T));
+  if (!on || d < 1 || d >= h->p.nlev || h->p.lev[d].kind != OR_RICH) return OR_OK;
+  int64_t n = h->n, m = h->p.lev[d].m;
+  if (m > 64) return OR_ERR_ARG;
+  T->v = xcalloc(n, sizeof(double));
+  T->r = xcalloc(m * n, sizeof(double));
+  T->tw = xcalloc(m * n, sizeof(double));
+  T->y = xcalloc(m * n, sizeof(double));
+  T->z = xcalloc(m * n, sizeof(double));
+  T->ta = xcalloc(m * n, sizeof(double));
+  if (!T->v || !T->r || !T->tw || !T->y || !T->z || !T->ta) return OR_ERR_NOMEM;
+  T->on = 1;
+  T->d = d;
+  T->m = (int32_t)m;
+  return OR_OK;
+}
+int32_t or_rich_trace(const or_handle* h, double* v, double* r, double* tw,
+                      double* y, double* z, double* ta, double* sc) {
+  const rich_trace* T = &h->tr;
+  if (!T->on) return 0;
+  int64_t n = h->n, k = T->steps;
+  memcpy(v, T->v, (size_t)n * sizeof(double));
+  memcpy(r, T->r, (size_t)(k * n) * sizeof(double));
+  memcpy(tw, T->tw, (size_t)(k * n) * sizeof(double));
+  memcpy(y, T->y, (size_t)(k * n) * sizeof(double));
+  memcpy(z, T->z, (size_t)(k * n) * sizeof(double));
+  memcpy(ta, T->ta, (size_t)(k * n) * sizeof(double));
+  memcpy(sc, T->sc, (size_t)k * 8 * sizeof(double));
+  return (int32_t)k;
+}
+int32_t or_level_cycle(const or_handle* h, int32_t d, double* V, double* Z,
+                       double* H, double* g, double* y, double* beta) {
+  if (d < 0 || d >= h->p.nlev || h->p.lev[d].kind != OR_FGMRES) return -1;
+  const level_ws* W = &h->ws[d];
+  int32_t m = W->meff;
+  int64_t n = h->n;
+  memcpy(V, W->V, (size_t)(m + 1) * (size_t)n * sizeof(double));
+  memcpy(Z, W->Z, (size_t)m * (size_t)n * sizeof(double));
+  for (int j = 0; j < m; j++)
+    for (int i = 0; i <= m; i++)
+      H[i + (int64_t)j * (m + 1)] = W->Hraw[i + (int64_t)j * (W->m + 1)];
+  memcpy(g, W->g, (size_t)(m + 1) * sizeof(double));
+  memcpy(y, W->y, (size_t)m * sizeof(double));
+  *beta = W->beta;
+  return m;
 }
 int32_t or_last_cycle(const or_handle* h, double* V, double* Z, double* H,
                       int32_t cap_m) {

@@ -138,6 +138,18 @@ void or_get_weights(const or_handle* h, int32_t d, double* omega, int64_t* cntr)
 void or_set_weights(or_handle* h, int32_t d, const double* omega, int64_t cntr);
 /* outermost history: relative residual estimate per outermost iteration */
 int64_t or_history(const or_handle* h, double* buf, int64_t cap);
+/* Pins of the narrow arithmetic: or_trace(h, d, 1) makes every later
+   invocation of the Richardson level d record its stored intermediates;
+   or_rich_trace copies those of the last invocation (k steps: v (n), then
+   r, tw, y, z, ta as k x n row-major, sc as k x 8) and returns k.
+   or_level_cycle copies the last invocation of the FGMRES level d: V
+   ((m+1) x n), Z (m x n), the Hessenberg matrix before rotations ((m+1) x m,
+   column-major), the rotated g (m+1), y (m) and beta; returns m, or -1. */
+int32_t or_trace(or_handle* h, int32_t d, int32_t on);
+int32_t or_rich_trace(const or_handle* h, double* v, double* r, double* tw,
+                      double* y, double* z, double* ta, double* sc);
+int32_t or_level_cycle(const or_handle* h, int32_t d, double* V, double* Z,
+                       double* H, double* g, double* y, double* beta);
 /* the last outermost cycle's basis, for the Arnoldi-relation pin */
 int32_t or_last_cycle(const or_handle* h, double* V, double* Z, double* H,
                       int32_t cap_m);
