@@ -39,7 +39,7 @@ class Params(C.Structure):
                 ("omega_init", C.c_double), ("max_outer", C.c_int32),
                 ("use_x0", C.c_int32), ("persist_weights", C.c_int32),
                 ("poison_call", C.c_int32), ("m_kind", C.c_int32),
-                ("ilu_blocks", C.c_int32)]
+                ("ilu_blocks", C.c_int32), ("dot_order", C.c_int32)]
 
 
 class Info(C.Structure):
@@ -110,6 +110,7 @@ def lib(path: str | None = None):
         "or_history": (C.c_int64, [H, C.c_void_p, C.c_int64]),
         "or_last_cycle": (C.c_int32, [H, _dp, _dp, _dp, C.c_int32]),
         "or_trace": (C.c_int32, [H, C.c_int32, C.c_int32]),
+        "or_level_history": (C.c_int64, [H, C.c_int32, C.c_void_p, C.c_int64]),
         "or_rich_trace": (C.c_int32, [H, _dp, _dp, _dp, _dp, _dp, _dp, _dp]),
         "or_level_cycle": (C.c_int32, [H, C.c_int32, _dp, _dp, _dp, _dp, _dp,
                                        C.POINTER(C.c_double)]),
@@ -291,10 +292,12 @@ class Oracle:
         om[: len(omega)] = omega
         self.L.or_set_weights(self.h, d, om, cntr)
 
-    def history(self):
-        k = self.L.or_history(self.h, None, 0)
+    def history(self, level=0):
+        """Level 0: the outermost estimate per outermost iteration; level d >= 1:
+        |g_{j+1}| / beta after every iteration of every call of that level."""
+        k = self.L.or_level_history(self.h, level, None, 0)
         buf = np.empty(max(k, 1))
-        self.L.or_history(self.h, buf.ctypes.data, k)
+        self.L.or_level_history(self.h, level, buf.ctypes.data, k)
         return buf[:k].copy()
 
     def trace(self, d, on=True):

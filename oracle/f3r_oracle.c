@@ -222,6 +222,8 @@ struct or_handle {
   int64_t hist_len, hist_cap;
   int32_t last_m;
   rich_trace tr;
+  double* lhist[OR_MAX_LEV]; /* inner levels: |g_{j+1}| / beta per iteration */
+  int64_t lhist_len[OR_MAX_LEV], lhist_cap[OR_MAX_LEV];
 };
 
 int64_t or_n(const or_handle* h) { return h->n; }
@@ -312,6 +314,7 @@ void or_destroy(or_handle* h) {
     free(w->tmp4);
   }
   free(h->hist);
+  for (int d = 0; d < OR_MAX_LEV; d++) free(h->lhist[d]);
   free(h->tr.v);
   free(h->tr.r);
   free(h->tr.tw);
@@ -632,6 +635,38 @@ static double nrm2(int32_t q, int64_t n, const double* x) {
   return RND(q, sqrt(dot(q, n, x, x)));
 }
 
+/* Sum of round_q(x_i y_i) over i = lo .. hi-1 in precision q, in the order
+   `order` (or_params.dot_order; the paper fixes no order for the dot
+   products of the Gram-Schmidt step or of the weight, Secs. 4.2-4.3):
+   0 left to right, 1 right to left, 2 blocks of 1024 summed left to right
+   and then the block sums left to right, 3 pairwise (halves summed
+   recursively, runs of at most 8 left to right). */
+static double dot_range(int32_t q, int32_t order, int64_t lo, int64_t hi,
+                        const double* x, const double* y) {
+  double acc = 0.0;
+  if (order == 1) {
+    for (int64_t i = hi - 1; i >= lo; i--) acc = RND(q, acc + RND(q, x[i] * y[i]));
+  } else if (order == 2) {
+    for (int64_t b = lo; b < hi; b += 1024) {
+      int64_t e = b + 1024 < hi ? b + 1024 : hi;
+      acc = RND(q, acc + dot_range(q, 0, b, e, x, y));
+    }
+  } else if (order == 3 && hi - lo > 8) {
+    int64_t mid = lo + (hi - lo) / 2;
+    acc = RND(q, dot_range(q, 3, lo, mid, x, y) + dot_range(q, 3, mid, hi, x, y));
+  } else {
+    for (int64_t i = lo; i < hi; i++) acc = RND(q, acc + RND(q, x[i] * y[i]));
+  }
+  return acc;
+}
+/* the dot products and norms of the level arithmetic, in the handle's order */
+static double ldot(const or_handle* h, int32_t q, int64_t n, const double* x, const double* y) {
+  return dot_range(q, h->p.dot_order, 0, n, x, y);
+}
+static double lnrm2(const or_handle* h, int32_t q, int64_t n, const double* x) {
+  return RND(q, sqrt(ldot(h, q, n, x, x)));
+}
+
 static int all_finite(int64_t n, const double* x) {
   for (int64_t i = 0; i < n; i++)
     if (!isfinite(x[i])) return 0;
@@ -705,6 +740,17 @@ static void apply_prec(or_handle* h, int d, const double* v, double* z) {
     apply_m_impl(h, h->p.lev[d].pv, h->p.lev[d].pacc, 0, v, z);
 }
 
+static void lhist_push(or_handle* h, int d, double v) {
+  if (h->lhist_len[d] == h->lhist_cap[d]) {
+    int64_t cap = h->lhist_cap[d] ? 2 * h->lhist_cap[d] : 1024;
+    double* nh = realloc(h->lhist[d], (size_t)cap * sizeof(double));
+    if (!nh) return;
+    h->lhist[d] = nh;
+    h->lhist_cap[d] = cap;
+  }
+  h->lhist[d][h->lhist_len[d]++] = v;
+}
+
 /* ------------------------------------------------------------------------ */
 /* FGMRES level (Sec. 4.2: classical Gram-Schmidt, Givens rotations)        */
 /* ------------------------------------------------------------------------ */
@@ -729,7 +775,7 @@ static int fgmres_cycle(or_handle* h, int d, const double* vin, int m,
 #define Hr(i, j) (W->Hraw[(i) + (int64_t)(j) * (M1 + 1)])
   *bad = 0;
   for (int64_t i = 0; i < n; i++) Vc(0)[i] = RND(p, vin[i]);
-  double beta = nrm2(q, n, Vc(0));
+  double beta = lnrm2(h, q, n, Vc(0));
   W->beta = beta;
   W->meff = 0;
   if (beta == 0.0) {
@@ -756,13 +802,13 @@ static int fgmres_cycle(or_handle* h, int d, const double* vin, int m,
       csr_mv(n, h->rp, h->ci, h->alev[L->pA], q, p, Zc(j), w);
     h->st.spmv[d]++;
     /* classical Gram-Schmidt: all h_ij from the same w */
-    for (int i = 0; i <= j; i++) Hh(i, j) = dot(q, n, w, Vc(i));
+    for (int i = 0; i <= j; i++) Hh(i, j) = ldot(h, q, n, w, Vc(i));
     for (int64_t k = 0; k < n; k++) {
       double acc = w[k];
       for (int i = 0; i <= j; i++) acc = RND(q, acc - RND(q, Hh(i, j) * Vc(i)[k]));
       w[k] = RND(p, acc);
     }
-    double hn = nrm2(q, n, w);
+    double hn = lnrm2(h, q, n, w);
     for (int i = 0; i <= j; i++) Hr(i, j) = Hh(i, j);
     Hr(j + 1, j) = hn;
     /* apply the previous rotations to column j */
@@ -797,6 +843,9 @@ static int fgmres_cycle(or_handle* h, int d, const double* vin, int m,
         }
       }
       if (h->hist_len < h->hist_cap) h->hist[h->hist_len++] = est;
+    } else {
+      /* inner levels: the estimate relative to the invocation's input norm */
+      lhist_push(h, d, fabs(W->g[j + 1]) / beta);
     }
     if (hn == 0.0) { /* exact breakdown: the subspace holds the solution */
       meff = j + 1;
@@ -878,8 +927,8 @@ static void richardson(or_handle* h, int d, const double* vin, double* out) {
       /* omega'_k = (r, A M r) / (A M r, A M r), in fp32 (Sec. 4.3) */
       csr_mv(n, h->rp, h->ci, h->alev[L->pA], q, q, y, t);
       h->st.spmv[d]++;
-      double num = dot(q, n, r, t);
-      double den = dot(q, n, t, t);
+      double num = ldot(h, q, n, r, t);
+      double den = ldot(h, q, n, t, t);
       double wp = RND(q, num / den);
       num_k = num;
       den_k = den;
@@ -951,6 +1000,7 @@ static int32_t outer_solve(or_handle* h, const double* b, double* x,
   int64_t n = h->n;
   memset(&h->st, 0, sizeof(h->st));
   h->hist_len = 0;
+  for (int d = 0; d < OR_MAX_LEV; d++) h->lhist_len[d] = 0;
   if (!h->p.persist_weights)
     for (int d = 0; d < OR_MAX_LEV; d++) h->cntr[d] = 1;
   double* r = xcalloc(n, sizeof(double));
@@ -1064,6 +1114,7 @@ int32_t or_krylov_solve(or_handle* h, int32_t method, int32_t m64, const double*
   memset(info, 0, sizeof(*info));
   memset(&h->st, 0, sizeof(h->st));
   h->hist_len = 0;
+  for (int d = 0; d < OR_MAX_LEV; d++) h->lhist_len[d] = 0;
   enum { NW = 10 };
   double* w[NW];
   for (int k = 0; k < NW; k++) w[k] = xcalloc((size_t)n, sizeof(double));
@@ -1201,6 +1252,13 @@ int64_t or_history(const or_handle* h, double* buf, int64_t cap) {
   int64_t k = h->hist_len < cap ? h->hist_len : cap;
   if (buf) memcpy(buf, h->hist, (size_t)k * sizeof(double));
   return h->hist_len;
+}
+int64_t or_level_history(const or_handle* h, int32_t d, double* buf, int64_t cap) {
+  if (d == 0) return or_history(h, buf, cap);
+  if (d < 0 || d >= OR_MAX_LEV) return 0;
+  int64_t k = h->lhist_len[d] < cap ? h->lhist_len[d] : cap;
+  if (buf && k > 0) memcpy(buf, h->lhist[d], (size_t)k * sizeof(double));
+  return h->lhist_len[d];
 }
 int32_t or_trace(or_handle* h, int32_t d, int32_t on) {
   rich_trace* T = &h->tr;

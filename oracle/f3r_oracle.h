@@ -61,6 +61,9 @@ typedef struct {
   int32_t poison_call;     /* >0: inject NaN into the output of that R call */
   int32_t m_kind;          /* OR_M_SGS (two-SpMV truncated inverse) or OR_M_ILU */
   int32_t ilu_blocks;      /* block-Jacobi ILU(0): number of row blocks */
+  int32_t dot_order;       /* summation order of the level dots and norms:
+                              0 left to right (default), 1 right to left,
+                              2 blocks of 1024, 3 pairwise */
 } or_params;
 
 #define OR_M_SGS 0
@@ -138,6 +141,10 @@ void or_get_weights(const or_handle* h, int32_t d, double* omega, int64_t* cntr)
 void or_set_weights(or_handle* h, int32_t d, const double* omega, int64_t cntr);
 /* outermost history: relative residual estimate per outermost iteration */
 int64_t or_history(const or_handle* h, double* buf, int64_t cap);
+/* level d's history: d = 0 as or_history; d >= 1 (FGMRES) the Givens
+   estimate |g_{j+1}| / beta after every iteration of every invocation of
+   the last solve, in order */
+int64_t or_level_history(const or_handle* h, int32_t d, double* buf, int64_t cap);
 /* Pins of the narrow arithmetic: or_trace(h, d, 1) makes every later
    invocation of the Richardson level d record its stored intermediates;
    or_rich_trace copies those of the last invocation (k steps: v (n), then

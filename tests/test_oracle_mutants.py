@@ -20,8 +20,8 @@ MUTANTS = [
      "r[i] = RND(p, RND(q, v[i] - t[i]));",
      "r[i] = RND(p, RND(q, v[i] - RND(p, t[i])));", "rich"),
     ("w': dots accumulated in the storage precision",
-     "double num = dot(q, n, r, t);\n      double den = dot(q, n, t, t);",
-     "double num = dot(p, n, r, t);\n      double den = dot(p, n, t, t);", "rich"),
+     "double num = ldot(h, q, n, r, t);\n      double den = ldot(h, q, n, t, t);",
+     "double num = ldot(h, p, n, r, t);\n      double den = ldot(h, p, n, t, t);", "rich"),
     ("w': t = A y stored narrow instead of kept in fp32",
      "csr_mv(n, h->rp, h->ci, h->alev[L->pA], q, q, y, t);\n      h->st.spmv[d]++;\n      double num",
      "csr_mv(n, h->rp, h->ci, h->alev[L->pA], q, p, y, t);\n      h->st.spmv[d]++;\n      double num",
@@ -55,12 +55,12 @@ MUTANTS = [
      "W->y[i] = RND(q, acc / Hh(i, i));",
      "W->y[i] = RND(q == OR_F32 ? OR_F16 : q, acc / Hh(i, i));", "fgmres"),
     ("FGMRES: dots h_ij rounded to fp16",
-     "for (int i = 0; i <= j; i++) Hh(i, j) = dot(q, n, w, Vc(i));",
-     "for (int i = 0; i <= j; i++) Hh(i, j) = RND(q == OR_F32 ? OR_F16 : q, dot(q, n, w, Vc(i)));",
+     "for (int i = 0; i <= j; i++) Hh(i, j) = ldot(h, q, n, w, Vc(i));",
+     "for (int i = 0; i <= j; i++) Hh(i, j) = RND(q == OR_F32 ? OR_F16 : q, ldot(h, q, n, w, Vc(i)));",
      "fgmres"),
     ("FGMRES: norm h_{j+1,j} rounded to fp16",
-     "static double nrm2(int32_t q, int64_t n, const double* x) {\n  return RND(q, sqrt(dot(q, n, x, x)));",
-     "static double nrm2(int32_t q, int64_t n, const double* x) {\n  return RND(q == OR_F32 ? OR_F16 : q, sqrt(dot(q, n, x, x)));",
+     "static double lnrm2(const or_handle* h, int32_t q, int64_t n, const double* x) {\n  return RND(q, sqrt(ldot(h, q, n, x, x)));",
+     "static double lnrm2(const or_handle* h, int32_t q, int64_t n, const double* x) {\n  return RND(q == OR_F32 ? OR_F16 : q, sqrt(ldot(h, q, n, x, x)));",
      "fgmres"),
     ("FGMRES: output Z y summed in fp16",
      "for (int j = 0; j < meff; j++) acc = RND(q, acc + RND(q, W->y[j] * Zc(j)[k]));",
