@@ -94,6 +94,7 @@ def lib(path: str | None = None):
         "or_krylov_solve": (C.c_int32, [H, C.c_int32, C.c_int32, _dp, _dp, C.c_double,
                                         C.c_int32, C.POINTER(Info)]),
         "or_n": (C.c_int64, [H]),
+        "or_threads": (C.c_int32, []),
         "or_get_ilu_values": (None, [H, C.c_int32, _dp]),
         "or_ilu_block_start": (C.c_int64, [H, C.c_int64]),
         "or_get_scaling": (None, [H, _dp]),

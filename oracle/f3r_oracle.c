@@ -55,12 +55,34 @@
  * stored intermediate of the narrow levels (Richardson in fp16/bf16, the
  * fp32 FGMRES levels) within the rounding bound of its stage, recorded
  * through or_trace / or_rich_trace / or_level_cycle (recording only).
+ *
+ * Threads: built with -fopenmp (the CPU-baseline build), the loops whose
+ * iterations write separate elements (SpMV rows, vector updates) and the
+ * blocks of the blocked dot orders are shared among threads; every value is computed
+ * by the same operations as in the plain build, so both builds give the
+ * same results bit for bit.  The plain build (-fno-openmp) is what the pins
+ * exercise.
  */
 #include "f3r_oracle.h"
 
 #include <math.h>
 #include <stdlib.h>
 #include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+/* the next loop's iterations are independent: share them among threads */
+#define OR_PAR_FOR _Pragma("omp parallel for schedule(static)")
+#else
+#define OR_PAR_FOR
+#endif
+
+int32_t or_threads(void) {
+#ifdef _OPENMP
+  return (int32_t)omp_get_max_threads();
+#else
+  return 1;
+#endif
+}
 
 /* ------------------------------------------------------------------------ */
 /* soft floating point                                                       */
@@ -617,6 +639,7 @@ int32_t or_setup(int64_t n, int64_t nnz, const int32_t* rp, const int32_t* ci,
 static void csr_mv(int64_t n, const int32_t* rp, const int32_t* ci,
                    const double* v, int32_t q, int32_t pout, const double* x,
                    double* y) {
+  OR_PAR_FOR
   for (int64_t i = 0; i < n; i++) {
     double acc = 0.0;
     for (int64_t k = rp[i]; k < rp[i + 1]; k++)
@@ -638,22 +661,36 @@ static double nrm2(int32_t q, int64_t n, const double* x) {
 /* Sum of round_q(x_i y_i) over i = lo .. hi-1 in precision q, in the order
    `order` (or_params.dot_order; the paper fixes no order for the dot
    products of the Gram-Schmidt step or of the weight, Secs. 4.2-4.3):
-   0 left to right, 1 right to left, 2 blocks of 1024 summed left to right
-   and then the block sums left to right, 3 pairwise (halves summed
-   recursively, runs of at most 8 left to right). */
+   0 left to right, 1 right to left, 2 / 4 / 5 / 6 blocks of 1024 / 64 /
+   256 / 4096 elements each summed left to right and then the block sums
+   left to right, 3 / 7 pairwise (halves summed recursively, runs of at
+   most 8 / 32 left to right). */
+static int64_t block_len(int32_t order) {
+  return order == 4 ? 64 : order == 5 ? 256 : order == 6 ? 4096 : 1024;
+}
 static double dot_range(int32_t q, int32_t order, int64_t lo, int64_t hi,
                         const double* x, const double* y) {
   double acc = 0.0;
   if (order == 1) {
     for (int64_t i = hi - 1; i >= lo; i--) acc = RND(q, acc + RND(q, x[i] * y[i]));
-  } else if (order == 2) {
-    for (int64_t b = lo; b < hi; b += 1024) {
-      int64_t e = b + 1024 < hi ? b + 1024 : hi;
-      acc = RND(q, acc + dot_range(q, 0, b, e, x, y));
+  } else if (order == 2 || order == 4 || order == 5 || order == 6) {
+    /* each block's sum alone (the blocks are independent), then the block
+       sums in block order */
+    int64_t bl = block_len(order);
+    int64_t nblk = (hi - lo + bl - 1) / bl;
+    double* bs = malloc((size_t)(nblk > 0 ? nblk : 1) * sizeof(double));
+    if (!bs) return NAN;
+    OR_PAR_FOR
+    for (int64_t t = 0; t < nblk; t++) {
+      int64_t b = lo + t * bl;
+      int64_t e = b + bl < hi ? b + bl : hi;
+      bs[t] = dot_range(q, 0, b, e, x, y);
     }
-  } else if (order == 3 && hi - lo > 8) {
+    for (int64_t t = 0; t < nblk; t++) acc = RND(q, acc + bs[t]);
+    free(bs);
+  } else if ((order == 3 && hi - lo > 8) || (order == 7 && hi - lo > 32)) {
     int64_t mid = lo + (hi - lo) / 2;
-    acc = RND(q, dot_range(q, 3, lo, mid, x, y) + dot_range(q, 3, mid, hi, x, y));
+    acc = RND(q, dot_range(q, order, lo, mid, x, y) + dot_range(q, order, mid, hi, x, y));
   } else {
     for (int64_t i = lo; i < hi; i++) acc = RND(q, acc + RND(q, x[i] * y[i]));
   }
@@ -726,11 +763,13 @@ static void apply_prec(or_handle* h, int d, const double* v, double* z) {
     /* outermost: the inner nest runs on the scaled system, P(v) = S F2(S v) */
     double* t0 = h->ws[0].tmp0;
     double* t1 = h->ws[0].tmp1;
+    OR_PAR_FOR
     for (int64_t i = 0; i < n; i++) t0[i] = h->s[i] * v[i];
     if (h->baseline || h->p.nlev == 1)
       apply_m_impl(h, OR_F64, OR_F64, h->baseline && h->base_m64, t0, t1);
     else
       apply_level_impl(h, 1, t0, t1);
+    OR_PAR_FOR
     for (int64_t i = 0; i < n; i++) z[i] = h->s[i] * t1[i];
     return;
   }
@@ -774,6 +813,7 @@ static int fgmres_cycle(or_handle* h, int d, const double* vin, int m,
 #define Hh(i, j) (W->H[(i) + (int64_t)(j) * (M1 + 1)])
 #define Hr(i, j) (W->Hraw[(i) + (int64_t)(j) * (M1 + 1)])
   *bad = 0;
+  OR_PAR_FOR
   for (int64_t i = 0; i < n; i++) Vc(0)[i] = RND(p, vin[i]);
   double beta = lnrm2(h, q, n, Vc(0));
   W->beta = beta;
@@ -783,6 +823,7 @@ static int fgmres_cycle(or_handle* h, int d, const double* vin, int m,
     skip_calls(h, d, m);
     return 0;
   }
+  OR_PAR_FOR
   for (int64_t i = 0; i < n; i++) Vc(0)[i] = RND(p, RND(q, Vc(0)[i] / beta));
   for (int j = 0; j <= m; j++) W->g[j] = 0.0;
   W->g[0] = beta;
@@ -792,6 +833,7 @@ static int fgmres_cycle(or_handle* h, int d, const double* vin, int m,
     /* z_j = P(v_j) */
     apply_prec(h, d, Vc(j), Zc(j));
     if (!all_finite(n, Zc(j))) { /* identity fallback for a bad inner output */
+      OR_PAR_FOR
       for (int64_t i = 0; i < n; i++) Zc(j)[i] = Vc(j)[i];
       h->st.fallbacks++;
     }
@@ -803,6 +845,7 @@ static int fgmres_cycle(or_handle* h, int d, const double* vin, int m,
     h->st.spmv[d]++;
     /* classical Gram-Schmidt: all h_ij from the same w */
     for (int i = 0; i <= j; i++) Hh(i, j) = ldot(h, q, n, w, Vc(i));
+    OR_PAR_FOR
     for (int64_t k = 0; k < n; k++) {
       double acc = w[k];
       for (int i = 0; i <= j; i++) acc = RND(q, acc - RND(q, Hh(i, j) * Vc(i)[k]));
@@ -854,6 +897,7 @@ static int fgmres_cycle(or_handle* h, int d, const double* vin, int m,
       done = 1;
       break;
     }
+    OR_PAR_FOR
     for (int64_t k = 0; k < n; k++) Vc(j + 1)[k] = RND(p, RND(q, w[k] / hn));
     if (tolabs > 0.0 && fabs(W->g[j + 1]) < tolabs) {
       meff = j + 1;
@@ -869,6 +913,7 @@ static int fgmres_cycle(or_handle* h, int d, const double* vin, int m,
     W->y[i] = RND(q, acc / Hh(i, i));
   }
   /* u = Z y */
+  OR_PAR_FOR
   for (int64_t k = 0; k < n; k++) {
     double acc = 0.0;
     for (int j = 0; j < meff; j++) acc = RND(q, acc + RND(q, W->y[j] * Zc(j)[k]));
@@ -902,7 +947,9 @@ static void richardson(or_handle* h, int d, const double* vin, double* out) {
   int32_t c = h->p.c;
   if (cn == 1) /* the first call: omega_1 = ... = omega_m = 1 */
     for (int k = 0; k < L->m; k++) om[k] = RND(q, h->p.omega_init);
+  OR_PAR_FOR
   for (int64_t i = 0; i < n; i++) v[i] = RND(p, vin[i]);
+  OR_PAR_FOR
   for (int64_t i = 0; i < n; i++) z[i] = 0.0; /* z_0 = 0 */
   rich_trace* T = (h->tr.on && h->tr.d == d) ? &h->tr : NULL;
   if (T) {
@@ -912,10 +959,12 @@ static void richardson(or_handle* h, int d, const double* vin, double* out) {
   for (int k = 0; k < L->m; k++) {
     /* r_{k-1} = v - A z_{k-1}; r_0 = v without computation */
     if (k == 0) {
+      OR_PAR_FOR
       for (int64_t i = 0; i < n; i++) r[i] = v[i];
     } else {
       csr_mv(n, h->rp, h->ci, h->alev[L->pA], q, q, z, t);
       h->st.spmv[d]++;
+      OR_PAR_FOR
       for (int64_t i = 0; i < n; i++) r[i] = RND(p, RND(q, v[i] - t[i]));
     }
     /* y = M r_{k-1} (or the next level when R is not innermost) */
@@ -934,6 +983,7 @@ static void richardson(or_handle* h, int d, const double* vin, double* out) {
       den_k = den;
       if (T) memcpy(T->ta + (int64_t)k * n, t, (size_t)n * sizeof(double));
       if (den > 0.0 && isfinite(wp)) {
+        OR_PAR_FOR
         for (int64_t i = 0; i < n; i++) z[i] = RND(p, RND(q, z[i] + RND(q, wp * y[i])));
         int64_t l = cn / c;
         om[k] = RND(q, RND(q, RND(q, (double)l * om[k]) + wp) / (double)(l + 1));
@@ -943,6 +993,7 @@ static void richardson(or_handle* h, int d, const double* vin, double* out) {
       }
     }
     if (!updated) {
+      OR_PAR_FOR
       for (int64_t i = 0; i < n; i++) z[i] = RND(p, RND(q, z[i] + RND(q, om[k] * y[i])));
       wp_used = om[k];
     }
@@ -965,6 +1016,7 @@ static void richardson(or_handle* h, int d, const double* vin, double* out) {
   }
   h->cntr[d] = cn + 1;
   h->st.r_calls++;
+  OR_PAR_FOR
   for (int64_t i = 0; i < n; i++) out[i] = z[i];
   if (h->p.poison_call > 0 && h->st.r_calls == h->p.poison_call) out[0] = NAN;
 }
@@ -991,6 +1043,7 @@ void or_apply_level(or_handle* h, int32_t d, const double* v, double* z) {
 static void residual64(const or_handle* h, const double* b, const double* x,
                        double* r) {
   csr_mv(h->n, h->rp, h->ci, h->a, OR_F64, OR_F64, x, r);
+  OR_PAR_FOR
   for (int64_t i = 0; i < h->n; i++) r[i] = b[i] - r[i];
 }
 
@@ -1037,6 +1090,7 @@ static int32_t outer_solve(or_handle* h, const double* b, double* x,
         status = OR_ERR_BREAKDOWN;
         break;
       }
+      OR_PAR_FOR
       for (int64_t i = 0; i < n; i++) x[i] = x[i] + u[i];
       residual64(h, b, x, r);
       rel = nrm2(OR_F64, n, r) / bnorm;

@@ -63,7 +63,8 @@ typedef struct {
   int32_t ilu_blocks;      /* block-Jacobi ILU(0): number of row blocks */
   int32_t dot_order;       /* summation order of the level dots and norms:
                               0 left to right (default), 1 right to left,
-                              2 blocks of 1024, 3 pairwise */
+                              2, 4, 5, 6 blocks of 1024, 64, 256, 4096,
+                              3, 7 pairwise with runs of 8, 32 */
 } or_params;
 
 #define OR_M_SGS 0
@@ -115,6 +116,8 @@ int32_t or_krylov_solve(or_handle* h, int32_t method, int32_t m64, const double*
 
 /* ---- pieces, for lockstep comparisons and pins ---- */
 int64_t or_n(const or_handle* h);
+/* threads the library's parallel loops use (1 for the plain build) */
+int32_t or_threads(void);
 void or_get_scaling(const or_handle* h, double* s);
 void or_get_level_values(const or_handle* h, int32_t p, double* vals);
 void or_get_m_factors(const or_handle* h, int32_t* wrp, int32_t* wci,

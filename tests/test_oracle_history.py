@@ -19,7 +19,7 @@ def _solve(A, variant, order, tol=1e-10):
     return o, info
 
 
-@pytest.mark.parametrize("order", [0, 1, 2, 3])
+@pytest.mark.parametrize("order", list(range(8)))
 def test_every_order_converges_and_certifies(order):
     A = W.poisson2d(40)
     o, info = _solve(A, O.FP16_F3R, order)
@@ -39,7 +39,7 @@ def test_orders_are_sums_within_the_dot_product_bound():
     v /= np.linalg.norm(v)
     v = NP.cast(NP.F32, v)
     hs = []
-    for order in (0, 1, 2, 3):
+    for order in range(8):
         p = O.default_params(O.FP16_F3R)
         p.dot_order = order
         o = O.Oracle(A.row_ptr, A.col_idx, A.val, p)
@@ -59,7 +59,7 @@ def test_integer_dots_are_exact_in_every_order():
     d = np.arange(1, n + 1, dtype=np.float64) % 7 + 1
     A = CSR(n, np.arange(n + 1, dtype=np.int32), np.arange(n, dtype=np.int32), d, "diag")
     v = (np.arange(n) % 5 - 2).astype(np.float64)
-    for order in (0, 1, 2, 3):
+    for order in range(8):
         p = O.make_params([(O.FGMRES, 1, O.F64, O.F64), (O.FGMRES, 1, O.F64, O.F64)], pM=O.F64)
         p.dot_order = order
         p.m_identity = 1
