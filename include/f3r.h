@@ -186,7 +186,10 @@ typedef struct {
   int32_t entry_chunk[3];   /* entries per load chunk of the same three sweeps */
   double tune_ms;        /* set-up time spent timing the candidate shapes */
   int32_t layout;        /* F3R_LAYOUT_SELL, _DIAG or _SLICE: format in use */
-  int32_t reserved_i;
+  int32_t ilu_sweep;     /* F3R_M_ILU: forms of the triangular sweeps launched
+                            since set-up, a bit mask: 1 = level windows staged
+                            in LDS, 2 = block vector in LDS without windows,
+                            4 = vector in global memory (0 otherwise) */
 } f3r_info;
 
 typedef struct f3r_handle f3r_handle;
@@ -244,9 +247,16 @@ f3r_status f3r_fgmres_solve(f3r_handle* h, const double* b, double* x,
 f3r_status f3r_krylov_solve(f3r_handle* h, int32_t method, int32_t prec_m, const double* b,
                             double* x, double tol, int32_t max_iter, f3r_info* info);
 
-/* Relative residual estimate after every outermost iteration of the last
-   solve (level 0 only).  Copies min(cap, available) values to buf (host),
-   *len = available.  Errors: F3R_ERR_ARG. */
+/* Residual history of the last solve (Sec. 4.2: each FGMRES level's Givens
+   estimate).  level 0: the relative residual estimate |g_{j+1}| / ||b||
+   after every outermost iteration.  level d >= 1 (an FGMRES level): the
+   estimate |g_{j+1}| / beta of that level after every iteration of every
+   call, in order (beta = the norm of the call's input; a call that ends in
+   a breakdown records the iterations it made; calls skipped because an
+   outer level stopped record nothing); at most 1,000 outermost iterations'
+   worth are kept, and none for batched handles (*len = 0).  Copies
+   min(cap, available) values to buf (host), *len = available.
+   Errors: F3R_ERR_ARG (bad level, a Richardson level), F3R_ERR_DEVICE. */
 f3r_status f3r_get_history(const f3r_handle* h, int32_t level, double* buf,
                            int64_t cap, int64_t* len);
 
@@ -326,9 +336,11 @@ f3r_status f3r_debug_spmv(f3r_handle* h, int32_t level, const double* x,
    level `level`'s SpMV (an FGMRES level: level 0 is the fp64 matrix with
    fp64 vectors, deeper levels their Table 1 storage) on the handle's own
    buffers, each bracketed by its own pair of HIP events on the handle's
-   stream.  With scrub_bytes > 0, a device buffer `scrub` (caller-owned) is
-   overwritten before every launch so that the matrix is read from HBM and not
-   from the caches.  *avg_ms = mean launch time.  Overwrites the level's first
+   stream.  With scrub_bytes > 0, a device buffer `scrub` (caller-owned,
+   16-byte aligned, larger than the last-level cache, zero-filled by the
+   caller) is read once before every launch, so that the matrix comes from
+   HBM and not from the caches and no dirty lines are written back during
+   the timed launch.  *avg_ms = mean launch time.  Overwrites the level's first
    Z slot and second V slot (solve state), nothing else.  F3R_ERR_ARG for a
    Richardson level or bad sizes. */
 f3r_status f3r_time_spmv(f3r_handle* h, int32_t level, int32_t reps, void* scrub,

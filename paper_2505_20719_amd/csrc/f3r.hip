@@ -38,6 +38,7 @@ struct LevelRT {
   LevelLayout L;
   double* S = nullptr;
   int* I = nullptr;
+  HistOut hist;         // inner FGMRES level: residual estimates of every call
   // Richardson
   void* rt = nullptr;
   void* ry = nullptr;
@@ -70,6 +71,7 @@ struct f3r_handle {
   uint16_t* kd_true = nullptr;  // diagonal-aligned format: true diagonal positions
   int32_t* ci = nullptr;        // slice-offset format: CSR columns (read-back)
   IluDesc ilu;                  // block-Jacobi ILU(0) schedule when M is ILU
+  int ilu_used = 0;             // ILU sweep forms launched since set-up
   uint32_t* kdr = nullptr;
   int32_t* rp = nullptr;  // CSR row pointers, kept for debug read-back
   double* a64 = nullptr;
@@ -231,6 +233,13 @@ void alloc_levels(f3r_handle* h) {
       L.Z = h->dalloc((size_t)m * n * tsz(L.zt));
       if (d + 1 == p.nlev) L.tmp = h->dalloc((size_t)n * tsz(L.pv));
       L.L.init(m);
+      if (d >= 1 && h->nsys == 1) {
+        // room for 1,000 outermost iterations of calls of this level
+        int64_t per = 1;
+        for (int e = 1; e <= d; e++) per *= p.lev[e].m;
+        L.hist.cap = std::min<int64_t>(1000 * per, (int64_t)1 << 22);
+        L.hist.p = (double*)h->dalloc((size_t)L.hist.cap * sizeof(double));
+      }
       soff[d] = h->dS;
       ioff[d] = h->dI;
       h->dS += L.L.total;
@@ -336,6 +345,10 @@ struct OutSpec {
   int* fb = nullptr;     // non-finite flag of the parent's column (base when cur is set)
 };
 
+// Gram-Schmidt step with nv dots whose finalisation runs inside the update
+// kernel (one system only: the batched layout sums per system)
+bool fuse_dots(const f3r_handle* h, int nv) { return !h->A.sys.blk && nv <= 16; }
+
 void enqueue_rich(Ctx& c, int d, const Basis& vin, const int* stop, void* out, int* fb);
 void enqueue_fgmres(Ctx& c, int d, const Basis& vin, const void* alias_raw, const int* pstop,
                     const OutSpec& out, bool force_entry);
@@ -434,10 +447,11 @@ void enqueue_fgmres(Ctx& c, int d, const Basis& vin, const void* alias_raw, cons
     ci_child.m = C->cfg.m;
     ci_child.g = C->L.g;
     ci_child.scale = C->L.scale;
+    ci_child.beta = C->L.beta;
   }
   const void* v0 = aliased ? alias_raw : L.V;
   if (!aliased) {
-    ChildInit self{L.S, L.I, m, L.L.g, L.L.scale};
+    ChildInit self{L.S, L.I, m, L.L.g, L.L.scale, L.L.beta};
     HIPCHK(entry_cast(c.st, h->A.sys, n, vin, L.V, L.pv, h->partials, pstop));
     HIPCHK(entry_finalize(c.st, h->A.sys, L.q, h->partials, nb, self,
                           child_alias ? &ci_child : nullptr, pstop));
@@ -473,11 +487,21 @@ void enqueue_fgmres(Ctx& c, int d, const Basis& vin, const void* alias_raw, cons
       HIPCHK(spmv_dots(c.st, h->A, h->ah[L.pa], L.pa, zj, L.zt, &bj, fbj, vec_at(L.V, L.pv, j + 1, n),
                        L.pv, v0, vb, j + 1, h->partials, stop));
     probe_end(c, pid);
-    HIPCHK(finalize_sums(c.st, h->A.sys, L.q, h->partials, nb, j + 1, L.S + L.L.scale, hcol, stop));
-    HIPCHK(axpy_norm(c.st, h->A.sys, n, vec_at(L.V, L.pv, j + 1, n), L.pv, v0, vb, j + 1, hcol,
-                     L.S + L.L.scale, h->partials, stop));
-    HIPCHK(givens(c.st, h->A.sys, L.q, h->partials, nb, L.S, L.I, L.L, j, j == m - 1, nullptr,
-                  nullptr, child_alias ? &ci_child : nullptr));
+    if (fuse_dots(h, j + 1)) {
+      // dots finalised inside the update; its norm partials follow the dots
+      void* npart = (char*)h->partials + (size_t)(j + 1) * (size_t)nb * tsz(L.q);
+      int64_t nnb = 0;
+      HIPCHK(axpy_norm_fin(c.st, n, vec_at(L.V, L.pv, j + 1, n), L.pv, v0, vb, j + 1, h->partials, nb,
+                           L.S + L.L.scale, hcol, npart, &nnb, stop));
+      HIPCHK(givens(c.st, h->A.sys, L.q, npart, nnb, L.S, L.I, L.L, j, j == m - 1, nullptr, nullptr,
+                    child_alias ? &ci_child : nullptr, 0.0, L.hist));
+    } else {
+      HIPCHK(finalize_sums(c.st, h->A.sys, L.q, h->partials, nb, j + 1, L.S + L.L.scale, hcol, stop));
+      HIPCHK(axpy_norm(c.st, h->A.sys, n, vec_at(L.V, L.pv, j + 1, n), L.pv, v0, vb, j + 1, hcol,
+                       L.S + L.L.scale, h->partials, stop));
+      HIPCHK(givens(c.st, h->A.sys, L.q, h->partials, nb, L.S, L.I, L.L, j, j == m - 1, nullptr,
+                    nullptr, child_alias ? &ci_child : nullptr, 0.0, L.hist));
+    }
   }
   LevelBasis lb;
   lb.v0 = v0;
@@ -851,12 +875,22 @@ f3r_status outer_solve(f3r_handle* h, const double* b, double* x, double tol, in
                          h->partials, L0.I + I_STOP));
       probe_end(c0, F3R_PROBE_SPMV_L0);
       double* hcol = L0.S + L0.L.H + (int64_t)j * (L0.cfg.m + 1);
-      HIPCHK(finalize_sums(h->st, sl, T64, h->partials, nb, j + 1, L0.S + L0.L.scale, hcol,
-                           L0.I + I_STOP));
-      HIPCHK(axpy_norm(h->st, sl, n, vec_at(L0.V, T64, j + 1, n), T64, L0.V, vec_at(L0.V, T64, 1, n),
-                       j + 1, hcol, L0.S + L0.L.scale, h->partials, L0.I + I_STOP));
-      HIPCHK(givens(h->st, sl, T64, h->partials, nb, L0.S, L0.I, L0.L, j, 0, h->ibn, h->hpin, nullptr,
-                    tol));
+      if (fuse_dots(h, j + 1)) {
+        void* npart = (double*)h->partials + (size_t)(j + 1) * (size_t)nb;
+        int64_t nnb = 0;
+        HIPCHK(axpy_norm_fin(h->st, n, vec_at(L0.V, T64, j + 1, n), T64, L0.V, vec_at(L0.V, T64, 1, n),
+                             j + 1, h->partials, nb, L0.S + L0.L.scale, hcol, npart, &nnb,
+                             L0.I + I_STOP));
+        HIPCHK(givens(h->st, sl, T64, npart, nnb, L0.S, L0.I, L0.L, j, 0, h->ibn, h->hpin, nullptr,
+                      tol));
+      } else {
+        HIPCHK(finalize_sums(h->st, sl, T64, h->partials, nb, j + 1, L0.S + L0.L.scale, hcol,
+                             L0.I + I_STOP));
+        HIPCHK(axpy_norm(h->st, sl, n, vec_at(L0.V, T64, j + 1, n), T64, L0.V, vec_at(L0.V, T64, 1, n),
+                         j + 1, hcol, L0.S + L0.L.scale, h->partials, L0.I + I_STOP));
+        HIPCHK(givens(h->st, sl, T64, h->partials, nb, L0.S, L0.I, L0.L, j, 0, h->ibn, h->hpin, nullptr,
+                      tol));
+      }
       HIPCHK(hipStreamSynchronize(h->st));
       probe_collect(h);
       it++;
@@ -962,6 +996,7 @@ f3r_status outer_solve(f3r_handle* h, const double* b, double* x, double tol, in
       info->probe_launches = h->probe_n;
       info->padded_nnz = h->padded;
       info->layout = layout_of(h->A);
+      info->ilu_sweep = h->ilu_used;
       for (int f = 0; f < 3; f++) {
         info->rows_per_lane[f] = h->kr[f] / 10;
         info->entry_chunk[f] = h->kr[f] % 10;
@@ -1103,7 +1138,10 @@ f3r_status setup_impl(const f3r_csr* A, const f3r_params* p, void* hip_stream, i
     h->kd_true = m.kd_true;
     h->ci = m.ci;
     h->ilu = m.ilu;
-    if (h->ilu.blocks > 0) h->A.ilu = &h->ilu;
+    if (h->ilu.blocks > 0) {
+      h->ilu.used = &h->ilu_used;
+      h->A.ilu = &h->ilu;
+    }
     h->kdr = (uint32_t*)m.A.kdr;
     h->rp = m.rp;
     h->a64 = m.a64;
@@ -1241,7 +1279,25 @@ f3r_status f3r_fgmres_solve(f3r_handle* h, const double* b, double* x, double to
 
 f3r_status f3r_get_history(const f3r_handle* h, int32_t level, double* buf, int64_t cap,
                            int64_t* len) {
-  if (!h || level != 0 || cap < 0 || (cap > 0 && !buf)) return F3R_ERR_ARG;
+  if (!h || level < 0 || level >= h->p.nlev || cap < 0 || (cap > 0 && !buf)) return F3R_ERR_ARG;
+  if (level > 0) {
+    // an inner FGMRES level: the device record of the last solve
+    const LevelRT& L = h->lev[(size_t)level];
+    if (L.cfg.kind != F3R_FGMRES) return F3R_ERR_ARG;
+    int cnt = 0;
+    if (L.hist.p) {
+      if (hipMemcpyAsync(&cnt, L.I + I_HLEN, sizeof(int), hipMemcpyDeviceToHost, h->st) != hipSuccess ||
+          hipStreamSynchronize(h->st) != hipSuccess)
+        return F3R_ERR_DEVICE;
+    }
+    const int64_t k = std::min<int64_t>(cap, cnt);
+    if (k > 0 && (hipMemcpyAsync(buf, L.hist.p, (size_t)k * sizeof(double), hipMemcpyDeviceToHost,
+                                 h->st) != hipSuccess ||
+                  hipStreamSynchronize(h->st) != hipSuccess))
+      return F3R_ERR_DEVICE;
+    if (len) *len = cnt;
+    return F3R_OK;
+  }
   const std::vector<double> none;
   const std::vector<double>& hs = h->history.empty() ? none : h->history[0];
   const int64_t k = std::min<int64_t>(cap, (int64_t)hs.size());
@@ -1297,6 +1353,24 @@ f3r_status f3r_debug_spmv(f3r_handle* h, int32_t level, const double* x, double*
   });
 }
 
+// Reads a buffer once with 16-byte loads (one pass, grid-stride) and writes
+// nothing unless the XOR of everything read equals a value a zero-filled
+// buffer cannot give: evicts the caches without leaving dirty lines behind.
+__global__ void k_scrub_read(const uint4* __restrict__ p, int64_t count, uint32_t* sink) {
+  uint32_t acc = 0;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  for (; i + 3 * stride < count; i += 4 * stride) {
+    const uint4 a = p[i], b = p[i + stride], c = p[i + 2 * stride], d = p[i + 3 * stride];
+    acc ^= a.x ^ a.y ^ a.z ^ a.w ^ b.x ^ b.y ^ b.z ^ b.w ^ c.x ^ c.y ^ c.z ^ c.w ^ d.x ^ d.y ^ d.z ^ d.w;
+  }
+  for (; i < count; i += stride) {
+    const uint4 a = p[i];
+    acc ^= a.x ^ a.y ^ a.z ^ a.w;
+  }
+  if (acc == 0x9e3779b9u) sink[0] = acc;
+}
+
 f3r_status f3r_time_spmv(f3r_handle* h, int32_t level, int32_t reps, void* scrub,
                          int64_t scrub_bytes, double* avg_ms) {
   if (!h || !avg_ms || level < 0 || level >= h->p.nlev || reps < 1 || reps > 10000 ||
@@ -1321,8 +1395,13 @@ f3r_status f3r_time_spmv(f3r_handle* h, int32_t level, int32_t reps, void* scrub
     double total = 0.0;
     hipError_t err = hipSuccess;
     for (int r = 0; r < reps && err == hipSuccess; r++) {
-      // evict the matrix from the caches before each timed launch
-      if (scrub_bytes > 0) err = hipMemsetAsync(scrub, r & 0xff, (size_t)scrub_bytes, h->st);
+      // evict the matrix from the caches before each timed launch (a read,
+      // so the eviction writes nothing back during the timed launch)
+      if (scrub_bytes >= 16) {
+        hipLaunchKernelGGL(k_scrub_read, dim3(4096), dim3(256), 0, h->st, (const uint4*)scrub,
+                           scrub_bytes / 16, (uint32_t*)h->partials);
+        err = hipGetLastError();
+      }
       if (err == hipSuccess) err = hipEventRecord(e0, h->st);
       if (err == hipSuccess)
         err = spmv_dots(h->st, h->A, av, ta, x, tx, nullptr, nullptr, y, ty, nullptr, nullptr, 0,

@@ -62,6 +62,8 @@ struct IluDesc {
   int win_pos = 0, win_ent = 0;  // window capacities (positions, entries)
   int lds_max = 65536;           // LDS bytes a workgroup may take
   bool chunk = false;            // long rows: entries summed four at a time
+  int* used = nullptr;           // host word: forms launched (1 windows, 2 LDS
+                                 // vector, 4 global vector), or null
 };
 
 // Writable arrays of the schedule, filled at set-up.

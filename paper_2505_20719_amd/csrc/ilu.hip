@@ -611,6 +611,7 @@ hipError_t ilu_apply_fwd(hipStream_t st, const SellDesc& A, const void* mv, int 
         const bool win = D.win && wl.total <= D.lds_max;
         // windowed LDS sweep when the block vector and a window fit, else
         // the LDS vector alone, else the global vector
+        if (D.used) *D.used |= win ? 1 : (lb ? 2 : 4);
         auto go = [&](auto ld, auto qtag) -> hipError_t {
           using LDT = decltype(ld);
           using QQ = TYPE_OF(qtag);
@@ -669,6 +670,7 @@ hipError_t ilu_apply_bwd(hipStream_t st, const SellDesc& A, const void* mv, int 
         using Q = wider_t<TM, TT>;
         const WinLds wl = win_lds(rows_max, (int)sizeof(TT), (int)sizeof(TM), D.win_pos, D.win_ent);
         const bool win = D.win && wl.total <= D.lds_max;
+        if (D.used) *D.used |= win ? 1 : (lb ? 2 : 4);
         auto go = [&](auto ep) -> hipError_t {
           using EPI = decltype(ep);
           if (win) {

@@ -109,6 +109,15 @@ hipError_t axpy_norm(hipStream_t st, const SysLayout& sl, int64_t n, void* w, in
                      const void* v0, const void* vb, int nv, const double* h,
                      const double* scales, void* partials, const int* stop);
 
+// The dot finalisation and the update in one kernel, for one system and
+// 1 <= nv <= 16: hcol[l] = round_q(sum_b dot_partials[l dnb + b] * scales[l])
+// (summed in the order finalize_sums uses, so bit for bit its result), then
+// the update and squared norm of axpy_norm, whose *nnb partials (one per
+// 8,192 rows) go to norm_partials, which must not overlap the dot partials.
+hipError_t axpy_norm_fin(hipStream_t st, int64_t n, void* w, int tw, const void* v0, const void* vb,
+                         int nv, const void* dot_partials, int64_t dnb, const double* scales,
+                         double* hcol, void* norm_partials, int64_t* nnb, const int* stop);
+
 // Layout of the device scalars of one FGMRES level (doubles).
 struct LevelLayout {
   int m = 0;
@@ -131,8 +140,9 @@ struct LevelLayout {
 };
 // ints of one FGMRES level
 // I_HOLD (outermost level): the system has finished and its rows are skipped
+// I_HLEN (inner levels): residual estimates recorded in the level's history
 enum { I_MEFF = 0, I_STOP = 1, I_CUR = 2, I_BAD = 3, I_FALLBACKS = 4, I_BREAKDOWNS = 5, I_HOLD = 6,
-       I_FB = 8 };
+       I_HLEN = 7, I_FB = 8 };
 inline int level_ints(int m) { return I_FB + m + 8; }
 
 struct ChildInit {  // state of a child FGMRES level reset by its parent
@@ -140,6 +150,15 @@ struct ChildInit {  // state of a child FGMRES level reset by its parent
   int* I = nullptr;
   int m = 0;
   int64_t g = 0, scale = 0;
+  int64_t beta = -1;  // slot keeping the input norm of the call (-1: none)
+};
+
+// Residual history of an inner FGMRES level: after each Givens step,
+// |g_{j+1}| / beta (beta = the norm of the call's input) is appended at
+// p[I[I_HLEN]++] while I_HLEN < cap.
+struct HistOut {
+  double* p = nullptr;
+  int64_t cap = 0;
 };
 
 // Givens step j of a level whose arithmetic is q (one block):
@@ -151,7 +170,7 @@ struct ChildInit {  // state of a child FGMRES level reset by its parent
 hipError_t givens(hipStream_t st, const SysLayout& sl, int q, const void* partials, int64_t nb,
                   double* S, int* I, const LevelLayout& L, int j, int solve_y,
                   const double* inv_bnorm, double* host_out, const ChildInit* child,
-                  double tol = 0.0);
+                  double tol = 0.0, HistOut hist = HistOut{});
 
 hipError_t backsolve(hipStream_t st, const SysLayout& sl, int q, double* S, int* I,
                      const LevelLayout& L);

@@ -287,6 +287,106 @@ hipError_t axpy_norm(hipStream_t st, const SysLayout& sl, int64_t n, void* w, in
   });
 }
 
+// The same update with the finalisation of the Gram-Schmidt dots folded in
+// (one system, at most kFuseMaxDots dots): every block first sums the
+// per-block dot partials of the level SpMV in the order of k_finalize
+// (thread t of kFinBlock adds entries t, t + kFinBlock, ... in index order,
+// then the waves in a fixed order), so h_l = round_q(sum * scale_l) is the
+// value the separate finalisation gives, bit for bit; logical block 0 stores
+// the column of H.  A block then covers kFuseRows rows (kFuseRowsPerThread
+// per thread), so the squared norm leaves few partials for the Givens step.
+constexpr int kFuseMaxDots = 16;
+constexpr int kFuseRowsPerThread = 8;
+constexpr int kFuseRows = kFinBlock * kFuseRowsPerThread;
+
+template <class TY, class Q>
+__global__ __launch_bounds__(kFinBlock) void k_axpy_norm_fin(
+    int64_t n, TY* __restrict__ w, const TY* __restrict__ v0, const TY* __restrict__ vb, int nv,
+    const Q* __restrict__ dpart, int64_t dnb, const double* __restrict__ scales, double* hcol,
+    Q* __restrict__ npart, int64_t nnb, const int* stop) {
+  __shared__ Q lds[kFinBlock / kWave][kFuseMaxDots];
+  __shared__ Q hs[kFuseMaxDots];
+  const int64_t lb = logical_block(nnb);
+  if (lb >= nnb) return;
+  const int stopped = read_flag(stop);  // checked at the stores
+  const int lane = threadIdx.x & (kWave - 1), wv = threadIdx.x / kWave;
+  int64_t row[kFuseRowsPerThread];
+  bool ok[kFuseRowsPerThread];
+  Q acc[kFuseRowsPerThread];
+#pragma unroll
+  for (int r = 0; r < kFuseRowsPerThread; r++) {
+    const int64_t rr = lb * kFuseRows + (int64_t)r * kFinBlock + threadIdx.x;
+    ok[r] = rr < n;
+    row[r] = ok[r] ? rr : n - 1;
+    acc[r] = widen<Q>(w[row[r]]);
+  }
+  // the dots: per-thread sums in index order, wave sums, waves in order
+  for (int l = 0; l < nv; l++) {
+    Q sl = thread_sum(dpart + (int64_t)l * dnb, dnb);
+    sl = wave_sum(sl);
+    if (lane == 0) lds[wv][l] = sl;
+  }
+  __syncthreads();
+  if ((int)threadIdx.x < nv) {
+    const int l = threadIdx.x;
+    Q sl = 0;
+#pragma unroll
+    for (int i = 0; i < kFinBlock / kWave; i++) sl = sl + lds[i][l];
+    sl = sl * (Q)scales[l];
+    hs[l] = sl;
+    if (lb == 0 && !stopped) hcol[l] = (double)sl;
+  }
+  __syncthreads();
+  for (int l0 = 0; l0 < nv; l0 += 4) {
+    Q vv[4][kFuseRowsPerThread];
+#pragma unroll
+    for (int u = 0; u < 4; u++) {
+      const int l = min(l0 + u, nv - 1);
+      const TY* V = l == 0 ? v0 : vb + (int64_t)(l - 1) * n;
+#pragma unroll
+      for (int r = 0; r < kFuseRowsPerThread; r++) vv[u][r] = widen<Q>(V[row[r]]);
+    }
+#pragma unroll
+    for (int u = 0; u < 4; u++) {
+      const int l = min(l0 + u, nv - 1);
+      const Q hl = hs[l], sc = (Q)scales[l];
+#pragma unroll
+      for (int r = 0; r < kFuseRowsPerThread; r++) {
+        const Q v = widen<Q>(round_to<TY>(vv[u][r] * sc));
+        const Q t = acc[r] - hl * v;
+        acc[r] = (l0 + u < nv) ? t : acc[r];
+      }
+    }
+  }
+  Q sq = 0;
+#pragma unroll
+  for (int r = 0; r < kFuseRowsPerThread; r++) {
+    const TY wr = round_to<TY>(acc[r]);
+    if (ok[r] && !stopped) w[row[r]] = wr;
+    const Q q = ok[r] ? widen<Q>(wr) : Q(0);
+    sq = sq + q * q;
+  }
+  __shared__ Q red[kFinBlock / kWave];
+  const Q tot = fin_block_sum(sq, red);
+  if (threadIdx.x == 0 && !stopped) npart[lb] = tot;
+}
+
+hipError_t axpy_norm_fin(hipStream_t st, int64_t n, void* w, int tw, const void* v0, const void* vb,
+                         int nv, const void* dot_partials, int64_t dnb, const double* scales,
+                         double* hcol, void* norm_partials, int64_t* nnb, const int* stop) {
+  if (nv < 1 || nv > kFuseMaxDots) return hipErrorInvalidValue;
+  const int64_t nb = (n + kFuseRows - 1) / kFuseRows;
+  *nnb = nb;
+  return with_type(tw, [&](auto pw) {
+    using TY = TYPE_OF(pw);
+    using Q = wider_t<TY, TY>;
+    hipLaunchKernelGGL((k_axpy_norm_fin<TY, Q>), dim3((unsigned)physical_grid(nb)), dim3(kFinBlock), 0,
+                       st, n, (TY*)w, (const TY*)v0, (const TY*)vb, nv, (const Q*)dot_partials, dnb,
+                       scales, hcol, (Q*)norm_partials, nb, stop);
+    return hipGetLastError();
+  });
+}
+
 // ---------------------------------------------------------------------------
 // Givens rotations, breakdown handling and the small triangular solve
 // ---------------------------------------------------------------------------
@@ -314,6 +414,7 @@ __device__ __forceinline__ ChildInit child_of(ChildInit c, const SysLayout& sl, 
 __device__ void init_child(const ChildInit& c, double scale0, double beta, int stop) {
   c.S[c.scale] = scale0;
   c.S[c.g] = beta;
+  if (c.beta >= 0) c.S[c.beta] = beta;
   for (int i = 1; i <= c.m; i++) c.S[c.g + i] = 0.0;
   c.I[I_MEFF] = 0;
   c.I[I_STOP] = stop;
@@ -325,7 +426,8 @@ __device__ void init_child(const ChildInit& c, double scale0, double beta, int s
 // orthogonalised w (thread 0 only).
 template <class Q>
 __device__ void givens_core(Q s, double* S, int* I, const LevelLayout& L, int j, int solve_y,
-                            double inv_bnorm, double* host_out, const ChildInit& child, double tol) {
+                            double inv_bnorm, double* host_out, const ChildInit& child, double tol,
+                            const HistOut& hist) {
   const int ld = L.m + 1;
   double* H = S + L.H;
   double* Hraw = S + L.Hraw;
@@ -360,6 +462,7 @@ __device__ void givens_core(Q s, double* S, int* I, const LevelLayout& L, int j,
     g[j + 1] = (double)(-sv * gj);
     g[j] = (double)(c * gj);
     I[I_MEFF] = j + 1;
+    if (hist.p && I[I_HLEN] < hist.cap) hist.p[I[I_HLEN]++] = fabs(g[j + 1]) / S[L.beta];
     if (hn == (Q)0) {
       I[I_BREAKDOWNS] += 1;
       stop = 1;
@@ -387,7 +490,7 @@ __global__ __launch_bounds__(kFinBlock) void k_givens(const Q* __restrict__ part
                                                       double* S, int* I, LevelLayout L, int j,
                                                       int solve_y, const double* inv_bnorm,
                                                       double* host_out, ChildInit child,
-                                                      SysLayout sl, double tol) {
+                                                      SysLayout sl, double tol, HistOut hist) {
   __shared__ Q lds[kFinBlock / kWave];
   const int sy = blockIdx.x;
   int64_t lo, hi;
@@ -399,20 +502,21 @@ __global__ __launch_bounds__(kFinBlock) void k_givens(const Q* __restrict__ part
   if (threadIdx.x != 0 || I[I_STOP]) return;
   const double ibn = inv_bnorm ? inv_bnorm[sy] : 0.0;
   givens_core<Q>(s, S, I, L, j, solve_y, ibn, host_out ? host_out + 4 * sy : nullptr,
-                 child.S ? child_of(child, sl, sy) : child, tol);
+                 child.S ? child_of(child, sl, sy) : child, tol, sy == 0 ? hist : HistOut{});
 }
 
 hipError_t givens(hipStream_t st, const SysLayout& sl, int q, const void* partials, int64_t nb,
                   double* S, int* I, const LevelLayout& L, int j, int solve_y,
-                  const double* inv_bnorm, double* host_out, const ChildInit* child, double tol) {
+                  const double* inv_bnorm, double* host_out, const ChildInit* child, double tol,
+                  HistOut hist) {
   ChildInit c = child ? *child : ChildInit{};
   const dim3 g((unsigned)sl.nsys);
   if (q == T64)
     hipLaunchKernelGGL(k_givens<double>, g, dim3(kFinBlock), 0, st, (const double*)partials, nb, S,
-                       I, L, j, solve_y, inv_bnorm, host_out, c, sl, tol);
+                       I, L, j, solve_y, inv_bnorm, host_out, c, sl, tol, hist);
   else
     hipLaunchKernelGGL(k_givens<float>, g, dim3(kFinBlock), 0, st, (const float*)partials, nb, S, I,
-                       L, j, solve_y, inv_bnorm, host_out, c, sl, tol);
+                       L, j, solve_y, inv_bnorm, host_out, c, sl, tol, hist);
   return hipGetLastError();
 }
 

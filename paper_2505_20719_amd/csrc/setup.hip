@@ -168,11 +168,39 @@ __global__ void k_to_sell(int64_t n, const int32_t* __restrict__ rp, const int32
                           const uint32_t* __restrict__ off, const int32_t* __restrict__ len,
                           const uint16_t* __restrict__ kd, int dkd, SellOut o, int* flags) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
   const int64_t sl = i / 64;
   const int lane = (int)(i % 64);
+  if (sl * 64 >= n) return;
   const uint32_t base = off[sl] + lane;
   const int w = (int)((off[sl + 1] - off[sl]) / 64);
+  if (i >= n) {
+    // lanes of the last slice past the last row: zero values and column 0,
+    // so that every stored position holds defined, finite data (the ILU
+    // finish pass and the format converters walk whole slices)
+    for (int p = 0; p < w; p++) {
+      const uint32_t e = base + (uint32_t)p * 64;
+      if (o.soff) {
+      } else if (o.idx16) {
+        ((int16_t*)o.idx)[e] = 0;
+      } else {
+        ((int32_t*)o.idx)[e] = 0;
+      }
+      o.a64[e] = 0.0;
+      for (int t = 0; t < 4; t++) {
+        if (o.ah[t]) {
+          if (t == T64) ((double*)o.ah[t])[e] = 0.0;
+          else if (t == T32) ((float*)o.ah[t])[e] = 0.f;
+          else ((uint16_t*)o.ah[t])[e] = 0;
+        }
+        if (o.mv[t]) {
+          if (t == T64) ((double*)o.mv[t])[e] = 0.0;
+          else if (t == T32) ((float*)o.mv[t])[e] = 0.f;
+          else ((uint16_t*)o.mv[t])[e] = 0;
+        }
+      }
+    }
+    return;
+  }
   const int64_t lo = rp[i];
   const int L = len[i];
   const double si = s[i];
@@ -237,7 +265,9 @@ __global__ void k_to_sell(int64_t n, const int32_t* __restrict__ rp, const int32
 hipError_t to_sell(hipStream_t st, int64_t n, const int32_t* rp, const int32_t* ci,
                    const double* val, const double* s, const uint32_t* off, const int32_t* len,
                    const uint16_t* kd, int dkd, const SellOut& o, int* flags) {
-  hipLaunchKernelGGL(k_to_sell, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, n, rp, ci, val, s,
+  // whole slices: the lanes past row n - 1 clear their positions
+  const int64_t rows = (n + 63) / 64 * 64;
+  hipLaunchKernelGGL(k_to_sell, dim3((unsigned)((rows + 255) / 256)), dim3(256), 0, st, n, rp, ci, val, s,
                      off, len, kd, dkd, o, flags);
   return hipGetLastError();
 }

@@ -58,7 +58,7 @@ class Info(C.Structure):
                 ("graph_launches", C.c_int64), ("idx_bits", C.c_int32), ("sell_c", C.c_int32),
                 ("probe_ms", C.c_double), ("probe_launches", C.c_int64), ("padded_nnz", C.c_int64),
                 ("rows_per_lane", C.c_int32 * 3), ("entry_chunk", C.c_int32 * 3), ("tune_ms", C.c_double),
-                ("layout", C.c_int32), ("reserved_i", C.c_int32)]
+                ("layout", C.c_int32), ("ilu_sweep", C.c_int32)]
 
     def as_dict(self):
         arrays = ("spmv", "rows_per_lane", "entry_chunk")
@@ -224,7 +224,8 @@ class Solver:
 
     def time_spmv(self, level, reps=10, scrub=None):
         """Mean time (ms) of one launch of level `level`'s SpMV; with `scrub`
-        (a device tensor) overwritten before every launch."""
+        (a zero-filled device tensor larger than the last-level cache) read
+        once before every launch."""
         ms = C.c_double()
         ptr = C.c_void_p(scrub.data_ptr()) if scrub is not None else None
         nb = scrub.numel() * scrub.element_size() if scrub is not None else 0

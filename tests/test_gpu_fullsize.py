@@ -74,6 +74,33 @@ def test_poisson3d_128_level_kernels_bit_exact(poisson128):
     g.close()
 
 
+FULL = {"convdiff_q1_100": lambda: W.convdiff_q1(100),
+        "elasticity_bonds_64": lambda: W.elasticity_bonds(64)}
+
+
+@pytest.mark.parametrize("name", sorted(FULL))
+def test_level_kernels_bit_exact_fullsize(name):
+    # the 27-point (slice-offset format) and the 3x3-block (SELL) workloads
+    # at full size, in the format and sweep shapes set-up picks: level
+    # SpMVs in fp64, fp32, fp16 and bf16 and M in fp16 and bf16 against the
+    # oracle, bit for bit
+    A = FULL[name]()
+    print(f"[case] {name} level SpMVs and M vs oracle (n={A.n}, nnz={A.nnz})", flush=True)
+    x = W.rng.uniform(W.rng.substream(f"fullsize/{name}/x"), A.n, -1, 1)
+    for variant, ov, narrow in ((0, O.FP16_F3R, O.F16), (4, O.BF16_F3R, O.BF16)):
+        g = P().Solver(A.row_ptr, A.col_idx, A.val, P().params_default(variant))
+        o = O.Oracle(A.row_ptr, A.col_idx, A.val, O.default_params(ov))
+        if variant == 0:
+            assert np.array_equal(host(g.debug_spmv(0, dev(x))), o.spmv(x, scaled=0))
+            x32 = O.round_to(O.F32, x)
+            assert np.array_equal(host(g.debug_spmv(1, dev(x32))), o.spmv(x32, 1, O.F32, O.F32, O.F32))
+        xn = O.round_to(narrow, x)
+        assert np.array_equal(host(g.debug_spmv(2, dev(xn))), o.spmv(xn, 1, narrow, O.F32, O.F32)), variant
+        assert np.array_equal(host(g.debug_apply_m(narrow, dev(xn))), o.apply_m(xn, narrow, O.F32)), variant
+        o.close()
+        g.close()
+
+
 @pytest.mark.parametrize("variant", [0, 4])
 def test_convdiff_q1_100_solve(variant):
     A = W.convdiff_q1(100)

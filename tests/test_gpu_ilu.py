@@ -179,16 +179,28 @@ def _upper_bidiagonal(n):
     return CSR(n, np.array(rp, np.int32), np.array(ci, np.int32), np.array(val), f"ubi{n}")
 
 
-@pytest.mark.parametrize("case", ["wide_level", "large_block"])
+# sweep forms (f3r_info.ilu_sweep bits): 1 level windows staged in LDS,
+# 2 block vector in LDS without windows, 4 vector in global memory.  The
+# cases follow from the 160 KB a gfx950 workgroup may take: a 16,384-row
+# upper bidiagonal matrix in 2 blocks has one forward level of 8,192 rows,
+# wider than any window (at most 4,096 positions), so no sweep is windowed
+# and the block vector (64 KB in fp64) sits in LDS alone; a 140^2 Poisson
+# block (19,600 rows) holds its fp64 vector in LDS (157 KB) with no room for
+# a window, its fp16 vector with windows; a 150^2 block's fp64 vector
+# (180 KB) stays in global memory.
+SWEEP_CASES = {
+    "wide_level": (lambda: _upper_bidiagonal(16384), 2, {0: 2, 2: 2}),
+    "lds_vector": (lambda: W.poisson2d(140), 1, {0: 1, 2: 2}),
+    "global_vector": (lambda: W.poisson2d(150), 1, {0: 1, 2: 4}),
+}
+
+
+@pytest.mark.parametrize("case", sorted(SWEEP_CASES))
 def test_sweep_variants_bit_exact(case):
-    # the sweeps without LDS windows: a level wider than a window (the
-    # vector alone in LDS) and a block whose vector exceeds the LDS the
-    # sweeps take (fp64, 22,500 rows: the vector in global memory); one
-    # application of M bit-exact against the oracle in fp16 and fp64
-    if case == "wide_level":
-        A, blocks = _upper_bidiagonal(4096), 2
-    else:
-        A, blocks = W.poisson2d(150), 1
+    # every sweep form: one application of M bit-exact against the oracle in
+    # fp16 and fp64, and the form the launchers took reported by the solve
+    make, blocks, forms = SWEEP_CASES[case]
+    A = make()
     r = np.random.default_rng(8).uniform(-1, 1, A.n)
     for variant in (0, 2):
         p = P().params_default(variant)
@@ -203,5 +215,9 @@ def test_sweep_variants_bit_exact(case):
             assert np.array_equal(host(g.debug_apply_m(O.F16, dev(r16))), o.apply_m(r16, O.F16, O.F32))
         else:
             assert np.array_equal(host(g.debug_apply_m(O.F64, dev(r))), o.apply_m(r, O.F64, O.F64))
+        ov = P().params_default(variant)
+        ov.max_outer = 1
+        _, info = g.solve(dev(r), tol=1e-10, override=ov, raise_on_error=False)
+        assert info.ilu_sweep == forms[variant], (case, variant, info.ilu_sweep)
         g.close()
         o.close()
