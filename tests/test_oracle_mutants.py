@@ -34,8 +34,8 @@ MUTANTS = [
     ("weight mean divides by l instead of l + 1",
      "/ (double)(l + 1));", "/ (double)(l > 1 ? l : 2));", "rich"),
     ("R input not rounded to the level storage",
-     "for (int64_t i = 0; i < n; i++) v[i] = RND(p, vin[i]);\n  for (int64_t i = 0; i < n; i++) z[i] = 0.0;",
-     "for (int64_t i = 0; i < n; i++) v[i] = vin[i];\n  for (int64_t i = 0; i < n; i++) z[i] = 0.0;",
+     "for (int64_t i = 0; i < n; i++) v[i] = RND(p, vin[i]);\n  OR_PAR_FOR\n  for (int64_t i = 0; i < n; i++) z[i] = 0.0;",
+     "for (int64_t i = 0; i < n; i++) v[i] = vin[i];\n  OR_PAR_FOR\n  for (int64_t i = 0; i < n; i++) z[i] = 0.0;",
      "rich"),
     ("M: intermediate W r not rounded to storage",
      "csr_mv(h->n, h->wrp, h->wci, wv, q, pv, r, h->mtmp);",
