@@ -221,6 +221,14 @@ WORKLOADS = {
                     "beta 0.5 (Table 2)", ("fp32", "fp64")),
     "varcoef2d_batch256": (None, "256 variable-coefficient 2D 5-point systems, sides U{32..256}", ()),
 }
+# the larger Table 2 operators (2^x x 2^y x 2^z grids)
+for _sz in ("8_7_7", "8_8_7", "8_8_8"):
+    WORKLOADS[f"hpcg_{_sz}"] = (lambda W, _s=_sz: W.build(f"hpcg_{_s}"),
+                                f"HPCG 27-point operator, 2^({_sz.replace('_', ',')}) grid (Table 2)",
+                                ("fp32", "fp64"))
+    WORKLOADS[f"hpgmp_{_sz}"] = (lambda W, _s=_sz: W.build(f"hpgmp_{_s}"),
+                                 f"HPGMP nonsymmetric 27-point operator, 2^({_sz.replace('_', ',')}) grid, "
+                                 "beta 0.5 (Table 2)", ("fp32", "fp64"))
 
 
 def ablation_settings(P):

@@ -320,6 +320,16 @@ __global__ __launch_bounds__(kFinBlock) void k_axpy_norm_fin(
     row[r] = ok[r] ? rr : n - 1;
     acc[r] = widen<Q>(w[row[r]]);
   }
+  // the first four basis vectors are loaded before the dot reduction, so
+  // their loads overlap its loads and barriers
+  Q vv[4][kFuseRowsPerThread];
+#pragma unroll
+  for (int u = 0; u < 4; u++) {
+    const int l = min(u, nv - 1);
+    const TY* V = l == 0 ? v0 : vb + (int64_t)(l - 1) * n;
+#pragma unroll
+    for (int r = 0; r < kFuseRowsPerThread; r++) vv[u][r] = widen<Q>(V[row[r]]);
+  }
   // the dots: per-thread sums in index order, wave sums, waves in order
   for (int l = 0; l < nv; l++) {
     Q sl = thread_sum(dpart + (int64_t)l * dnb, dnb);
@@ -338,13 +348,14 @@ __global__ __launch_bounds__(kFinBlock) void k_axpy_norm_fin(
   }
   __syncthreads();
   for (int l0 = 0; l0 < nv; l0 += 4) {
-    Q vv[4][kFuseRowsPerThread];
+    if (l0 > 0) {
 #pragma unroll
-    for (int u = 0; u < 4; u++) {
-      const int l = min(l0 + u, nv - 1);
-      const TY* V = l == 0 ? v0 : vb + (int64_t)(l - 1) * n;
+      for (int u = 0; u < 4; u++) {
+        const int l = min(l0 + u, nv - 1);
+        const TY* V = l == 0 ? v0 : vb + (int64_t)(l - 1) * n;
 #pragma unroll
-      for (int r = 0; r < kFuseRowsPerThread; r++) vv[u][r] = widen<Q>(V[row[r]]);
+        for (int r = 0; r < kFuseRowsPerThread; r++) vv[u][r] = widen<Q>(V[row[r]]);
+      }
     }
 #pragma unroll
     for (int u = 0; u < 4; u++) {
@@ -422,68 +433,15 @@ __device__ void init_child(const ChildInit& c, double scale0, double beta, int s
   for (int i = 0; i < c.m; i++) c.I[I_FB + i] = 0;
 }
 
-// The Givens step j of a level, from the summed squared norm s of the
-// orthogonalised w (thread 0 only).
-template <class Q>
-__device__ void givens_core(Q s, double* S, int* I, const LevelLayout& L, int j, int solve_y,
-                            double inv_bnorm, double* host_out, const ChildInit& child, double tol,
-                            const HistOut& hist) {
-  const int ld = L.m + 1;
-  double* H = S + L.H;
-  double* Hraw = S + L.Hraw;
-  double* g = S + L.g;
-  double* cs = S + L.cs;
-  double* sn = S + L.sn;
-  const Q hn = sqrt(s);
-  for (int i = 0; i <= j; i++) Hraw[i + (int64_t)j * ld] = H[i + (int64_t)j * ld];
-  Hraw[j + 1 + (int64_t)j * ld] = (double)hn;
-  for (int i = 0; i < j; i++) {
-    const Q a0 = (Q)H[i + (int64_t)j * ld], a1 = (Q)H[i + 1 + (int64_t)j * ld];
-    const Q c = (Q)cs[i], sv = (Q)sn[i];
-    H[i + (int64_t)j * ld] = (double)(c * a0 + sv * a1);
-    H[i + 1 + (int64_t)j * ld] = (double)(-sv * a0 + c * a1);
-  }
-  if (I[I_FB + j]) I[I_FALLBACKS] += 1;
-  const Q hjj = (Q)H[j + (int64_t)j * ld];
-  const Q rho = (Q)hypot((double)hjj, (double)hn);
-  int stop = 0;
-  if (!(rho != (Q)0) || !isfinite((double)rho) || !isfinite((double)hn)) {
-    I[I_MEFF] = j;
-    I[I_BREAKDOWNS] += 1;
-    if (!isfinite((double)rho) || !isfinite((double)hn)) I[I_BAD] = 1;
-    stop = 1;
-  } else {
-    const Q c = hjj / rho, sv = hn / rho;
-    cs[j] = (double)c;
-    sn[j] = (double)sv;
-    H[j + (int64_t)j * ld] = (double)rho;
-    H[j + 1 + (int64_t)j * ld] = 0.0;
-    const Q gj = (Q)g[j];
-    g[j + 1] = (double)(-sv * gj);
-    g[j] = (double)(c * gj);
-    I[I_MEFF] = j + 1;
-    if (hist.p && I[I_HLEN] < hist.cap) hist.p[I[I_HLEN]++] = fabs(g[j + 1]) / S[L.beta];
-    if (hn == (Q)0) {
-      I[I_BREAKDOWNS] += 1;
-      stop = 1;
-    } else {
-      const Q inv = (Q)1 / hn;
-      S[L.scale + j + 1] = (double)inv;
-      S[L.cbeta] = (double)(hn * inv);
-    }
-  }
-  if (host_out) {
-    const double est = fabs(g[j + 1]) * inv_bnorm;
-    // outermost level: a system that reached the tolerance stops its rows
-    if (tol > 0.0 && est < tol) stop = 1;
-    host_out[0] = est;
-    host_out[1] = (double)(stop | (I[I_BAD] << 1));
-  }
-  I[I_STOP] = stop;
-  I[I_CUR] = j + 1;
-  if (child.S) init_child(child, S[L.scale + j + 1], S[L.cbeta], stop);
-  if (solve_y || stop) back_substitute<Q>(S, I, L);
-}
+// The Givens step with the level state it reads staged in LDS: the threads
+// load the column of H, the rotations, g, the flags and (for the last step)
+// the leading columns of H together, while the norm partials are summed;
+// thread 0 then runs the step on the staged copies, so its serial work waits
+// on no global load.  The step: h_{j+1,j} = sqrt(sum of the norm partials);
+// the previous rotations applied to column j; the new rotation, g, the
+// residual estimate and the history; breakdown and stop handling; the next
+// scale; the state of an aliased child; R y = g on the last step or a stop.
+constexpr int kGivStage = 2048;  // doubles of H staged for the back substitution
 
 template <class Q>
 __global__ __launch_bounds__(kFinBlock) void k_givens(const Q* __restrict__ part, int64_t nb,
@@ -492,17 +450,122 @@ __global__ __launch_bounds__(kFinBlock) void k_givens(const Q* __restrict__ part
                                                       double* host_out, ChildInit child,
                                                       SysLayout sl, double tol, HistOut hist) {
   __shared__ Q lds[kFinBlock / kWave];
+  __shared__ double hc[kMaxM + 1], csl[kMaxM], snl[kMaxM], gl[kMaxM + 1], yl[kMaxM];
+  __shared__ double hm[kGivStage];
+  __shared__ double sc[4];
+  __shared__ int fl[4];
   const int sy = blockIdx.x;
   int64_t lo, hi;
   sys_range(sl, sy, nb, lo, hi);
-  Q s = thread_sum(part + lo, hi - lo);
-  s = fin_block_sum(s, lds);
   S = sys_ptr(S, sy, sl.dS);
   I = sys_ptr(I, sy, sl.dI);
-  if (threadIdx.x != 0 || I[I_STOP]) return;
-  const double ibn = inv_bnorm ? inv_bnorm[sy] : 0.0;
-  givens_core<Q>(s, S, I, L, j, solve_y, ibn, host_out ? host_out + 4 * sy : nullptr,
-                 child.S ? child_of(child, sl, sy) : child, tol, sy == 0 ? hist : HistOut{});
+  const int ld = L.m + 1;
+  const int t = threadIdx.x;
+  if (t <= j) {
+    hc[t] = S[L.H + t + (int64_t)j * ld];
+    gl[t] = S[L.g + t];
+  }
+  if (t < j) {
+    csl[t] = S[L.cs + t];
+    snl[t] = S[L.sn + t];
+  }
+  const int nstage = solve_y && (j + 1) * ld <= kGivStage ? (j + 1) * ld : 0;
+  for (int e = t; e < nstage; e += kFinBlock) hm[e] = S[L.H + e];
+  if (t == kFinBlock - 1) {
+    sc[0] = S[L.g + j + 1];
+    sc[1] = S[L.beta];
+    sc[2] = S[L.scale + j + 1];
+    sc[3] = S[L.cbeta];
+  }
+  if (t == kFinBlock - 2) {
+    fl[0] = I[I_STOP];
+    fl[1] = I[I_FB + j];
+    fl[2] = I[I_HLEN];
+    fl[3] = I[I_BAD];
+  }
+  Q s = thread_sum(part + lo, hi - lo);
+  s = fin_block_sum(s, lds);  // its barriers also publish the staged values
+  if (t != 0 || fl[0]) return;
+  const double inv_bn = inv_bnorm ? inv_bnorm[sy] : 0.0;
+  const HistOut hs = sy == 0 ? hist : HistOut{};
+  if (child.S) child = child_of(child, sl, sy);
+  host_out = host_out ? host_out + 4 * sy : nullptr;
+  double* H = S + L.H;
+  double* Hraw = S + L.Hraw;
+  const Q hn = sqrt(s);
+  for (int i = 0; i <= j; i++) Hraw[i + (int64_t)j * ld] = hc[i];
+  Hraw[j + 1 + (int64_t)j * ld] = (double)hn;
+  for (int i = 0; i < j; i++) {
+    const Q a0 = (Q)hc[i], a1 = (Q)hc[i + 1];
+    const Q c = (Q)csl[i], sv = (Q)snl[i];
+    hc[i] = (double)(c * a0 + sv * a1);
+    hc[i + 1] = (double)(-sv * a0 + c * a1);
+  }
+  if (fl[1]) atomicAdd(I + I_FALLBACKS, 1);
+  const Q hjj = (Q)hc[j];
+  const Q rho = (Q)hypot((double)hjj, (double)hn);
+  int stop = 0, bad = fl[3], meff;
+  double gnext = sc[0], scale_next = sc[2], cbeta = sc[3];
+  const bool fail = !(rho != (Q)0) || !isfinite((double)rho) || !isfinite((double)hn);
+  if (fail) {
+    meff = j;
+    atomicAdd(I + I_BREAKDOWNS, 1);
+    if (!isfinite((double)rho) || !isfinite((double)hn)) bad = 1;
+    stop = 1;
+  } else {
+    const Q c = hjj / rho, sv = hn / rho;
+    S[L.cs + j] = (double)c;
+    S[L.sn + j] = (double)sv;
+    hc[j] = (double)rho;
+    const Q gj = (Q)gl[j];
+    gnext = (double)(-sv * gj);
+    gl[j] = (double)(c * gj);
+    S[L.g + j + 1] = gnext;
+    S[L.g + j] = gl[j];
+    meff = j + 1;
+    if (hs.p && fl[2] < hs.cap) {
+      hs.p[fl[2]] = fabs(gnext) / sc[1];
+      I[I_HLEN] = fl[2] + 1;
+    }
+    if (hn == (Q)0) {
+      atomicAdd(I + I_BREAKDOWNS, 1);
+      stop = 1;
+    } else {
+      const Q inv = (Q)1 / hn;
+      scale_next = (double)inv;
+      cbeta = (double)(hn * inv);
+      S[L.scale + j + 1] = scale_next;
+      S[L.cbeta] = cbeta;
+    }
+  }
+  for (int i = 0; i <= j; i++) H[i + (int64_t)j * ld] = hc[i];
+  if (!fail) H[j + 1 + (int64_t)j * ld] = 0.0;
+  I[I_MEFF] = meff;
+  I[I_BAD] = bad;
+  if (host_out) {
+    const double est = fabs(gnext) * inv_bn;
+    // outermost level: a system that reached the tolerance stops its rows
+    if (tol > 0.0 && est < tol) stop = 1;
+    host_out[0] = est;
+    host_out[1] = (double)(stop | (bad << 1));
+  }
+  I[I_STOP] = stop;
+  I[I_CUR] = j + 1;
+  if (child.S) init_child(child, scale_next, cbeta, stop);
+  if (!(solve_y || stop)) return;
+  if (nstage) {
+    // R y = g from the staged columns (column j as just rotated), rows from
+    // the last, each sum taken left to right, as back_substitute does
+    for (int i = 0; i <= j; i++) hm[i + j * ld] = hc[i];
+    for (int i = meff - 1; i >= 0; i--) {
+      Q acc = (Q)gl[i];
+      for (int k = i + 1; k < meff; k++) acc = acc - (Q)hm[i + k * ld] * (Q)yl[k];
+      yl[i] = (double)(acc / (Q)hm[i + i * ld]);
+    }
+    for (int i = 0; i < meff; i++) S[L.y + i] = yl[i];
+  } else {
+    back_substitute<Q>(S, I, L);
+  }
 }
 
 hipError_t givens(hipStream_t st, const SysLayout& sl, int q, const void* partials, int64_t nb,
