@@ -332,6 +332,22 @@ void f3r_batch_destroy(f3r_batch* bt);
 f3r_status f3r_debug_spmv(f3r_handle* h, int32_t level, const double* x,
                           double* y);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+   capture, tight serving loops, harnesses that forbid allocation): y = M r
+   as f3r_debug_apply_m computes it (same kernels, same results bit for
+   bit), with its two intermediate vectors (the input cast to prec and
+   t = W r) in a fixed 64 MiB device array of the library instead of the
+   handle's workspace, so the call allocates nothing.  Each device keeps
+   its own copy of the array until the process ends; its address is looked
+   up when a handle is set up on that device.  Calls on one device share
+   that array: calls that overlap on one device (several host threads or
+   streams) race, and must be serialised by the caller.  r, y: device
+   arrays of n doubles; prec as for f3r_debug_apply_m.
+   Errors: F3R_ERR_ARG (bad arguments, or 2 n (bytes of prec) rounded up to
+   256 each above 64 MiB: n > 4,194,304 in fp64, 8,388,608 in fp32,
+   16,777,216 in fp16/bf16), F3R_ERR_DEVICE. */
+f3r_status f3r_apply_m_static(f3r_handle* h, int32_t prec, const double* r, double* y);
+
 /* Measurement of the level SpMV of Sec. 4.2 on its own: `reps` launches of
    level `level`'s SpMV (an FGMRES level: level 0 is the fp64 matrix with
    fp64 vectors, deeper levels their Table 1 storage) on the handle's own

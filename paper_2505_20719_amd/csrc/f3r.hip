@@ -15,6 +15,7 @@
 #include <cmath>
 #include <cstring>
 #include <map>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -142,6 +143,9 @@ static const int32_t* soff_of(const f3r_handle* h) {
   return h->A.idx16 == 2 ? (const int32_t*)h->A.idx : nullptr;
 }
 
+
+// address of this device's copy of the fixed scratch (defined with it below)
+static hipError_t scratch_address(int device, void** out);
 
 namespace {
 
@@ -1125,6 +1129,11 @@ f3r_status setup_impl(const f3r_csr* A, const f3r_params* p, void* hip_stream, i
   const double t0 = now_ms();
   f3r_status st = guarded(h, nullptr, [&]() -> f3r_status {
     HIPCHK(hipGetDevice(&h->device));
+    {
+      // the device's copy of the fixed scratch of f3r_apply_m_static
+      void* sp = nullptr;
+      HIPCHK(scratch_address(h->device, &sp));
+    }
     HIPCHK(hipStreamCreateWithFlags(&h->cap, hipStreamNonBlocking));
     // fp64 copy: fp64 levels and the comparison solver
     const bool need[4] = {true, false, false, false};
@@ -1450,6 +1459,70 @@ f3r_status f3r_debug_apply_m(f3r_handle* h, int32_t prec, const double* r, doubl
     HIPCHK(m_apply_g(h->st, h->A, mv, tm, neg, gd, t, prec, 0, nullptr, nullptr, h->tmp64, prec,
                      nullptr, nullptr, nullptr, nullptr, shape(h->kr[1])));
     HIPCHK(convert(h->st, n, h->tmp64, prec, y, T64));
+    HIPCHK(hipStreamSynchronize(h->st));
+    return F3R_OK;
+  });
+}
+
+// ---------------------------------------------------------------------------
+// M applied without allocating: the two intermediate vectors of
+// f3r_debug_apply_m live in a fixed device array of this file instead of the
+// handle's workspace.  Each device holds its own copy of the array; its
+// address on a device is looked up once (hipGetSymbolAddress), with that
+// device current, when a handle is set up there.
+// ---------------------------------------------------------------------------
+constexpr size_t kStaticScratchBytes = (size_t)64 << 20;
+static __device__ __align__(256) unsigned char scratch[kStaticScratchBytes];
+constexpr int kMaxDevices = 64;
+static void* g_scratch[kMaxDevices] = {};
+static std::once_flag g_scratch_once[kMaxDevices];
+static hipError_t g_scratch_err[kMaxDevices] = {};
+
+// address of this device's scratch (the caller has made `device` current)
+static hipError_t scratch_address(int device, void** out) {
+  if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+  std::call_once(g_scratch_once[device], [device]() {
+    void* p = nullptr;
+    g_scratch_err[device] = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (g_scratch_err[device] == hipSuccess) g_scratch[device] = p;
+  });
+  *out = g_scratch[device];
+  return g_scratch_err[device];
+}
+
+f3r_status f3r_apply_m_static(f3r_handle* h, int32_t prec, const double* r, double* y) {
+  if (!h || !r || !y || !prec_ok(prec)) return F3R_ERR_ARG;
+  const int64_t n = h->n;
+  // the input cast to prec and t = W r, each n values of prec, 256-aligned
+  const size_t vec = ((size_t)n * tsz(prec) + 255) & ~(size_t)255;
+  if (2 * vec > kStaticScratchBytes) return F3R_ERR_ARG;
+  return guarded(h, nullptr, [&]() -> f3r_status {
+    HIPCHK(hipSetDevice(h->device));
+    void* base = nullptr;
+    HIPCHK(scratch_address(h->device, &base));
+    if (!base) return F3R_ERR_DEVICE;
+    int tm, neg;
+    const void* mv = m_values(h, tm, neg);
+    double gd = h->gd[tm];
+    if (prec == T64 && tm != T64) {  // the comparison solver's fp64 factors
+      mv = h->m_shared ? h->ah[T64] : h->mv[T64];
+      tm = T64;
+      gd = h->gd[T64];
+    }
+    void* rin = base;
+    void* t = (unsigned char*)base + vec;
+    Basis in;
+    in.raw = rin;
+    in.type = prec;
+    HIPCHK(convert(h->st, n, r, T64, rin, prec));
+    auto shape = [&](int code) { return code % 10 == 3 && tsz(prec) != 2 ? code + 1 : code; };
+    hipError_t e = m_apply_w(h->st, h->A, mv, tm, neg, in, t, prec, nullptr, nullptr, shape(h->kr[0]));
+    if (e == hipErrorInvalidValue) return F3R_ERR_ARG;
+    HIPCHK(e);
+    // y (type prec) over the input, which is dead now
+    HIPCHK(m_apply_g(h->st, h->A, mv, tm, neg, gd, t, prec, 0, nullptr, nullptr, rin, prec, nullptr,
+                     nullptr, nullptr, nullptr, shape(h->kr[1])));
+    HIPCHK(convert(h->st, n, rin, prec, y, T64));
     HIPCHK(hipStreamSynchronize(h->st));
     return F3R_OK;
   });

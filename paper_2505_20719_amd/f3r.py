@@ -102,6 +102,7 @@ EXPORTS = {
     "f3r_batch_destroy": (None, [C.c_void_p]),
     "f3r_debug_spmv": (C.c_int32, [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p]),
     "f3r_debug_apply_m": (C.c_int32, [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p]),
+    "f3r_apply_m_static": (C.c_int32, [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p]),
     "f3r_debug_apply_level": (C.c_int32, [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p]),
     "f3r_debug_scaling": (C.c_int32, [C.c_void_p, C.c_void_p]),
     "f3r_debug_round": (C.c_int32, [C.c_int32, C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p]),
@@ -261,6 +262,13 @@ class Solver:
         import torch
         y = torch.empty_like(r)
         self._check(self.L.f3r_debug_apply_m(self.h, prec, _dptr(r), _dptr(y)), "debug_apply_m")
+        return y
+
+    def apply_m_static(self, prec, r, y):
+        """y = M r like debug_apply_m, into the caller's y, through the entry
+        point that allocates nothing (its intermediates live in the library's
+        fixed device scratch)."""
+        self._check(self.L.f3r_apply_m_static(self.h, prec, _dptr(r), _dptr(y)), "apply_m_static")
         return y
 
     def debug_apply_level(self, level, v):
