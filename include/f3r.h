@@ -62,9 +62,18 @@ typedef int32_t f3r_status;
 /* flags */
 #define F3R_USE_X0 1u          /* x holds the initial guess on entry */
 #define F3R_PERSIST_WEIGHTS 2u /* keep omega and c_ntr from the previous solve */
-#define F3R_NO_GRAPH 4u        /* launch kernels one by one, no hipGraph */
+#define F3R_NO_GRAPH 4u        /* launch kernels one by one (the default; wins over
+                                  F3R_USE_GRAPH) */
 #define F3R_BATCH_LOCKSTEP 8u  /* batches: solve the systems in lockstep with
                                   the per-kernel path (see f3r_setup_batched) */
+#define F3R_USE_GRAPH 16u      /* record each call of the second level (one per
+                                  Richardson update pattern) as a hipGraph and
+                                  replay it.  Off by default: the outermost
+                                  level waits on the host after every
+                                  iteration, so each replay starts on an idle
+                                  GPU, and launching the kernels one by one
+                                  measured as fast or faster (fp16-F3R on the
+                                  128^3 Poisson system 15.1 ms against 15.6 ms) */
 
 /* kernels that f3r_params.probe_kernel can time with HIP events */
 #define F3R_PROBE_NONE 0
@@ -174,7 +183,7 @@ typedef struct {
   double relres_true;    /* ||b - A x|| / ||b|| at exit, fp64 */
   double setup_ms;       /* wall time of f3r_setup */
   double solve_ms;       /* wall time of the solve */
-  int64_t graph_launches; /* F2-call graphs replayed */
+  int64_t graph_launches; /* F2-call graphs replayed (F3R_USE_GRAPH) */
   int32_t idx_bits;      /* 16 or 32: column index width of the device format
                             (0: offsets per slice, no per-entry index) */
   int32_t sell_c;        /* rows per slice of the device format */

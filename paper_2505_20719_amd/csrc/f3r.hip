@@ -45,6 +45,8 @@ struct LevelRT {
   void* ry = nullptr;
   void* rr = nullptr;
   void* rz[2] = {nullptr, nullptr};
+  void* rv = nullptr;   // the level's input rounded to its precision (a Richardson
+                        // level whose preconditioner is the next level)
   double* omega = nullptr;
   double* wcur = nullptr;
   int64_t* cntr_dev = nullptr;
@@ -54,6 +56,10 @@ struct LevelRT {
 struct RSched {
   std::vector<char> upd, poison;
   size_t pos = 0;
+};
+// the schedules of every Richardson level of one enqueue (indexed by level)
+struct RScheds {
+  RSched lev[F3R_MAX_LEVELS];
 };
 
 }  // namespace
@@ -84,8 +90,9 @@ struct f3r_handle {
   int64_t padded = 0;
   // levels
   std::vector<LevelRT> lev;
-  int rich = -1;  // index of the Richardson level, -1 when none
-  int64_t cntr = 1;  // host copy of c_ntr of the Richardson level
+  int rich = -1;  // the innermost level when it is a Richardson level (it applies M), else -1
+  std::vector<int> rlevs;  // every Richardson level (each keeps its own weights, Sec. 4.3)
+  int64_t rcnt[F3R_MAX_LEVELS] = {1, 1, 1, 1, 1, 1, 1, 1};  // host copies of each level's c_ntr
   void* partials = nullptr;
   double* one = nullptr;   // device constant 1.0
   double* tmp64 = nullptr;  // n doubles
@@ -163,6 +170,9 @@ void* vec_at(void* base, int t, int64_t j, int64_t n) {
 
 bool prec_ok(int p) { return p >= F3R_FP64 && p <= F3R_BF16; }
 
+// the inner levels are recorded and replayed as hipGraphs only on request
+bool use_graphs(const f3r_params& p) { return (p.flags & F3R_USE_GRAPH) && !(p.flags & F3R_NO_GRAPH); }
+
 f3r_status check_params(const f3r_params* p) {
   if (!p || p->nlev < 1 || p->nlev > F3R_MAX_LEVELS) return F3R_ERR_ARG;
   if (p->lev[0].kind != F3R_FGMRES || p->lev[0].prec_a != F3R_FP64 || p->lev[0].prec_v != F3R_FP64)
@@ -171,7 +181,10 @@ f3r_status check_params(const f3r_params* p) {
   for (int d = 1; d < p->nlev; d++) {
     const f3r_level& l = p->lev[d];
     if (l.m < 1 || l.m > 64 || !prec_ok(l.prec_a) || !prec_ok(l.prec_v)) return F3R_ERR_ARG;
-    if (l.kind == F3R_RICHARDSON && d != p->nlev - 1) return F3R_ERR_ARG;
+    // a Richardson level below the second; one that is not innermost hands
+    // its vectors to the next level, whose vectors have its precision
+    if (l.kind == F3R_RICHARDSON && d < 2) return F3R_ERR_ARG;
+    if (l.kind == F3R_RICHARDSON && d + 1 < p->nlev && p->lev[d + 1].prec_v != l.prec_v) return F3R_ERR_ARG;
     if (l.kind != F3R_FGMRES && l.kind != F3R_RICHARDSON) return F3R_ERR_ARG;
     // matrix no wider than the vectors, narrow vectors only with equal matrix
     if (l.prec_v == F3R_FP64 && l.prec_a != F3R_FP64) return F3R_ERR_ARG;
@@ -191,6 +204,9 @@ f3r_status check_params(const f3r_params* p) {
   if (!(p->alpha > 0.0) || !std::isfinite(p->alpha)) return F3R_ERR_ARG;
   if (p->c < 0 || p->max_outer < 1) return F3R_ERR_ARG;
   if (p->m_identity != 0) return F3R_ERR_ARG;  // M = I is not provided
+  int nrich = 0;
+  for (int d = 1; d < p->nlev; d++) nrich += p->lev[d].kind == F3R_RICHARDSON;
+  if (nrich > 1 && p->poison_call > 0) return F3R_ERR_ARG;  // the test hook needs one Richardson level
   if (p->layout < F3R_LAYOUT_AUTO || p->layout > F3R_LAYOUT_SLICE) return F3R_ERR_ARG;
   if (p->m_kind != F3R_M_SGS && p->m_kind != F3R_M_ILU) return F3R_ERR_ARG;
   if (p->m_kind == F3R_M_ILU && p->ilu_blocks < 1) return F3R_ERR_ARG;
@@ -220,6 +236,7 @@ void alloc_levels(f3r_handle* h) {
   const int64_t n = h->n;
   h->lev.assign(p.nlev, LevelRT{});
   h->rich = -1;
+  h->rlevs.clear();
   h->dS = 0;
   h->dI = 0;
   std::vector<int64_t> soff((size_t)p.nlev, 0), ioff((size_t)p.nlev, 0);
@@ -249,7 +266,9 @@ void alloc_levels(f3r_handle* h) {
       h->dS += L.L.total;
       h->dI += level_ints(m);
     } else {
-      h->rich = d;
+      if (d + 1 == p.nlev) h->rich = d;
+      else L.rv = h->dalloc((size_t)n * tsz(L.pv));
+      h->rlevs.push_back(d);
       L.rt = h->dalloc((size_t)n * tsz(L.pv));
       L.ry = h->dalloc((size_t)n * tsz(L.pv));
       L.rr = h->dalloc((size_t)n * tsz(L.pv));
@@ -281,8 +300,8 @@ void alloc_levels(f3r_handle* h) {
   h->A.sys.dI = h->dI;
   h->ibn = (double*)h->dalloc(ns * sizeof(double));
   h->mask = (int*)h->dalloc(ns * sizeof(int));
-  if (h->rich >= 0) {
-    const LevelRT& R = h->lev[h->rich];
+  for (int d : h->rlevs) {
+    const LevelRT& R = h->lev[d];
     HIPCHK(set_omega(h->st, h->A.sys, R.omega, R.cfg.m,
                      R.q == T32 ? (double)(float)p.omega_init : p.omega_init));
   }
@@ -294,7 +313,7 @@ void alloc_levels(f3r_handle* h) {
 struct Ctx {
   f3r_handle* h;
   hipStream_t st;
-  RSched* rs;
+  RScheds* rs;
 };
 
 // HIP events around the launches of the probed kernel (direct launches on
@@ -373,15 +392,22 @@ void enqueue_rich(Ctx& c, int d, const Basis& vin, const int* stop, void* out, i
   LevelRT& R = h->lev[d];
   const int tr = R.pv;
   const int m = R.cfg.m;
-  const bool upd = c.rs->upd[c.rs->pos] != 0;
-  const bool poison = c.rs->poison[c.rs->pos] != 0;
-  c.rs->pos++;
-  int tm, neg;
-  const void* mv = m_values(h, tm, neg);
-  const double gd = h->gd[tm];
+  RSched& rs = c.rs->lev[d];
+  const bool upd = rs.upd[rs.pos] != 0;
+  const bool poison = rs.poison[rs.pos] != 0;
+  rs.pos++;
+  const bool inner = d + 1 == h->p.nlev;  // the innermost level applies M
+  int tm = T64, neg = 0;
+  const void* mv = inner ? m_values(h, tm, neg) : nullptr;
+  const double gd = inner ? h->gd[tm] : 1.0;
   const void* av = h->ah[R.pa];
   const void* zprev = nullptr;
   const int64_t nb = n_blocks(h->n);
+  if (!inner) {
+    // v = the input rounded to the level's precision, which the next level
+    // receives as its right-hand side in the first step
+    HIPCHK(entry_cast(c.st, h->A.sys, h->n, vin, R.rv, tr, h->partials, stop));
+  }
   for (int k = 0; k < m; k++) {
     const bool last = k == m - 1;
     void* zk = last ? out : R.rz[k & 1];
@@ -390,12 +416,40 @@ void enqueue_rich(Ctx& c, int d, const Basis& vin, const int* stop, void* out, i
     if (k == 0) {
       rsrc = vin;
     } else {
-      const int nr = probe_begin(c, F3R_PROBE_R_RESIDUAL);
+      const int nr = inner ? probe_begin(c, F3R_PROBE_R_RESIDUAL) : 1;
       for (int r = 0; r < nr; r++)
         HIPCHK(rich_residual(c.st, h->A, av, R.pa, vin, zprev, R.rr, tr, stop, h->kr[2]));
-      probe_end(c, F3R_PROBE_R_RESIDUAL);
+      if (inner) probe_end(c, F3R_PROBE_R_RESIDUAL);
       rsrc.raw = R.rr;
       rsrc.type = tr;
+    }
+    if (!inner) {
+      // y = the next level applied to r (Sec. 4.3: Richardson at several
+      // levels, each with its own weights), then the update of z
+      Basis cin;
+      cin.raw = k == 0 ? R.rv : R.rr;
+      cin.type = tr;
+      if (k == 0) HIPCHK(cntr_advance(c.st, R.cntr_dev));
+      const LevelRT& C = h->lev[d + 1];
+      if (C.cfg.kind == F3R_FGMRES) {
+        OutSpec o;
+        o.ptr = R.ry;
+        enqueue_fgmres(c, d + 1, cin, nullptr, stop, o, true);
+      } else {
+        enqueue_rich(c, d + 1, cin, stop, R.ry, nullptr);
+      }
+      if (!upd) {
+        HIPCHK(rich_zupdate(c.st, h->A.sys, h->n, k == 0 ? nullptr : zprev, R.ry, tr, R.omega + k, zk,
+                            zfb, stop));
+      } else {
+        HIPCHK(rich_tdots(c.st, h->A, av, R.pa, R.ry, tr, rsrc, h->partials, stop));
+        HIPCHK(rich_omega(c.st, h->A.sys, q_of(tr), h->partials, nb, R.omega + k, R.wcur, R.cntr_dev,
+                          h->p.c, stop));
+        HIPCHK(rich_zupdate(c.st, h->A.sys, h->n, k == 0 ? nullptr : zprev, R.ry, tr, R.wcur, zk, zfb,
+                            stop));
+      }
+      zprev = zk;
+      continue;
     }
     const int nw = probe_begin(c, F3R_PROBE_M_LOWER);
     for (int r = 0; r < nw; r++)  // the call counter advances once
@@ -625,39 +679,72 @@ void autotune(f3r_handle* h) {
   h->tune_ms = now_ms() - t0;
 }
 
-// initial weight in the Richardson level's arithmetic
-double omega_init_q(const f3r_handle* h) {
+// initial weight in the arithmetic of Richardson level d
+double omega_init_q(const f3r_handle* h, int d) {
   const double w = h->p.omega_init;
-  return h->lev[h->rich].q == T32 ? (double)(float)w : w;
+  return h->lev[d].q == T32 ? (double)(float)w : w;
 }
 
-// Richardson calls made by one invocation of level 1
-int64_t r_calls_per_f2(const f3r_params& p) {
-  if (p.nlev < 2 || p.lev[p.nlev - 1].kind != F3R_RICHARDSON) return 0;
+// calls of level d made by one call of level `from` (from <= d)
+int64_t calls_between(const f3r_params& p, int from, int d) {
   int64_t c = 1;
-  for (int d = 1; d < p.nlev - 1; d++) c *= p.lev[d].m;
+  for (int e = from; e < d; e++) c *= p.lev[e].m;
   return c;
 }
 
-RSched make_sched(f3r_handle* h, int64_t ncalls, int64_t executed_before) {
-  RSched rs;
-  rs.upd.resize((size_t)std::max<int64_t>(ncalls, 1), 0);
-  rs.poison.resize((size_t)std::max<int64_t>(ncalls, 1), 0);
-  for (int64_t i = 0; i < ncalls; i++) {
-    const int64_t cn = h->cntr + i;
-    rs.upd[(size_t)i] = h->p.c > 0 && cn % h->p.c == 0;
-    rs.poison[(size_t)i] = h->p.poison_call > 0 && executed_before + i + 1 == h->p.poison_call;
+// Update and poison flags of every call, in order, of each Richardson level
+// at or below `from` during one call of level `from` (Alg. 1: an update when
+// the level's c_ntr is a multiple of c).  executed_inner: calls of the
+// innermost Richardson level made before (the poison test hook counts them).
+RScheds make_scheds(const f3r_handle* h, int from, int64_t executed_inner) {
+  RScheds rs;
+  for (int d : h->rlevs) {
+    if (d < from) continue;
+    const int64_t ncalls = calls_between(h->p, from, d);
+    RSched& r = rs.lev[d];
+    r.upd.assign((size_t)ncalls, 0);
+    r.poison.assign((size_t)ncalls, 0);
+    for (int64_t i = 0; i < ncalls; i++) {
+      const int64_t cn = h->rcnt[d] + i;
+      r.upd[(size_t)i] = h->p.c > 0 && cn % h->p.c == 0;
+      r.poison[(size_t)i] = d == h->rich && h->p.poison_call > 0 && executed_inner + i + 1 == h->p.poison_call;
+    }
   }
   return rs;
 }
 
-std::string sched_key(const RSched& rs) {
-  std::string k(rs.upd.size() * 2, '0');
-  for (size_t i = 0; i < rs.upd.size(); i++) {
-    k[2 * i] = rs.upd[i] ? '1' : '0';
-    k[2 * i + 1] = rs.poison[i] ? '1' : '0';
+std::string sched_key(const RScheds& rs) {
+  std::string k;
+  for (int d = 0; d < F3R_MAX_LEVELS; d++) {
+    const RSched& r = rs.lev[d];
+    if (r.upd.empty()) continue;
+    k += 'L';
+    k += (char)('0' + d);
+    for (size_t i = 0; i < r.upd.size(); i++) {
+      k += r.upd[i] ? '1' : '0';
+      k += r.poison[i] ? '1' : '0';
+    }
   }
   return k;
+}
+
+// sets the weights of every Richardson level at or below `from` whose next
+// call is its first (Alg. 1: omega_k = 1 at the first call), and after the
+// enqueue advances the host counters by the calls it made
+void scheds_begin(f3r_handle* h, hipStream_t st, int from) {
+  for (int d : h->rlevs)
+    if (d >= from && h->rcnt[d] == 1)
+      HIPCHK(set_omega(st, h->A.sys, h->lev[d].omega, h->lev[d].cfg.m, omega_init_q(h, d)));
+}
+void scheds_end(f3r_handle* h, const RScheds& rs, int from, int64_t* upd) {
+  for (int d : h->rlevs) {
+    if (d < from) continue;
+    const RSched& r = rs.lev[d];
+    int64_t u = 0;
+    for (char f : r.upd) u += f;
+    if (upd) upd[d] = u;
+    h->rcnt[d] += (int64_t)r.upd.size();
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -665,18 +752,17 @@ std::string sched_key(const RSched& rs) {
 // ---------------------------------------------------------------------------
 struct SolveStats {
   int outer = 0, restarts = 0;
-  int64_t r_calls = 0, m_calls = 0, upd_calls = 0;
+  int64_t m_calls = 0;
+  int64_t rc[F3R_MAX_LEVELS] = {}, ru[F3R_MAX_LEVELS] = {};  // Richardson calls and updates per level
   double est = 0, relres = 0;
 };
 
-// one call of the second level for every system; returns the number of
-// Richardson calls of it that update the weights
-int64_t f2_call(f3r_handle* h, SolveStats& ss, bool use_graph) {
+// one call of the second level for every system; upd[d]: the Richardson
+// calls of level d in it that update the weights
+void f2_call(f3r_handle* h, SolveStats& ss, bool use_graph, int64_t* upd) {
   LevelRT& L0 = h->lev[0];
-  const int64_t ncalls = r_calls_per_f2(h->p);
-  RSched rs = make_sched(h, ncalls, ss.r_calls);
-  if (h->rich >= 0 && h->cntr == 1)  // Alg. 1: the first call sets every weight to omega_init
-    HIPCHK(set_omega(h->st, h->A.sys, h->lev[h->rich].omega, h->lev[h->rich].cfg.m, omega_init_q(h)));
+  RScheds rs = make_scheds(h, 1, h->rich >= 0 ? ss.rc[h->rich] : 0);
+  scheds_begin(h, h->st, 1);
   Basis in;
   in.raw = L0.V;
   in.type = T64;
@@ -708,7 +794,6 @@ int64_t f2_call(f3r_handle* h, SolveStats& ss, bool use_graph) {
       HIPCHK(hipGraphInstantiate(&ex, g, nullptr, nullptr, 0));
       h->graph_objs.push_back(g);
       h->graphs[key] = ex;
-      rs.pos = 0;
     } else {
       ex = it->second;
     }
@@ -718,12 +803,11 @@ int64_t f2_call(f3r_handle* h, SolveStats& ss, bool use_graph) {
     Ctx c{h, h->st, &rs};
     enqueue_fgmres(c, 1, in, nullptr, L0.I + I_STOP, out, false);
   }
-  int64_t upd = 0;
-  for (int64_t i = 0; i < ncalls; i++) upd += rs.upd[(size_t)i];
-  ss.upd_calls += upd;
-  h->cntr += ncalls;
-  ss.r_calls += ncalls;
-  return upd;
+  scheds_end(h, rs, 1, upd);
+  for (int d : h->rlevs) {
+    ss.rc[d] += calls_between(h->p, 1, d);
+    ss.ru[d] += upd[d];
+  }
 }
 
 void baseline_prec(f3r_handle* h) {
@@ -749,7 +833,8 @@ void baseline_prec(f3r_handle* h) {
 struct SysStat {
   f3r_status status = F3R_NOT_CONVERGED;
   int outer = 0, restarts = 0;
-  int64_t r_calls = 0, upd_calls = 0, m_calls = 0;
+  int64_t m_calls = 0;
+  int64_t rc[F3R_MAX_LEVELS] = {}, ru[F3R_MAX_LEVELS] = {};  // Richardson calls and updates per level
   double est = 0, relres = 0;
   bool hold = false;   // finished (or failed): its rows are skipped by every kernel
   bool run = false;    // iterating in the current cycle
@@ -800,16 +885,17 @@ f3r_status outer_solve(f3r_handle* h, const double* b, double* x, double tol, in
   h->probe_n = 0;
   h->ev_used = 0;
   if (h->probe) use_graph = false;
-  const int64_t per_f2 = baseline ? 0 : r_calls_per_f2(h->p);
   int64_t m_per_outer = 1;
   if (!baseline)
     for (int d = 1; d < h->p.nlev; d++) m_per_outer *= h->p.lev[d].m;
   if (!(h->p.flags & F3R_USE_X0)) HIPCHK(hipMemsetAsync(x, 0, (size_t)n * sizeof(double), h->st));
-  if (h->rich >= 0 && !(h->p.flags & F3R_PERSIST_WEIGHTS)) {
-    h->cntr = 1;
-    // synchronous: the host copy of the counter changes as calls are enqueued
+  if (!h->rlevs.empty() && !(h->p.flags & F3R_PERSIST_WEIGHTS)) {
+    // synchronous: the host copies of the counters change as calls are enqueued
     HIPCHK(hipStreamSynchronize(h->st));
-    HIPCHK(hipMemcpy(h->lev[h->rich].cntr_dev, &h->cntr, sizeof(int64_t), hipMemcpyHostToDevice));
+    for (int d : h->rlevs) {
+      h->rcnt[d] = 1;
+      HIPCHK(hipMemcpy(h->lev[d].cntr_dev, &h->rcnt[d], sizeof(int64_t), hipMemcpyHostToDevice));
+    }
   }
   // every level's flags and counters of every system start clear
   HIPCHK(hipMemsetAsync(h->Iall, 0, (size_t)ns * (size_t)h->dI * sizeof(int), h->st));
@@ -862,11 +948,11 @@ f3r_status outer_solve(f3r_handle* h, const double* b, double* x, double tol, in
     const int len = std::min(m1, max_outer - omax);
     int it = 0;
     for (int j = 0; j < len; j++) {
-      int64_t upd = 0;
+      int64_t upd[F3R_MAX_LEVELS] = {};
       if (baseline)
         baseline_prec(h);
       else
-        upd = f2_call(h, gs, use_graph);
+        f2_call(h, gs, use_graph, upd);
       void* zj = vec_at(L0.Z, T64, j, n);
       Basis bj;
       bj.raw = vec_at(L0.V, T64, j, n);
@@ -904,8 +990,11 @@ f3r_status outer_solve(f3r_handle* h, const double* b, double* x, double tol, in
         SysStat& q = ss[(size_t)s];
         if (!q.run) continue;
         q.outer++;
-        q.r_calls += per_f2;
-        q.upd_calls += upd;
+        if (!baseline)
+          for (int d : h->rlevs) {
+            q.rc[d] += calls_between(h->p, 1, d);
+            q.ru[d] += upd[d];
+          }
         q.m_calls += baseline ? 1 : m_per_outer;
         q.est = h->hpin[4 * s];
         h->history[(size_t)s].push_back(q.est);
@@ -976,10 +1065,10 @@ f3r_status outer_solve(f3r_handle* h, const double* b, double* x, double tol, in
           if (p.lev[d].kind == F3R_FGMRES)
             info->spmv[d] = (int64_t)q.outer * per * p.lev[d].m;
           else
-            info->spmv[d] = q.r_calls * (p.lev[d].m - 1) + q.upd_calls * p.lev[d].m;
+            info->spmv[d] = q.rc[d] * (p.lev[d].m - 1) + q.ru[d] * p.lev[d].m;
           per *= p.lev[d].m;
         }
-        info->r_calls = q.r_calls;
+        for (int d : h->rlevs) info->r_calls += q.rc[d];
       }
       int64_t fbk = 0, brk = 0;
       for (size_t d = 0; d < h->lev.size(); d++) {
@@ -1265,7 +1354,7 @@ f3r_status f3r_solve(f3r_handle* h, const double* b, double* x, double tol,
   f3r_status s = guarded(h, info, [&]() {
     HIPCHK(hipSetDevice(h->device));
     return outer_solve(h, b, x, tol, h->p.lev[0].m, h->p.max_outer, false,
-                       !(h->p.flags & F3R_NO_GRAPH), info);
+                       use_graphs(h->p), info);
   });
   if (lo) {
     if (h->p.c != saved.c || h->p.poison_call != saved.poison_call) destroy_graphs(h);
@@ -1316,19 +1405,23 @@ f3r_status f3r_get_history(const f3r_handle* h, int32_t level, double* buf, int6
   return F3R_OK;
 }
 
+static bool is_rich(const f3r_handle* h, int32_t level) {
+  return level >= 1 && level < h->p.nlev && h->lev[(size_t)level].cfg.kind == F3R_RICHARDSON;
+}
+
 f3r_status f3r_get_weights(f3r_handle* h, int32_t level, double* omega, int64_t* c_ntr) {
-  if (!h || level != h->rich || h->rich < 0 || !omega) return F3R_ERR_ARG;
+  if (!h || !is_rich(h, level) || !omega) return F3R_ERR_ARG;
   return guarded(h, nullptr, [&]() {
     HIPCHK(hipStreamSynchronize(h->st));
     HIPCHK(hipMemcpy(omega, h->lev[level].omega, (size_t)h->lev[level].cfg.m * sizeof(double),
                      hipMemcpyDeviceToHost));
-    if (c_ntr) *c_ntr = h->cntr;
+    if (c_ntr) *c_ntr = h->rcnt[level];
     return F3R_OK;
   });
 }
 
 f3r_status f3r_set_weights(f3r_handle* h, int32_t level, const double* omega, int64_t c_ntr) {
-  if (!h || level != h->rich || h->rich < 0 || !omega || c_ntr < 1) return F3R_ERR_ARG;
+  if (!h || !is_rich(h, level) || !omega || c_ntr < 1) return F3R_ERR_ARG;
   return guarded(h, nullptr, [&]() {
     // weights are quantities of the level arithmetic (fp32 for narrow levels)
     std::vector<double> w(omega, omega + h->lev[level].cfg.m);
@@ -1336,8 +1429,8 @@ f3r_status f3r_set_weights(f3r_handle* h, int32_t level, const double* omega, in
       for (double& v : w) v = (double)(float)v;
     HIPCHK(hipMemcpy(h->lev[level].omega, w.data(), w.size() * sizeof(double),
                      hipMemcpyHostToDevice));
-    h->cntr = c_ntr;
-    HIPCHK(hipMemcpy(h->lev[level].cntr_dev, &h->cntr, sizeof(int64_t), hipMemcpyHostToDevice));
+    h->rcnt[level] = c_ntr;
+    HIPCHK(hipMemcpy(h->lev[level].cntr_dev, &h->rcnt[level], sizeof(int64_t), hipMemcpyHostToDevice));
     return F3R_OK;
   });
 }
@@ -1536,14 +1629,8 @@ f3r_status f3r_debug_apply_level(f3r_handle* h, int32_t level, const double* v, 
     // every inner-level state flag starts clear
     for (size_t d = 1; d < h->lev.size(); d++)
       if (h->lev[d].I) HIPCHK(hipMemsetAsync(h->lev[d].I, 0, level_ints(h->lev[d].cfg.m) * sizeof(int), h->st));
-    int64_t ncalls = 0;
-    if (h->rich >= 0) {
-      ncalls = 1;
-      for (int d = level; d < h->rich; d++) ncalls *= h->p.lev[d].m;
-    }
-    RSched rs = make_sched(h, ncalls, 0);
-    if (h->rich >= 0 && h->cntr == 1)
-      HIPCHK(set_omega(h->st, h->A.sys, h->lev[h->rich].omega, h->lev[h->rich].cfg.m, omega_init_q(h)));
+    RScheds rs = make_scheds(h, level, 0);
+    scheds_begin(h, h->st, level);
     Ctx c{h, h->st, &rs};
     // the level receives its input in the parent's vector precision
     const int tin = h->p.lev[level - 1].prec_v;
@@ -1563,7 +1650,7 @@ f3r_status f3r_debug_apply_level(f3r_handle* h, int32_t level, const double* v, 
       enqueue_fgmres(c, level, in, nullptr, nullptr, o, true);
       HIPCHK(convert(h->st, n, h->tmp64b, L.pv, z, T64));
     }
-    h->cntr += ncalls;
+    scheds_end(h, rs, level, nullptr);
     HIPCHK(hipMemsetAsync(zero_flag, 0, sizeof(int), h->st));
     HIPCHK(hipStreamSynchronize(h->st));
     return F3R_OK;
@@ -1690,7 +1777,7 @@ f3r_status stacked_solve(f3r_handle* h, const double* const* b, double* const* x
                           h->st));
     if (h->p.flags & F3R_USE_X0) HIPCHK(stack_gather(h->st, io, h->xcat));
     const f3r_status r = outer_solve(h, h->bcat, h->xcat, tol, h->p.lev[0].m, h->p.max_outer,
-                                     h->p.nlev < 2, !(h->p.flags & F3R_NO_GRAPH), infos);
+                                     h->p.nlev < 2, use_graphs(h->p), infos);
     HIPCHK(stack_scatter(h->st, io, h->xcat));
     HIPCHK(hipStreamSynchronize(h->st));
     return r;

@@ -258,6 +258,9 @@ hipError_t rich_tdots(hipStream_t st, const SellDesc& A, const void* av, int ta,
 hipError_t rich_omega(hipStream_t st, const SysLayout& sl, int q, const void* partials,
                       int64_t nb, double* omega_k, double* wcur, const int64_t* cntr, int c,
                       const int* stop);
+// advances a Richardson level's call counter by one (a level whose
+// preconditioner is the next level; the innermost level's W sweep does it)
+hipError_t cntr_advance(hipStream_t st, int64_t* cntr);
 // z = round(zprev + w y) (zprev may be null), w = *wcur
 hipError_t rich_zupdate(hipStream_t st, const SysLayout& sl, int64_t n, const void* zprev,
                         const void* y, int tr, const double* wcur, void* z, int* fbflag,

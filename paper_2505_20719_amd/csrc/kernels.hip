@@ -743,6 +743,15 @@ hipError_t entry_cast(hipStream_t st, const SysLayout& sl, int64_t n, const Basi
     return with_type(in.type, [&](auto pi) -> hipError_t {
       using TIN = TYPE_OF(pi);
       using QQ = wider_t<TIN, TO>;
+      if (!in.scale) {
+        // a stored vector (the right-hand side a Richardson level hands to
+        // an FGMRES level below it)
+        if (in.cur) return hipErrorInvalidValue;
+        LdVec<TIN, QQ> ld{(const TIN*)in.raw};
+        hipLaunchKernelGGL((k_entry<LdVec<TIN, QQ>, TO, Q>), grid_for(n), dim3(kBlock), 0, st, sl, n,
+                           ld, (TO*)out, (Q*)partials, nb, parent_stop);
+        return hipGetLastError();
+      }
       LdBasis<TIN, TO, QQ> ld{(const TIN*)in.raw, in.scale, in.cur, in.stride, 0.0};
       hipLaunchKernelGGL((k_entry<LdBasis<TIN, TO, QQ>, TO, Q>), grid_for(n), dim3(kBlock), 0, st,
                          sl, n, ld, (TO*)out, (Q*)partials, nb, parent_stop);
@@ -1163,6 +1172,15 @@ hipError_t rich_residual(hipStream_t st, const SellDesc& A, const void* av, int 
           return hipErrorInvalidValue;
         } else {
           using Q = wider_t<TA, TR>;
+          if (!in.scale) {
+            // a stored vector of the level's own type (the input a Richardson
+            // level receives from a Richardson level above it)
+            if (in.type != tr || in.cur) return hipErrorInvalidValue;
+            LdVec<TR, Q> ld{(const TR*)in.raw};
+            hipLaunchKernelGGL((k_rres<KR, U, TI, TA, TR, Q, LdVec<TR, Q>>), grid, dim3(kBlock), 0, st,
+                               A, (const TA*)av, ld, (const TR*)z, (TR*)r, stop, nb);
+            return hipGetLastError();
+          }
           return with_type(in.type, [&](auto pin) -> hipError_t {
             using TIN = TYPE_OF(pin);
             using QQ = wider_t<TIN, Q>;
@@ -1288,6 +1306,15 @@ __global__ __launch_bounds__(kFinBlock) void k_romega(const Q* __restrict__ part
       *wcur = (double)ok;
     }
   }
+}
+
+__global__ void k_cntr_advance(int64_t* c) {
+  if (threadIdx.x == 0) *c += 1;
+}
+
+hipError_t cntr_advance(hipStream_t st, int64_t* cntr) {
+  hipLaunchKernelGGL(k_cntr_advance, dim3(1), dim3(64), 0, st, cntr);
+  return hipGetLastError();
 }
 
 hipError_t rich_omega(hipStream_t st, const SysLayout& sl, int q, const void* partials, int64_t nb,

@@ -18,7 +18,7 @@ LIB_PATH = os.path.join(HERE, "libf3r.so")
 FP64, FP32, FP16, BF16 = 0, 1, 2, 3
 FGMRES, RICHARDSON = 0, 1
 VARIANT_FP16, VARIANT_FP32, VARIANT_FP64, VARIANT_FGMRES64, VARIANT_BF16 = 0, 1, 2, 3, 4
-USE_X0, PERSIST_WEIGHTS, NO_GRAPH, BATCH_LOCKSTEP = 1, 2, 4, 8
+USE_X0, PERSIST_WEIGHTS, NO_GRAPH, BATCH_LOCKSTEP, USE_GRAPH = 1, 2, 4, 8, 16
 (PROBE_NONE, PROBE_M_LOWER, PROBE_M_UPPER, PROBE_R_RESIDUAL, PROBE_SPMV_L2, PROBE_SPMV_L1,
  PROBE_SPMV_L0) = range(7)
 MAX_LEVELS = 8

@@ -396,12 +396,12 @@ def test_graph_and_direct_launch_agree_and_runs_are_deterministic():
     import paper_2505_20719_amd as PP
     A, g, o = pair("poisson3d_30")
     xs, b = W.rhs(A, "poisson3d_30")
-    x1, i1 = g.solve(dev(b))
-    x2, i2 = g.solve(dev(b))
     ov = PP.params_default(0)
-    ov.flags = PP.NO_GRAPH
-    x3, i3 = g.solve(dev(b), override=ov)
-    assert i1.graph_launches > 0 and i3.graph_launches == 0
+    ov.flags = PP.USE_GRAPH
+    x1, i1 = g.solve(dev(b), override=ov)  # records the graphs
+    x2, i2 = g.solve(dev(b), override=ov)  # replays them
+    x3, i3 = g.solve(dev(b))               # direct launches (the default)
+    assert i1.graph_launches > 0 and i2.graph_launches > 0 and i3.graph_launches == 0
     assert torch.equal(x1, x2) and torch.equal(x1, x3)
 
 
