@@ -137,6 +137,9 @@ __device__ __forceinline__ void make_slots(const SellDesc& A, int64_t gw, int la
 struct NoInit {
   template <class A> __device__ __forceinline__ void operator()(A&) const {}
 };
+// loaders that split a load (raw) from its conversion (cook)
+template <class T, class = void> struct has_raw : std::false_type {};
+template <class T> struct has_raw<T, std::void_t<typename T::raw_t>> : std::true_type {};
 template <int U, class TI, class TV, class Q, class XF, int KR, class INIT = NoInit>
 __device__ __forceinline__ void rows_sum(const TV* __restrict__ val, const TI* __restrict__ idx,
                                          const RowSlot (&s)[KR], const int (&lo)[KR],
@@ -160,10 +163,38 @@ __device__ __forceinline__ void rows_sum(const TV* __restrict__ val, const TI* _
       }
     }
     Q xv[KR][U];
+    if constexpr (has_raw<XF>::value) {
+      // every gather issued before any conversion: a conversion may hold an
+      // empty volatile asm (the fp32 rounding point), across which the
+      // compiler does not move loads, and each gather would then wait for
+      // the one before it
+      typename XF::raw_t xr[KR][U];
 #pragma unroll
-    for (int r = 0; r < KR; r++) {
+      for (int r = 0; r < KR; r++) {
 #pragma unroll
-      for (int u = 0; u < U; u++) xv[r][u] = x(col_of<TI>(d[r][u], s[r].row, s[r].n));
+        for (int u = 0; u < U; u++) xr[r][u] = x.raw(col_of<TI>(d[r][u], s[r].row, s[r].n));
+      }
+#pragma unroll
+      for (int r = 0; r < KR; r++) {
+#pragma unroll
+        for (int u = 0; u < U; u++) {
+          xv[r][u] = x.cook(xr[r][u]);
+          // a costly conversion (and the entry value) is made here for every
+          // entry, so the compiler does not move it, with its load, into the
+          // branch of the entries that count, where the wait for that load
+          // would be left open at the end of the chunk
+          if constexpr (XF::kCostlyCook) {
+            xv[r][u] = value_barrier(xv[r][u]);
+            v[r][u] = value_barrier(v[r][u]);
+          }
+        }
+      }
+    } else {
+#pragma unroll
+      for (int r = 0; r < KR; r++) {
+#pragma unroll
+        for (int u = 0; u < U; u++) xv[r][u] = x(col_of<TI>(d[r][u], s[r].row, s[r].n));
+      }
     }
     if (i0 == 0) init(acc);
 #pragma unroll
@@ -191,6 +222,7 @@ constexpr int kUnroll = 4;
 // converts it at the end, so nothing waits for it before the entry loads.
 template <class TT, class Q> struct LdVec {
   using raw_t = TT;
+  static constexpr bool kCostlyCook = false;
   const TT* p;
   __device__ __forceinline__ void at_sys(int, const SysLayout&) {}
   __device__ __forceinline__ void init() {}
@@ -206,6 +238,9 @@ template <class TT, class Q> struct LdVec {
 // load before the matrix loads are issued.
 template <class TIN, class TT, class Q> struct LdBasis {
   using raw_t = TIN;
+  // fp32 consumers (with a rounding to a narrower storage type, an fp32
+  // rounding point first); measured: the fp64 levels run best without
+  static constexpr bool kCostlyCook = !std::is_same<Q, double>::value;
   const TIN* p;
   const double* scp;
   const int* cur;
@@ -236,6 +271,7 @@ struct SRaw {
 };
 template <class TT, class Q> struct LdSBasis {
   using raw_t = SRaw;
+  static constexpr bool kCostlyCook = false;
   const double* p;
   const double* scp;
   const double* s;
