@@ -152,7 +152,8 @@ typedef struct {
                                     on it. */
   int32_t entry_chunk;           /* with rows_per_lane != 0: entries per load
                                     chunk (0 = 8, 4, 4 for 1, 2, 4 rows; 3 is
-                                    allowed with 2 or 4 rows and narrow vectors) */
+                                    allowed with 2 or 4 rows and narrow vectors,
+                                    or with layout F3R_LAYOUT_SLICE) */
   int32_t layout;                /* F3R_LAYOUT_*: device format of the matrix
                                     and M; results do not depend on it */
   int32_t m_kind;                /* F3R_M_SGS (default) or F3R_M_ILU */

@@ -99,6 +99,11 @@ constexpr int kBlock = 256;
 constexpr int kR = 4;
 constexpr int kRowsPerBlock = kBlock * kR;
 constexpr int kXcd = 8;
+// Positions read past a slice's last one by a chunk of the slice-offset
+// sums: the value arrays and the offset table of that format carry this
+// many positions of padding (zeros) after the last slice, so a chunk of up
+// to 8 positions is read without clamping.
+constexpr int kSlicePad = 8;
 
 // index of the calling wave in its block, as a wave-uniform (scalar) value
 __device__ __forceinline__ int wave_index() {

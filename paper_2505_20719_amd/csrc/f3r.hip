@@ -218,7 +218,8 @@ f3r_status check_params(const f3r_params* p) {
     const int code = 10 * p->rows_per_lane + p->entry_chunk;
     const int plast = p->lev[p->nlev - 1].prec_v;
     const bool narrow_v = plast == F3R_FP16 || plast == F3R_BF16;
-    if (!(code == 18 || code == 24 || code == 44 || ((code == 23 || code == 43) && narrow_v)))
+    const bool any3 = narrow_v || p->layout == F3R_LAYOUT_SLICE;
+    if (!(code == 18 || code == 24 || code == 44 || ((code == 23 || code == 43) && any3)))
       return F3R_ERR_ARG;
   }
   return F3R_OK;
@@ -607,7 +608,11 @@ void autotune(f3r_handle* h) {
     } else {
       lower = upper = (int)((h->padded / std::max<int64_t>(h->n, 1) - 1) / 2);
     }
-    auto pick = [&](int side) { return side <= 3 && narrow ? 23 : side <= 4 ? 24 : 18; };
+    // (the slice-offset format reads every position of a chunk: a chunk
+    // longer than the side reads values it does not sum, so chunks of three
+    // serve three entries in every precision there)
+    const bool slice = h->A.idx16 == 2;
+    auto pick = [&](int side) { return side <= 3 && (narrow || slice) ? 23 : side <= 4 ? 24 : 18; };
     h->kr[0] = pick(lower);
     h->kr[1] = pick(upper);
     h->kr[2] = 18;
@@ -641,7 +646,7 @@ void autotune(f3r_handle* h) {
   HIPCHK(hipEventCreate(&e0));
   HIPCHK(hipEventCreate(&e1));
   const int cand[5] = {18, 24, 44, 23, 43};
-  const int ncand = tsz(tr) == 2 ? 5 : 3;
+  const int ncand = tsz(tr) == 2 || h->A.idx16 == 2 ? 5 : 3;
   for (int f = 0; f < 3; f++) {
     auto launch = [&](int kr) {
       if (f == 0) {

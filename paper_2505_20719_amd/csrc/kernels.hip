@@ -23,8 +23,9 @@ static_assert(kRowsPerBlock == kSysAlign, "systems are aligned to reduction bloc
 
 // Shape of the sweeps whose shape the set-up autotuner picks (their results
 // do not depend on it), coded as 10 KR + U: KR rows per lane, entries in
-// chunks of U.  Chunks of 3 exist for narrow vectors only (7-point stencils
-// have 3 entries on each side of the diagonal).
+// chunks of U.  Chunks of 3 (7-point stencils have 3 entries on each side of
+// the diagonal) exist for narrow vectors, and for every vector type in the
+// slice-offset format, whose chunks read whole positions unclamped.
 template <class F> static hipError_t with_kr(int code, F&& f) {
   switch (code) {
     case 18: return f(std::integral_constant<int, 1>{}, std::integral_constant<int, 8>{});
@@ -35,7 +36,9 @@ template <class F> static hipError_t with_kr(int code, F&& f) {
   }
   return hipErrorInvalidValue;
 }
-template <int U, class TT> constexpr bool shape_ok() { return U != 3 || sizeof(TT) == 2; }
+template <int U, class TT, class TI> constexpr bool shape_ok() {
+  return U != 3 || sizeof(TT) == 2 || std::is_same<TI, SOff>::value;
+}
 
 static inline dim3 grid_for(int64_t n) { return dim3((unsigned)physical_grid(n_blocks(n))); }
 
@@ -1035,7 +1038,7 @@ hipError_t m_apply_w(hipStream_t st, const SellDesc& A, const void* mv, int tm, 
       using TM = TYPE_OF(pm);
       return with_type(tt, [&](auto pt) -> hipError_t {
         using TT = TYPE_OF(pt);
-        if constexpr (!ok_m<TM, TT>() || !shape_ok<U, TT>()) {
+        if constexpr (!ok_m<TM, TT>() || !shape_ok<U, TT, TI>()) {
           return hipErrorInvalidValue;
         } else {
           using Q = wider_t<TM, TT>;
@@ -1086,7 +1089,7 @@ hipError_t m_apply_g(hipStream_t st, const SellDesc& A, const void* mv, int tm, 
       using TM = TYPE_OF(pm);
       return with_type(tt, [&](auto pt) -> hipError_t {
         using TT = TYPE_OF(pt);
-        if constexpr (!ok_m<TM, TT>() || !shape_ok<U, TT>()) {
+        if constexpr (!ok_m<TM, TT>() || !shape_ok<U, TT, TI>()) {
           return hipErrorInvalidValue;
         } else {
           using Q = wider_t<TM, TT>;
@@ -1168,7 +1171,7 @@ hipError_t rich_residual(hipStream_t st, const SellDesc& A, const void* av, int 
       using TA = TYPE_OF(pa);
       return with_type(tr, [&](auto pr) -> hipError_t {
         using TR = TYPE_OF(pr);
-        if constexpr (!ok_m<TA, TR>() || !shape_ok<U, TR>()) {
+        if constexpr (!ok_m<TA, TR>() || !shape_ok<U, TR, TI>()) {
           return hipErrorInvalidValue;
         } else {
           using Q = wider_t<TA, TR>;

@@ -117,6 +117,121 @@ __device__ __forceinline__ void make_slots(const SellDesc& A, int64_t gw, int la
   }
 }
 
+// ---- range-checked gathers -------------------------------------------------
+// A raw buffer resource over [p, p + bytes): a load at a byte offset at or
+// past the end (a negative offset counts as a large unsigned one) returns
+// zero and reads no memory.  Word 3 selects the 32-bit data format, with no
+// swizzle and no thread-id addressing; the byte count must stay below 2^31.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t buf_over(const void* p, uint32_t bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), (short)0, (int)bytes, 0x00020000);
+}
+template <class T> __device__ __forceinline__ T buf_load(__amdgpu_buffer_rsrc_t r, uint32_t off);
+template <> __device__ __forceinline__ f16 buf_load<f16>(__amdgpu_buffer_rsrc_t r, uint32_t off) {
+  return __builtin_bit_cast(f16, __builtin_amdgcn_raw_buffer_load_b16(r, (int)off, 0, 0));
+}
+template <> __device__ __forceinline__ bf16 buf_load<bf16>(__amdgpu_buffer_rsrc_t r, uint32_t off) {
+  return bf16{__builtin_amdgcn_raw_buffer_load_b16(r, (int)off, 0, 0)};
+}
+template <> __device__ __forceinline__ float buf_load<float>(__amdgpu_buffer_rsrc_t r, uint32_t off) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, (int)off, 0, 0));
+}
+template <> __device__ __forceinline__ double buf_load<double>(__amdgpu_buffer_rsrc_t r, uint32_t off) {
+  return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, (int)off, 0, 0));
+}
+
+// Row sums in the slice-offset format (the same sums as rows_sum below, in
+// the same order).  Everything that locates an entry is uniform over the
+// wave: the slice, the position k, the value row (the 64 values of position
+// k are consecutive) and the column offset d_k from the table, so the value
+// of a lane is a load at a wave-uniform address plus the lane, and its
+// gather is the loader's range-checked load at byte offset (row + d_k) x
+// the element size.  A column outside the vector reads zero (the entry's
+// value is zero there: the row has no such entry).  The positions of a chunk
+// are not clamped to the slice's range (the arrays are padded; the sums
+// mask them).  The ranges are the first lane's: every row of a slice that
+// exists has the same ones, and a missing row's sums are left as they were
+// before the first entry, as with the per-row ranges.
+template <int U, bool NEG, class TV, class Q, class XF, int KR, class INIT>
+__device__ __forceinline__ void rows_sum_slice(const TV* __restrict__ val, const SOff* __restrict__ idx,
+                                               const RowSlot (&s)[KR], const int (&lo)[KR],
+                                               const int (&hi)[KR], const int (&kb)[KR],
+                                               const int (&ke)[KR], Q (&acc)[KR], const XF& x0,
+                                               const INIT& init) {
+  static_assert(U <= kSlicePad, "chunk longer than the padding");
+  XF x = x0;
+  x.bind(s[0].n);
+  const uint32_t lane = threadIdx.x & (kWave - 1);
+  int ulo[KR], ukb[KR], uke[KR];
+  const TV* vrow[KR];
+  const int32_t* trow[KR];
+  uint32_t xrow[KR];
+  int it = 0;
+#pragma unroll
+  for (int r = 0; r < KR; r++) {
+    ulo[r] = __builtin_amdgcn_readfirstlane(lo[r]);
+    const int uhi = __builtin_amdgcn_readfirstlane(hi[r]);
+    ukb[r] = __builtin_amdgcn_readfirstlane(kb[r]);
+    uke[r] = __builtin_amdgcn_readfirstlane(ke[r]);
+    // slice x width: the table row, and the value row of position 0
+    const uint32_t sb = (uint32_t)__builtin_amdgcn_readfirstlane((int)(s[r].e0 >> 6));
+    vrow[r] = val + (size_t)sb * kWave;
+    trow[r] = (const int32_t*)idx + sb;
+    xrow[r] = (uint32_t)s[r].row * XF::kBytes;
+    it = max(it, uhi - ulo[r]);
+  }
+  Q a0[KR];
+  int i0 = 0;
+  do {
+    TV v[KR][U];
+    int32_t d[KR][U];
+#pragma unroll
+    for (int r = 0; r < KR; r++) {
+#pragma unroll
+      for (int u = 0; u < U; u++) {
+        const int k = ulo[r] + i0 + u;
+        v[r][u] = vrow[r][(uint32_t)k * kWave + lane];
+        d[r][u] = trow[r][k];
+      }
+    }
+    typename XF::raw_t xr[KR][U];
+#pragma unroll
+    for (int r = 0; r < KR; r++) {
+#pragma unroll
+      for (int u = 0; u < U; u++) xr[r][u] = x.raw_b(xrow[r] + (uint32_t)d[r][u] * XF::kBytes);
+    }
+    Q xv[KR][U];
+#pragma unroll
+    for (int r = 0; r < KR; r++) {
+#pragma unroll
+      for (int u = 0; u < U; u++) {
+        xv[r][u] = x.cook(xr[r][u]);
+        if constexpr (XF::kCostlyCook) {
+          xv[r][u] = value_barrier(xv[r][u]);
+          v[r][u] = value_barrier(v[r][u]);
+        }
+      }
+    }
+    if (i0 == 0) {
+      init(acc);
+#pragma unroll
+      for (int r = 0; r < KR; r++) a0[r] = acc[r];
+    }
+#pragma unroll
+    for (int r = 0; r < KR; r++) {
+#pragma unroll
+      for (int u = 0; u < U; u++) {
+        const int k = ulo[r] + i0 + u;
+        const Q m = NEG ? -widen<Q>(v[r][u]) : widen<Q>(v[r][u]);
+        const Q t = acc[r] + m * xv[r][u];
+        acc[r] = (k >= ukb[r] && k < uke[r]) ? t : acc[r];
+      }
+    }
+    i0 += U;
+  } while (i0 < it);
+#pragma unroll
+  for (int r = 0; r < KR; r++) acc[r] = s[r].ok ? acc[r] : a0[r];
+}
+
 // For each of the lane's rows, acc_r += sum over entries k in [kb_r, ke_r)
 // of round(a_k x_{c_k}), left to right.  The loop runs over [lo_r, hi_r), a
 // range that is uniform over the slice (so the loads never wait for per-row
@@ -146,6 +261,13 @@ __device__ __forceinline__ void rows_sum(const TV* __restrict__ val, const TI* _
                                          const int (&hi)[KR], const int (&kb)[KR],
                                          const int (&ke)[KR], Q (&acc)[KR], const XF& x,
                                          bool neg = false, const INIT& init = INIT()) {
+  if constexpr (std::is_same<TI, SOff>::value && has_raw<XF>::value) {
+    if (neg)
+      rows_sum_slice<U, true>(val, idx, s, lo, hi, kb, ke, acc, x, init);
+    else
+      rows_sum_slice<U, false>(val, idx, s, lo, hi, kb, ke, acc, x, init);
+    return;
+  }
   int it = 0;
 #pragma unroll
   for (int r = 0; r < KR; r++) it = max(it, hi[r] - lo[r]);
@@ -220,12 +342,19 @@ constexpr int kUnroll = 4;
 // raw(c) loads what entry c needs and cook(raw) converts it; a kernel that
 // uses the row's own value after its sums loads it with raw() first and
 // converts it at the end, so nothing waits for it before the entry loads.
+//
+// bind(n) / raw_b(byte offset): the same loads through a range-checked
+// buffer over the n entries of the vector (the slice-offset gathers).
 template <class TT, class Q> struct LdVec {
   using raw_t = TT;
   static constexpr bool kCostlyCook = false;
+  static constexpr uint32_t kBytes = sizeof(TT);
   const TT* p;
+  uint32_t nb;
   __device__ __forceinline__ void at_sys(int, const SysLayout&) {}
   __device__ __forceinline__ void init() {}
+  __device__ __forceinline__ void bind(int64_t n) { nb = (uint32_t)(n * kBytes); }
+  __device__ __forceinline__ raw_t raw_b(uint32_t off) const { return buf_load<TT>(buf_over(p, nb), off); }
   __device__ __forceinline__ raw_t raw(int64_t c) const { return p[c]; }
   __device__ __forceinline__ Q cook(raw_t v) const { return widen<Q>(v); }
   __device__ __forceinline__ Q operator()(int64_t c) const { return widen<Q>(p[c]); }
@@ -241,11 +370,16 @@ template <class TIN, class TT, class Q> struct LdBasis {
   // fp32 consumers (with a rounding to a narrower storage type, an fp32
   // rounding point first); measured: the fp64 levels run best without
   static constexpr bool kCostlyCook = !std::is_same<Q, double>::value;
+  static constexpr uint32_t kBytes = sizeof(TIN);
   const TIN* p;
   const double* scp;
   const int* cur;
   int64_t stride;
   double sc;
+  uint32_t nb;
+  // after init (which selects the basis vector)
+  __device__ __forceinline__ void bind(int64_t n) { nb = (uint32_t)(n * kBytes); }
+  __device__ __forceinline__ raw_t raw_b(uint32_t off) const { return buf_load<TIN>(buf_over(p, nb), off); }
   // the scale and basis index of system sy
   __device__ __forceinline__ void at_sys(int sy, const SysLayout& sl) {
     scp = sys_ptr(scp, sy, sl.dS);
@@ -272,12 +406,18 @@ struct SRaw {
 template <class TT, class Q> struct LdSBasis {
   using raw_t = SRaw;
   static constexpr bool kCostlyCook = false;
+  static constexpr uint32_t kBytes = 8;
   const double* p;
   const double* scp;
   const double* s;
   const int* cur;
   int64_t stride;
   double sc;
+  uint32_t nb;
+  __device__ __forceinline__ void bind(int64_t n) { nb = (uint32_t)(n * kBytes); }
+  __device__ __forceinline__ raw_t raw_b(uint32_t off) const {
+    return SRaw{buf_load<double>(buf_over(p, nb), off), buf_load<double>(buf_over(s, nb), off)};
+  }
   __device__ __forceinline__ void at_sys(int sy, const SysLayout& sl) {
     scp = sys_ptr(scp, sy, sl.dS);
     cur = sys_ptr(cur, sy, sl.dI);

@@ -408,7 +408,9 @@ f3r_status build_matrix(hipStream_t st, const f3r_csr* A, const f3r_params* p, c
     skd = lmax;
     sw = lmax + 1 + umax;
     sacc = (uint64_t)ns * 64 * sw;
-    sfits = !over && sacc < 0xFFFFFFF0ull;
+    // the gathers of this format go through range-checked buffers of at
+    // most 2^31 - 1 bytes (an fp64 vector of n entries)
+    sfits = !over && sacc + (uint64_t)kSlicePad * 64 < 0xFFFFFFF0ull && (uint64_t)n * 8 < 0x7FFFFFFFull;
   }
   bool diag = false, slice = false;
   if (p->layout == F3R_LAYOUT_DIAG) {
@@ -436,8 +438,12 @@ f3r_status build_matrix(hipStream_t st, const f3r_csr* A, const f3r_params* p, c
   HIPCHK(hipMemcpyAsync(offd, off.data(), (size_t)(ns + 1) * 4, hipMemcpyHostToDevice, st));
   SellOut so;
   int32_t* stab = nullptr;
+  // value arrays: the slice-offset sums read up to kSlicePad positions past
+  // the last slice (zeros, never summed)
+  const size_t vcount = (size_t)acc + (slice ? (size_t)kSlicePad * 64 : 0);
   if (slice) {
-    stab = (int32_t*)al.get((size_t)ns * sw * 4);
+    stab = (int32_t*)al.get(((size_t)ns * sw + kSlicePad) * 4);
+    HIPCHK(hipMemsetAsync(stab + (size_t)ns * sw, 0, kSlicePad * 4, st));
     HIPCHK(slice_table(st, ns, uni, lucd, (int)sw, (int)skd, stab));
     so.soff = stab;
     so.idx16 = 2;
@@ -448,7 +454,7 @@ f3r_status build_matrix(hipStream_t st, const f3r_csr* A, const f3r_params* p, c
   }
   if (uni) al.release(uni);
   if (lucd) al.release(lucd);
-  so.a64 = (double*)al.get((size_t)acc * 8);
+  so.a64 = (double*)al.get(vcount * 8);
   so.alpha = p->alpha;
   if (ilu && (p->ilu_blocks < 1 || p->ilu_blocks > n)) return F3R_ERR_ARG;
   so.ilu_blocks = ilu ? p->ilu_blocks : 0;
@@ -464,12 +470,20 @@ f3r_status build_matrix(hipStream_t st, const f3r_csr* A, const f3r_params* p, c
     need[p->prec_m] = true;
     mask |= 1 << p->prec_m;
   } else {
-    so.mv[p->prec_m] = al.get((size_t)acc * type_size(p->prec_m));
-    if (p->prec_m != T64) so.mv[T64] = al.get((size_t)acc * 8);
+    so.mv[p->prec_m] = al.get(vcount * type_size(p->prec_m));
+    if (p->prec_m != T64) so.mv[T64] = al.get(vcount * 8);
     mask |= 1 << p->prec_m;
   }
   for (int t = 0; t < 4; t++)
-    if (need[t]) so.ah[t] = al.get((size_t)acc * type_size(t));
+    if (need[t]) so.ah[t] = al.get(vcount * type_size(t));
+  if (slice) {
+    const size_t tail = (size_t)kSlicePad * 64;
+    HIPCHK(hipMemsetAsync(so.a64 + acc, 0, tail * 8, st));
+    for (int t = 0; t < 4; t++) {
+      if (so.ah[t]) HIPCHK(hipMemsetAsync((char*)so.ah[t] + (size_t)acc * type_size(t), 0, tail * type_size(t), st));
+      if (so.mv[t]) HIPCHK(hipMemsetAsync((char*)so.mv[t] + (size_t)acc * type_size(t), 0, tail * type_size(t), st));
+    }
+  }
   so.range_mask = mask;
   HIPCHK(to_sell(st, n, m.rp, ci, val, m.s, offd, len, kd, diag ? (int)dkd : (slice ? (int)skd : -1), so,
                  flags));

@@ -544,3 +544,32 @@ def test_time_spmv_entry():
         with pytest.raises(PP.F3RError):
             g.time_spmv(level, reps=reps)
     g.close()
+
+
+@pytest.mark.parametrize("variant", [1, 2])
+def test_wide_vector_chunks_of_three_in_slice_format(variant):
+    # the slice-offset format offers chunks of three in every precision;
+    # fp32 and fp64 nests give bitwise the same solve with every shape
+    PP = P()
+    A = MATS["poisson3d_30"]()
+    xs, b = W.rhs(A, "poisson3d_30")
+    ref = None
+    for kr, ch in ((0, 0), (2, 3), (4, 3), (2, 4), (1, 8)):
+        prm = PP.params_default(variant)
+        prm.rows_per_lane, prm.entry_chunk, prm.layout = kr, ch, PP.LAYOUT_SLICE
+        print(f"[case] poisson3d_30 variant={variant} rows_per_lane={kr} chunk={ch}", flush=True)
+        g = PP.Solver(A.row_ptr, A.col_idx, A.val, prm)
+        x, info = g.solve(dev(b))
+        assert info.status == 0 and info.layout == PP.LAYOUT_SLICE
+        if kr == 0:
+            # the row-length rule: three entries a side, chunks of three
+            assert list(info.entry_chunk)[:2] == [3, 3], list(info.entry_chunk)
+        if ref is None:
+            ref = x
+        else:
+            assert torch.equal(x, ref), (kr, ch)
+        g.close()
+    bad = PP.params_default(variant)
+    bad.rows_per_lane, bad.entry_chunk = 2, 3
+    with pytest.raises(PP.F3RError):
+        PP.Solver(A.row_ptr, A.col_idx, A.val, bad)
