@@ -964,14 +964,20 @@ __global__ __launch_bounds__(kBlock) void k_mw(SellDesc A, const TM* __restrict_
   Q acc[KR];
 #pragma unroll
   for (int r = 0; r < KR; r++) {
-    const int64_t slice = gw * KR + r;
-    // loop bound from the slice; the row's own diagonal position only masks
-    // (diagonal-aligned format: every row's diagonal at dell_kd)
     lo[r] = 0;
-    hi[r] = s[r].ok ? max(A.dell_w ? A.dell_kd : (int)(A.kdr[slice] >> 16), 1) : 1;
     kb[r] = 0;
-    ke[r] = s[r].ok ? (A.dell_w ? A.dell_kd : (int)A.kd[s[r].row]) : 0;
     acc[r] = 0;
+    if constexpr (std::is_same<TI, SOff>::value) {
+      // slice-offset format: every row's diagonal at the common position
+      hi[r] = max(A.dell_kd, 1);
+      ke[r] = A.dell_kd;
+    } else {
+      const int64_t slice = gw * KR + r;
+      // loop bound from the slice; the row's own diagonal position only
+      // masks (diagonal-aligned format: every row's diagonal at dell_kd)
+      hi[r] = s[r].ok ? max(A.dell_w ? A.dell_kd : (int)(A.kdr[slice] >> 16), 1) : 1;
+      ke[r] = s[r].ok ? (A.dell_w ? A.dell_kd : (int)A.kd[s[r].row]) : 0;
+    }
   }
   typename LD::raw_t dg[KR];  // the unit-diagonal term, loaded with the matrix entries
 #pragma unroll
@@ -1003,13 +1009,19 @@ __global__ __launch_bounds__(kBlock) void k_mg(SellDesc A, const TM* __restrict_
   Q acc[KR];
 #pragma unroll
   for (int r = 0; r < KR; r++) {
-    const int64_t slice = gw * KR + r;
-    const int kd = s[r].ok ? (A.dell_w ? A.dell_kd : (int)A.kd[s[r].row]) : 0;
-    // loop from just after the slice's smallest diagonal position
-    lo[r] = s[r].ok ? (A.dell_w ? A.dell_kd : (int)(A.kdr[slice] & 0xffffu)) + 1 : 0;
-    hi[r] = s[r].ok ? s[r].w : 1;
-    kb[r] = s[r].ok ? kd + 1 : 0;
-    ke[r] = s[r].ok ? s[r].w : 0;
+    if constexpr (std::is_same<TI, SOff>::value) {
+      // slice-offset format: every row's diagonal at the common position
+      lo[r] = kb[r] = A.dell_kd + 1;
+      hi[r] = ke[r] = A.dell_w;
+    } else {
+      const int64_t slice = gw * KR + r;
+      const int kd = s[r].ok ? (A.dell_w ? A.dell_kd : (int)A.kd[s[r].row]) : 0;
+      // loop from just after the slice's smallest diagonal position
+      lo[r] = s[r].ok ? (A.dell_w ? A.dell_kd : (int)(A.kdr[slice] & 0xffffu)) + 1 : 0;
+      hi[r] = s[r].ok ? s[r].w : 1;
+      kb[r] = s[r].ok ? kd + 1 : 0;
+      ke[r] = s[r].ok ? s[r].w : 0;
+    }
     traw[r] = t[s[r].row];
     epi.prefetch(r, s[r].row);
   }
@@ -1017,7 +1029,7 @@ __global__ __launch_bounds__(kBlock) void k_mg(SellDesc A, const TM* __restrict_
   rows_sum<U, TI>(mv, (const TI*)A.idx, s, lo, hi, kb, ke, acc, LdVec<TT, Q>{t}, neg != 0,
                   [&](Q (&a)[KR]) {
 #pragma unroll
-                    for (int r = 0; r < KR; r++) a[r] = gd * value_barrier(widen<Q>(traw[r]));
+                    for (int r = 0; r < KR; r++) a[r] = gd * widen<Q>(value_barrier(traw[r]));
                   });
 #pragma unroll
   for (int r = 0; r < KR; r++)
