@@ -145,11 +145,12 @@ typedef struct {
   int32_t rows_per_lane;         /* shape of the M sweeps and of the Richardson
                                     residual: 0 = picked from the row lengths
                                     (two rows per lane for at most four
-                                    entries on a side of the diagonal, else
-                                    one); -1 = picked by timing the candidate
-                                    shapes at set-up; 1, 2 or 4 = that many
-                                    rows per lane.  Results do not depend
-                                    on it. */
+                                    entries on a side of the diagonal, four
+                                    with narrow vectors in the slice-offset
+                                    layout, else one); -1 = picked by timing
+                                    the candidate shapes at set-up; 1, 2 or
+                                    4 = that many rows per lane.  Results do
+                                    not depend on it. */
   int32_t entry_chunk;           /* with rows_per_lane != 0: entries per load
                                     chunk (0 = 8, 4, 4 for 1, 2, 4 rows; 3 is
                                     allowed with 2 or 4 rows and narrow vectors,
