@@ -200,6 +200,7 @@ __device__ __forceinline__ void rows_sum_slice(const TV* __restrict__ val, const
 #pragma unroll
       for (int u = 0; u < U; u++) xr[r][u] = x.raw_b(xrow[r] + (uint32_t)d[r][u] * XF::kBytes);
     }
+    if (i0 == 0) x.pin();
     Q xv[KR][U];
 #pragma unroll
     for (int r = 0; r < KR; r++) {
@@ -356,16 +357,17 @@ template <class TT, class Q> struct LdVec {
   __device__ __forceinline__ void init() {}
   __device__ __forceinline__ void bind(int64_t n) { nb = (uint32_t)(n * kBytes); }
   __device__ __forceinline__ raw_t raw_b(uint32_t off) const { return buf_load<TT>(buf_over(p, nb), off); }
+  __device__ __forceinline__ void pin() {}
   __device__ __forceinline__ raw_t raw(int64_t c) const { return p[c]; }
   __device__ __forceinline__ Q cook(raw_t v) const { return widen<Q>(v); }
   __device__ __forceinline__ Q operator()(int64_t c) const { return widen<Q>(p[c]); }
 };
 
-// round_to<TT>(raw_c * sc) with the product rounded to Q.  The scale (a Q
-// value) is kept as the double it is stored as and the product is formed in
-// fp64 and rounded once to Q: the exact product of two fp32 values fits in
-// fp64, so this is the fp32 product, and no conversion waits for the scale
-// load before the matrix loads are issued.
+// round_to<TT>(raw_c * sc) with the product rounded to Q.  The scale is a Q
+// value (a level with vectors no wider than fp32 computes in fp32, so its
+// scales are fp32 values), kept as the double it is stored as.  For fp32
+// consumers the product is the fp32 product of the raw value and the scale
+// converted once at init; for fp64 ones it is formed in fp64.
 template <class TIN, class TT, class Q> struct LdBasis {
   using raw_t = TIN;
   // fp32 consumers (with a rounding to a narrower storage type, an fp32
@@ -387,14 +389,26 @@ template <class TIN, class TT, class Q> struct LdBasis {
     cur = sys_ptr(cur, sy, sl.dI);
   }
   __device__ __forceinline__ void init() {
-    int64_t j = cur ? vload(cur) : 0;
+    // the same index for every lane: kept wave-uniform, so the vector's
+    // address (and a buffer over it) is too
+    int64_t j = cur ? __builtin_amdgcn_readfirstlane(vload(cur)) : 0;
     p += j * stride;
     sc = vload(scp + j);
   }
+  // the scale as loaded here, after the chunk's loads: its conversion for
+  // the cooks cannot be hoisted ahead of them (and wait for the scale)
+  __device__ __forceinline__ void pin() { sc = value_barrier(sc); }
   __device__ __forceinline__ raw_t raw(int64_t c) const { return p[c]; }
   __device__ __forceinline__ Q cook(raw_t r) const {
-    const Q v = (Q)(widen<double>(r) * sc);
-    return widen<Q>(round_to<TT>(v));
+    if constexpr (std::is_same<Q, float>::value) {
+      // the exact product of two fp32 values fits in fp64, so rounding it
+      // to fp32 once is the fp32 product
+      const float v = widen<float>(r) * (float)sc;  // exact conversion: an fp32 value
+      return widen<Q>(round_to<TT>(v));
+    } else {
+      const Q v = (Q)(widen<double>(r) * sc);
+      return widen<Q>(round_to<TT>(v));
+    }
   }
   __device__ __forceinline__ Q operator()(int64_t c) const { return cook(p[c]); }
 };
@@ -424,10 +438,11 @@ template <class TT, class Q> struct LdSBasis {
     cur = sys_ptr(cur, sy, sl.dI);
   }
   __device__ __forceinline__ void init() {
-    int64_t j = cur ? vload(cur) : 0;
+    int64_t j = cur ? __builtin_amdgcn_readfirstlane(vload(cur)) : 0;
     p += j * stride;
     sc = vload(scp + j);
   }
+  __device__ __forceinline__ void pin() { sc = value_barrier(sc); }
   __device__ __forceinline__ raw_t raw(int64_t c) const { return SRaw{p[c], s[c]}; }
   __device__ __forceinline__ Q cook(raw_t r) const {
     double v = r.s * (r.v * sc);
