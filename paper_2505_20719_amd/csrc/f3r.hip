@@ -568,7 +568,7 @@ void enqueue_fgmres(Ctx& c, int d, const Basis& vin, const void* alias_raw, cons
   lb.vb = vb;
   lb.type = L.pv;
   lb.scales = L.S + L.L.scale;
-  HIPCHK(combine(c.st, h->A.sys, n, L.Z, L.zt, L.pv, L.S + L.L.y, L.I + I_MEFF, out.ptr, out.s,
+  HIPCHK(combine(c.st, h->A.sys, n, L.Z, L.zt, L.pv, L.S + L.L.y, L.I + I_MEFF, m, out.ptr, out.s,
                  out.cur, 0, &lb, L.I + I_FB, out.fb, pstop));
 }
 
@@ -1029,8 +1029,8 @@ f3r_status outer_solve(f3r_handle* h, const double* b, double* x, double tol, in
     lb.vb = vec_at(L0.V, T64, 1, n);
     lb.type = T64;
     lb.scales = L0.S + L0.L.scale;
-    HIPCHK(combine(h->st, sl, n, L0.Z, T64, T64, L0.S + L0.L.y, L0.I + I_MEFF, x, nullptr, nullptr, 1,
-                   &lb, L0.I + I_FB, nullptr, L0.I + I_HOLD));
+    HIPCHK(combine(h->st, sl, n, L0.Z, T64, T64, L0.S + L0.L.y, L0.I + I_MEFF, L0.cfg.m, x, nullptr,
+                   nullptr, 1, &lb, L0.I + I_FB, nullptr, L0.I + I_HOLD));
     HIPCHK(residual64(h->st, h->A, h->a64, x, b, (double*)L0.V, h->partials));
     HIPCHK(residual_finalize(h->st, sl, h->partials, nb, L0.S, L0.I, L0.L, h->ibn, h->hpin));
     HIPCHK(hipStreamSynchronize(h->st));

@@ -189,9 +189,10 @@ struct LevelBasis {
 // in fp64; with accumulate: out_i += u_i; otherwise out_i = u_i (type tv).
 // When `cur` is set the output vector is out + (*cur) n.  fb: per-column
 // flags; a flagged column uses the basis vector V_j instead of Z_j.
-// Rows of systems whose pstop flag is set are left alone.
+// Rows of systems whose pstop flag is set are left alone.  m: the level's
+// restart length (Z holds m columns, y m entries; meff <= m).
 hipError_t combine(hipStream_t st, const SysLayout& sl, int64_t n, const void* Z, int tz,
-                   int tv, const double* y, const int* meff, void* out, const double* s,
+                   int tv, const double* y, const int* meff, int m, void* out, const double* s,
                    const int* cur, int accumulate, const LevelBasis* alt,
                    const int* fb, int* out_fb, const int* pstop);
 

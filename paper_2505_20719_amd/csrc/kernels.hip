@@ -604,69 +604,96 @@ hipError_t backsolve(hipStream_t st, const SysLayout& sl, int q, double* S, int*
 // ---------------------------------------------------------------------------
 // level output: sum_j y_j z_j
 // ---------------------------------------------------------------------------
+// A level with at most kCombineAll directions loads every column Z_j
+// without waiting for meff (columns past meff are masked; they lie inside
+// Z); a longer one (the outermost level) loops to meff.
+constexpr int kCombineAll = 8;
+
 template <class TZ, class TV, class Q>
 __global__ __launch_bounds__(kBlock) void k_combine(SysLayout sl, int64_t n, const TZ* __restrict__ Z,
-                                                    const double* y, const int* meffp,
+                                                    const double* y, const int* meffp, int m,
                                                     void* out, const double* s, const int* cur,
                                                     int accumulate, LdLevelBasis<TV, Q> alt,
                                                     const int* fb, int* out_fb, const int* pstop,
                                                     int64_t nb) {
-  __shared__ Q ys[kMaxM];
-  __shared__ int fbs[kMaxM];
   const int64_t lb = logical_block(nb);
   if (lb >= nb) return;
   const int sy = sys_of(sl, lb * kRowsPerBlock);
   pstop = sys_ptr(pstop, sy, sl.dI);
-  if (pstop && *pstop) return;
+  if (sl.blk && pstop && *pstop) return;
+  const int stopped = read_flag(pstop);  // checked at the stores (one system)
   y = sys_ptr(y, sy, sl.dS);
   meffp = sys_ptr(meffp, sy, sl.dI);
   cur = sys_ptr(cur, sy, sl.dI);
   fb = sys_ptr(fb, sy, sl.dI);
   out_fb = sys_ptr(out_fb, sy, sl.dI);
   alt.scales = sys_ptr(alt.scales, sy, sl.dS);
-  const int meff = *meffp;
-  for (int t = threadIdx.x; t < meff; t += kBlock) {
-    ys[t] = (Q)y[t];
-    fbs[t] = fb ? fb[t] : 0;
+  // (a stopped system's meff may be stale: kept inside [0, m])
+  const int meff = min(max(*meffp, 0), m);
+  const int jend = m <= kCombineAll ? m : meff;
+  // the thread's rows, clamped into the vector (a row past n is not stored)
+  const int64_t row0 = lb * kRowsPerBlock + threadIdx.x;
+  int64_t rowc[kR];
+#pragma unroll
+  for (int r = 0; r < kR; r++) rowc[r] = min(row0 + (int64_t)r * kBlock, n - 1);
+  // u_i = sum over j < meff of y_j Z_j,i, j ascending
+  Q acc[kR];
+#pragma unroll
+  for (int r = 0; r < kR; r++) acc[r] = 0;
+  for (int j0 = 0; j0 < jend; j0 += 4) {
+    Q zz[4][kR];
+#pragma unroll
+    for (int u = 0; u < 4; u++) {
+      const TZ* zj = Z + (int64_t)min(j0 + u, jend - 1) * n;
+#pragma unroll
+      for (int r = 0; r < kR; r++) zz[u][r] = widen<Q>(zj[rowc[r]]);
+    }
+#pragma unroll
+    for (int u = 0; u < 4; u++) {
+      const int j = j0 + u;
+      const Q yj = (Q)y[min(j, m - 1)];
+#pragma unroll
+      for (int r = 0; r < kR; r++) {
+        const Q t = acc[r] + yj * zz[u][r];
+        acc[r] = j < meff ? t : acc[r];
+      }
+    }
   }
-  __syncthreads();
   int anyfb = 0;
-  for (int j = 0; j < meff; j++) anyfb |= fbs[j];
+  if (fb)
+    for (int j = 0; j < meff; j++) anyfb |= fb[j];
+  if (anyfb) {
+    // rare: flagged columns use the basis vector V_j instead of Z_j
+#pragma unroll
+    for (int r = 0; r < kR; r++) acc[r] = 0;
+    for (int j = 0; j < meff; j++) {
+      const Q yj = (Q)y[j];
+      const int f = fb[j];
+#pragma unroll
+      for (int r = 0; r < kR; r++) {
+        const Q zv = f ? alt.get(j, rowc[r]) : widen<Q>(Z[(int64_t)j * n + rowc[r]]);
+        acc[r] = acc[r] + yj * zv;
+      }
+    }
+  }
+  if (stopped) return;
   const int ci = cur ? *cur : 0;
   const int64_t o = (int64_t)ci * n;
 #pragma unroll
   for (int r = 0; r < kR; r++) {
-    const int64_t row = lb * kRowsPerBlock + (int64_t)r * kBlock + threadIdx.x;
+    const int64_t row = row0 + (int64_t)r * kBlock;
     if (row >= n) continue;
-    Q acc = 0;
-    if (!anyfb) {
-      for (int j0 = 0; j0 < meff; j0 += 8) {
-        Q zz[8];
-#pragma unroll
-        for (int u = 0; u < 8; u++) zz[u] = widen<Q>(Z[(int64_t)min(j0 + u, meff - 1) * n + row]);
-#pragma unroll
-        for (int u = 0; u < 8; u++) {
-          const Q t = acc + ys[min(j0 + u, meff - 1)] * zz[u];
-          acc = (j0 + u < meff) ? t : acc;
-        }
-      }
-    } else {
-      for (int j = 0; j < meff; j++) {
-        const Q zv = fbs[j] ? alt.get(j, row) : widen<Q>(Z[(int64_t)j * n + row]);
-        acc = acc + ys[j] * zv;
-      }
-    }
     bool fin;
     if (s) {
       // consumer on the unscaled outermost system: z = s_i u_i in fp64
-      const double v = s[row] * widen<double>(round_to<TV>(acc));
+      const double v = s[row] * widen<double>(round_to<TV>(acc[r]));
       double* od = (double*)out + o;
       const double rv = accumulate ? od[row] + v : v;
       od[row] = rv;
       fin = isfinite(rv);
     } else {
       TV* ov = (TV*)out + o;
-      const TV rv = accumulate ? round_to<TV>(widen<Q>(ov[row]) + acc) : round_to<TV>(acc);
+      const TV rv = accumulate ? round_to<TV>(widen<Q>(ov[row]) + acc[r]) : round_to<TV>(acc[r]);
       ov[row] = rv;
       fin = finite_val(rv);
     }
@@ -675,9 +702,10 @@ __global__ __launch_bounds__(kBlock) void k_combine(SysLayout sl, int64_t n, con
 }
 
 hipError_t combine(hipStream_t st, const SysLayout& sl, int64_t n, const void* Z, int tz, int tv,
-                   const double* y, const int* meff, void* out, const double* s, const int* cur,
-                   int accumulate, const LevelBasis* alt, const int* fb, int* out_fb,
-                   const int* pstop) {
+                   const double* y, const int* meff, int m, void* out, const double* s,
+                   const int* cur, int accumulate, const LevelBasis* alt, const int* fb,
+                   int* out_fb, const int* pstop) {
+  if (m < 1) return hipErrorInvalidValue;
   const int64_t nb = n_blocks(n);
   return with_type(tz, [&](auto pz) {
     using TZ = TYPE_OF(pz);
@@ -693,7 +721,7 @@ hipError_t combine(hipStream_t st, const SysLayout& sl, int64_t n, const void* Z
         ld.n = n;
       }
       hipLaunchKernelGGL((k_combine<TZ, TV, Q>), grid_for(n), dim3(kBlock), 0, st, sl, n,
-                         (const TZ*)Z, y, meff, out, s, cur, accumulate, ld, alt ? fb : nullptr,
+                         (const TZ*)Z, y, meff, m, out, s, cur, accumulate, ld, alt ? fb : nullptr,
                          out_fb, pstop, nb);
       return hipGetLastError();
     });
