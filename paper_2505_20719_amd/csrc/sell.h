@@ -174,8 +174,8 @@ __device__ __forceinline__ void rows_sum_slice(const TV* __restrict__ val, const
     uke[r] = __builtin_amdgcn_readfirstlane(ke[r]);
     // slice x width: the table row, and the value row of position 0
     const uint32_t sb = (uint32_t)__builtin_amdgcn_readfirstlane((int)(s[r].e0 >> 6));
-    // from the first position of the range on, so a chunk's positions are
-    // constant offsets
+    // from the first position of the range on; a chunk reads at a uniform
+    // base plus constant position offsets
     vrow[r] = val + ((size_t)sb + (size_t)ulo[r]) * kWave;
     trow[r] = (const int32_t*)idx + sb + ulo[r];
     xrow[r] = (uint32_t)s[r].row * XF::kBytes;
@@ -190,8 +190,8 @@ __device__ __forceinline__ void rows_sum_slice(const TV* __restrict__ val, const
     for (int r = 0; r < KR; r++) {
 #pragma unroll
       for (int u = 0; u < U; u++) {
-        v[r][u] = vrow[r][(uint32_t)(i0 + u) * kWave + lane];
-        d[r][u] = trow[r][i0 + u];
+        v[r][u] = (vrow[r] + (uint32_t)i0 * kWave)[u * kWave + lane];
+        d[r][u] = (trow[r] + i0)[u];
       }
     }
     typename XF::raw_t xr[KR][U];
