@@ -148,9 +148,9 @@ template <> __device__ __forceinline__ double buf_load<double>(__amdgpu_buffer_r
 // the element size.  A column outside the vector reads zero (the entry's
 // value is zero there: the row has no such entry).  The positions of a chunk
 // are not clamped to the slice's range (the arrays are padded; the sums
-// mask them).  The ranges are the first lane's: every row of a slice that
-// exists has the same ones, and a missing row's sums are left as they were
-// before the first entry, as with the per-row ranges.
+// mask them).  The ranges are the first lane's of the first slice: every
+// existing row has the same ones in this format, and a missing row's sums
+// are left as they were before the first entry, as with per-row ranges.
 template <int U, bool NEG, class TV, class Q, class XF, int KR, class INIT>
 __device__ __forceinline__ void rows_sum_slice(const TV* __restrict__ val, const SOff* __restrict__ idx,
                                                const RowSlot (&s)[KR], const int (&lo)[KR],
@@ -161,25 +161,26 @@ __device__ __forceinline__ void rows_sum_slice(const TV* __restrict__ val, const
   XF x = x0;
   x.bind(s[0].n);
   const uint32_t lane = threadIdx.x & (kWave - 1);
-  int ulo[KR], ukb[KR], uke[KR];
+  // One set of ranges for all the lane's slices: they follow from the
+  // format's common widths, the same for every slice (the first slice's are
+  // taken; a missing slice, which can only follow it, keeps its sums as
+  // they were and is never stored).
+  const int ulo = __builtin_amdgcn_readfirstlane(lo[0]);
+  const int ukb = __builtin_amdgcn_readfirstlane(kb[0]);
+  const int uke = __builtin_amdgcn_readfirstlane(ke[0]);
+  const int it = __builtin_amdgcn_readfirstlane(hi[0]) - ulo;
   const TV* vrow[KR];
   const int32_t* trow[KR];
   uint32_t xrow[KR];
-  int it = 0;
 #pragma unroll
   for (int r = 0; r < KR; r++) {
-    ulo[r] = __builtin_amdgcn_readfirstlane(lo[r]);
-    const int uhi = __builtin_amdgcn_readfirstlane(hi[r]);
-    ukb[r] = __builtin_amdgcn_readfirstlane(kb[r]);
-    uke[r] = __builtin_amdgcn_readfirstlane(ke[r]);
     // slice x width: the table row, and the value row of position 0
     const uint32_t sb = (uint32_t)__builtin_amdgcn_readfirstlane((int)(s[r].e0 >> 6));
     // from the first position of the range on; a chunk reads at a uniform
     // base plus constant position offsets
-    vrow[r] = val + ((size_t)sb + (size_t)ulo[r]) * kWave;
-    trow[r] = (const int32_t*)idx + sb + ulo[r];
+    vrow[r] = val + ((size_t)sb + (size_t)ulo) * kWave;
+    trow[r] = (const int32_t*)idx + sb + ulo;
     xrow[r] = (uint32_t)s[r].row * XF::kBytes;
-    it = max(it, uhi - ulo[r]);
   }
   Q a0[KR];
   int i0 = 0;
@@ -218,14 +219,16 @@ __device__ __forceinline__ void rows_sum_slice(const TV* __restrict__ val, const
 #pragma unroll
       for (int r = 0; r < KR; r++) a0[r] = acc[r];
     }
+    bool in[U];
+#pragma unroll
+    for (int u = 0; u < U; u++) in[u] = ulo + i0 + u >= ukb && ulo + i0 + u < uke;
 #pragma unroll
     for (int r = 0; r < KR; r++) {
 #pragma unroll
       for (int u = 0; u < U; u++) {
-        const int k = ulo[r] + i0 + u;
         const Q m = NEG ? -widen<Q>(v[r][u]) : widen<Q>(v[r][u]);
         const Q t = acc[r] + m * xv[r][u];
-        acc[r] = (k >= ukb[r] && k < uke[r]) ? t : acc[r];
+        acc[r] = in[u] ? t : acc[r];
       }
     }
     i0 += U;
