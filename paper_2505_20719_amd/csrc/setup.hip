@@ -438,9 +438,9 @@ f3r_status build_matrix(hipStream_t st, const f3r_csr* A, const f3r_params* p, c
   HIPCHK(hipMemcpyAsync(offd, off.data(), (size_t)(ns + 1) * 4, hipMemcpyHostToDevice, st));
   SellOut so;
   int32_t* stab = nullptr;
-  // value arrays: the slice-offset sums read up to kSlicePad positions past
-  // the last slice (zeros, never summed)
-  const size_t vcount = (size_t)acc + (slice ? (size_t)kSlicePad * 64 : 0);
+  // value and index arrays: the row sums read up to kSlicePad positions
+  // past the last slice (zeros, never summed)
+  const size_t vcount = (size_t)acc + (size_t)kSlicePad * 64;
   if (slice) {
     stab = (int32_t*)al.get(((size_t)ns * sw + kSlicePad) * 4);
     HIPCHK(hipMemsetAsync(stab + (size_t)ns * sw, 0, kSlicePad * 4, st));
@@ -450,7 +450,9 @@ f3r_status build_matrix(hipStream_t st, const f3r_csr* A, const f3r_params* p, c
     so.idx = nullptr;
   } else {
     so.idx16 = (hflags & SF_IDX32) ? 0 : 1;
-    so.idx = al.get((size_t)acc * (so.idx16 ? 2 : 4));
+    so.idx = al.get(vcount * (so.idx16 ? 2 : 4));
+    HIPCHK(hipMemsetAsync((char*)so.idx + (size_t)acc * (so.idx16 ? 2 : 4), 0,
+                          (size_t)kSlicePad * 64 * (so.idx16 ? 2 : 4), st));
   }
   if (uni) al.release(uni);
   if (lucd) al.release(lucd);
@@ -476,7 +478,7 @@ f3r_status build_matrix(hipStream_t st, const f3r_csr* A, const f3r_params* p, c
   }
   for (int t = 0; t < 4; t++)
     if (need[t]) so.ah[t] = al.get(vcount * type_size(t));
-  if (slice) {
+  {
     const size_t tail = (size_t)kSlicePad * 64;
     HIPCHK(hipMemsetAsync(so.a64 + acc, 0, tail * 8, st));
     for (int t = 0; t < 4; t++) {
