@@ -596,9 +596,11 @@ def main():
                 "bytes_per_launch": int(ab[dom]), "avg_launch_us": round(kern[dom]["avg_us"], 3),
                 "bytes_model": "device format: stored values and per-slice offsets read once, "
                                "vectors read and written once",
+                # the same launch priced as a CSR kernel with 4-byte indices
+                # and row pointers; an effective rate, not a fraction of
+                # the peak (this format does not move those bytes)
                 "effective_csr_model": {"bytes_per_launch": int(sb[dom]),
-                                        "achieved": round(kern[dom]["gbs"], 1),
-                                        "frac": round(kern[dom]["gbs"] / HBM_PEAK_GBS, 4)}}
+                                        "achieved": round(kern[dom]["gbs"], 1)}}
     result_cfg["kernels"] = {k: {kk: round(vv, 3) if isinstance(vv, float) else vv for kk, vv in v.items()}
                              for k, v in kern.items()}
     # standalone level SpMVs, warm (back to back) and cold (a 1 GiB buffer
