@@ -169,6 +169,12 @@ __device__ __forceinline__ void rows_sum_slice(const TV* __restrict__ val, const
   const int ukb = __builtin_amdgcn_readfirstlane(kb[0]);
   const int uke = __builtin_amdgcn_readfirstlane(ke[0]);
   const int it = __builtin_amdgcn_readfirstlane(hi[0]) - ulo;
+  // fp64 sums read a chunk's positions past the range as the range's last
+  // one (cached), not the next positions: with 8-byte values the unsummed
+  // reads of chunks of eight over 13 entries cost more than the clamp
+  // (fp64-F3R on the 27-point matrices); narrower sums read them unclamped
+  constexpr bool kClampChunk = std::is_same<Q, double>::value;
+  const int last = max(it - 1, 0);
   const TV* vrow[KR];
   const int32_t* trow[KR];
   uint32_t xrow[KR];
@@ -191,8 +197,14 @@ __device__ __forceinline__ void rows_sum_slice(const TV* __restrict__ val, const
     for (int r = 0; r < KR; r++) {
 #pragma unroll
       for (int u = 0; u < U; u++) {
-        v[r][u] = (vrow[r] + (uint32_t)i0 * kWave)[u * kWave + lane];
-        d[r][u] = (trow[r] + i0)[u];
+        if constexpr (kClampChunk) {
+          const int kk = min(i0 + u, last);
+          v[r][u] = (vrow[r] + (uint32_t)kk * kWave)[lane];
+          d[r][u] = trow[r][kk];
+        } else {
+          v[r][u] = (vrow[r] + (uint32_t)i0 * kWave)[u * kWave + lane];
+          d[r][u] = (trow[r] + i0)[u];
+        }
       }
     }
     typename XF::raw_t xr[KR][U];
