@@ -177,6 +177,32 @@ template <class Q> __device__ __forceinline__ Q thread_sum(const Q* __restrict__
   return s;
 }
 
+// thread_sum of four series at once, p + l stride for l = l0 .. l0 + 3
+// (past nv - 1 the last one is read again and its sums are unused): each
+// sum adds the thread's terms in index order, as thread_sum does, with the
+// loads of four terms of every series in flight together
+template <class Q>
+__device__ __forceinline__ void thread_sums4(const Q* __restrict__ p, int64_t stride, int l0, int nv,
+                                             int64_t cnt, Q (&s)[4]) {
+  const int nt = kFinBlock;
+#pragma unroll
+  for (int u = 0; u < 4; u++) s[u] = 0;
+  for (int64_t i = threadIdx.x; i < cnt; i += 4 * (int64_t)nt) {
+    Q v[4][4];
+#pragma unroll
+    for (int u = 0; u < 4; u++) {
+      const Q* P = p + (int64_t)min(l0 + u, nv - 1) * stride;
+#pragma unroll
+      for (int k = 0; k < 4; k++) v[u][k] = P[min(i + (int64_t)k * nt, cnt - 1)];
+    }
+#pragma unroll
+    for (int u = 0; u < 4; u++) {
+#pragma unroll
+      for (int k = 0; k < 4; k++) s[u] = i + (int64_t)k * nt < cnt ? s[u] + v[u][k] : s[u];
+    }
+  }
+}
+
 // sum over a kFinBlock-thread block, valid in thread 0 (lds: 16 entries)
 template <class T> __device__ __forceinline__ T fin_block_sum(T v, T* lds) {
   v = wave_sum(v);

@@ -333,11 +333,18 @@ __global__ __launch_bounds__(kFinBlock) void k_axpy_norm_fin(
 #pragma unroll
     for (int r = 0; r < kFuseRowsPerThread; r++) vv[u][r] = widen<Q>(V[row[r]]);
   }
-  // the dots: per-thread sums in index order, wave sums, waves in order
-  for (int l = 0; l < nv; l++) {
-    Q sl = thread_sum(dpart + (int64_t)l * dnb, dnb);
-    sl = wave_sum(sl);
-    if (lane == 0) lds[wv][l] = sl;
+  // the dots: per-thread sums in index order (four dots' loads in flight
+  // together), wave sums, waves in order
+  for (int l0 = 0; l0 < nv; l0 += 4) {
+    Q s4[4];
+    thread_sums4(dpart, dnb, l0, nv, dnb, s4);
+#pragma unroll
+    for (int u = 0; u < 4; u++) {
+      if (l0 + u < nv) {
+        const Q sl = wave_sum(s4[u]);
+        if (lane == 0) lds[wv][l0 + u] = sl;
+      }
+    }
   }
   __syncthreads();
   if ((int)threadIdx.x < nv) {
