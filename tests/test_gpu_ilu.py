@@ -221,3 +221,28 @@ def test_sweep_variants_bit_exact(case):
         assert info.ilu_sweep == forms[variant], (case, variant, info.ilu_sweep)
         g.close()
         o.close()
+
+
+def test_ilu_setup_on_dirty_memory():
+    # set-up writes every padded position of the device format (rows past n
+    # in the last slice included), so ILU(0) set-up on a matrix with a
+    # ragged last slice reads no uninitialised value: the device memory is
+    # first filled with 0xFF bytes (NaN patterns) and returned to the driver
+    junk = torch.full((256 * 1024 * 1024,), -1, dtype=torch.int32, device="cuda")  # 1 GiB of 0xFF
+    torch.cuda.synchronize()
+    del junk
+    torch.cuda.empty_cache()
+    for name, make, blocks in (("elastic_6", MATS["elastic_6"], 3), ("poisson2d_70", lambda: W.poisson2d(70), 7)):
+        A = make()
+        assert A.n % 64 != 0
+        p = P().params_default(0)
+        p.m_kind, p.ilu_blocks = P().M_ILU, blocks
+        q = O.default_params(O.FP16_F3R)
+        q.m_kind, q.ilu_blocks = O.M_ILU, blocks
+        print(f"[case] ilu dirty memory {name} n={A.n} blocks={blocks}", flush=True)
+        g = P().Solver(A.row_ptr, A.col_idx, A.val, p)
+        o = O.Oracle(A.row_ptr, A.col_idx, A.val, q)
+        assert np.array_equal(g.debug_m_values(O.F64), o.ilu_values(True))
+        assert np.array_equal(g.debug_m_values(O.F16), o.ilu_values(False))
+        g.close()
+        o.close()
