@@ -148,7 +148,8 @@ template <> __device__ __forceinline__ double buf_load<double>(__amdgpu_buffer_r
 // the element size.  A column outside the vector reads zero (the entry's
 // value is zero there: the row has no such entry).  The positions of a chunk
 // are not clamped to the slice's range (the arrays are padded; the sums
-// mask them).  The ranges are the first lane's of the first slice: every
+// mask them), except in fp64 (below).  The ranges are the first lane's of
+// the first slice: every
 // existing row has the same ones in this format, and a missing row's sums
 // are left as they were before the first entry, as with per-row ranges.
 template <int U, bool NEG, class TV, class Q, class XF, int KR, class INIT>
@@ -251,10 +252,10 @@ __device__ __forceinline__ void rows_sum_slice(const TV* __restrict__ val, const
 
 // Row sums in SELL-64 and the diagonal-aligned format (16-bit offsets from
 // the row or 32-bit columns per entry; the same sums as rows_sum below, in
-// the same order), for fp32 arithmetic.  A slice's entries of position k are 64 consecutive
-// elements at a wave-uniform address, so values and indices load at a
-// uniform base plus the lane; the gather is the loader's range-checked load
-// at byte offset column x element size.  Positions past a slice's width are
+// the same order), for fp32 arithmetic.  A slice's entries of position k
+// are 64 consecutive elements at a wave-uniform address, so values and
+// indices load at a uniform base plus the lane; the gather is the loader's
+// range-checked load at byte offset column x element size.  Positions past a slice's width are
 // read unclamped (the next slice's entries, or the zero padding after the
 // last slice) and masked by the rows' own ranges, which also mask every
 // position of a missing row.
