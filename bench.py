@@ -623,6 +623,19 @@ def main():
                      "cold_us": round(cold * 1e3, 3), "cold_gbs": round(nbytes / (cold * 1e-3) / 1e9, 1)}
         log(f"[bench] standalone SpMV {key}: {nbytes / 1e6:.1f} MB, warm {warm * 1e3:.2f} us "
             f"({spmv[key]['warm_gbs']:.0f} GB/s), cold {cold * 1e3:.2f} us ({spmv[key]['cold_gbs']:.0f} GB/s)")
+    # what a plain read of the same 1 GiB buffer reaches (contiguous ranges
+    # per workgroup, non-temporal 16-byte loads): the cold rates as a
+    # fraction of it
+    read_ms = s16.time_read(scrub, reps=10)
+    rbytes = scrub.numel() * scrub.element_size()
+    read_gbs = rbytes / (read_ms * 1e-3) / 1e9
+    for key in spmv:
+        spmv[key]["cold_frac_of_read"] = round(spmv[key]["cold_gbs"] / read_gbs, 3)
+    result_cfg["read_reference"] = {"bytes": int(rbytes), "us": round(read_ms * 1e3, 3),
+                                    "gbs": round(read_gbs, 1),
+                                    "kernel": "k_read_ref: one contiguous range per workgroup, "
+                                              "16-byte non-temporal loads"}
+    log(f"[bench] read reference: {rbytes / 2**30:.0f} GiB in {read_ms * 1e3:.1f} us ({read_gbs:.0f} GB/s)")
     del scrub
     result_cfg["spmv_standalone"] = spmv
 

@@ -373,6 +373,17 @@ f3r_status f3r_apply_m_static(f3r_handle* h, int32_t prec, const double* r, doub
 f3r_status f3r_time_spmv(f3r_handle* h, int32_t level, int32_t reps, void* scrub,
                          int64_t scrub_bytes, double* avg_ms);
 
+/* The reference that the SpMV rates above are read against (Sec. 5.2 counts
+   the sliced-ELLPACK SpMV as bandwidth-bound): `reps` plain reads of the
+   first bytes / 16 x 16 bytes of the device buffer `buf` (caller-owned,
+   16-byte aligned, zero-filled by the caller, not written), each workgroup
+   reading one contiguous range with 16-byte non-temporal loads, each read
+   bracketed by its own pair of HIP events on the handle's stream.
+   *avg_ms = mean time of one read.  F3R_ERR_ARG for a null or unaligned
+   buffer, bytes < 16 or reps outside [1, 10000]. */
+f3r_status f3r_time_read(f3r_handle* h, const void* buf, int64_t bytes, int32_t reps,
+                         double* avg_ms);
+
 /* y = M r with vectors stored in prec (the two-SpMV application of
    Sec. 5.2; fp32 arithmetic for narrow prec, fp64 for fp64). prec must be
    the precision of M or wider. */

@@ -87,6 +87,7 @@ EXPORTS = {
                                      C.c_double, C.c_int32, C.POINTER(Info)]),
     "f3r_time_spmv": (C.c_int32, [C.c_void_p, C.c_int32, C.c_int32, C.c_void_p, C.c_int64,
                                   C.POINTER(C.c_double)]),
+    "f3r_time_read": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_int64, C.c_int32, C.POINTER(C.c_double)]),
     "f3r_get_history": (C.c_int32, [C.c_void_p, C.c_int32, C.c_void_p, C.c_int64,
                                     C.POINTER(C.c_int64)]),
     "f3r_get_weights": (C.c_int32, [C.c_void_p, C.c_int32, C.c_void_p, C.POINTER(C.c_int64)]),
@@ -231,6 +232,15 @@ class Solver:
         ptr = C.c_void_p(scrub.data_ptr()) if scrub is not None else None
         nb = scrub.numel() * scrub.element_size() if scrub is not None else 0
         self._check(self.L.f3r_time_spmv(self.h, level, reps, ptr, nb, C.byref(ms)), "time_spmv")
+        return ms.value
+
+    def time_read(self, buf, reps=10):
+        """Mean time (ms) of one read of the zero-filled device tensor `buf`
+        by the library's read-bandwidth reference kernel."""
+        ms = C.c_double()
+        nb = buf.numel() * buf.element_size()
+        self._check(self.L.f3r_time_read(self.h, C.c_void_p(buf.data_ptr()), nb, reps, C.byref(ms)),
+                    "time_read")
         return ms.value
 
     def history(self, level=0):

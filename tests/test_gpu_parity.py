@@ -548,6 +548,17 @@ def test_time_spmv_entry():
     for level, reps in ((3, 1), (4, 1), (-1, 1), (0, 0)):
         with pytest.raises(PP.F3RError):
             g.time_spmv(level, reps=reps)
+    # the read reference: positive times; a buffer under 16 bytes, an
+    # unaligned one or a bad count is rejected before any launch
+    print("[case] time_read", flush=True)
+    scrub.zero_()
+    assert g.time_read(scrub, reps=3) > 0.0
+    raw = torch.zeros(64, dtype=torch.uint8, device="cuda")
+    for buf, reps in ((raw[:8], 1), (raw[1:33], 1), (raw[:32], 0), (raw[:32], 10001)):
+        with pytest.raises(PP.F3RError):
+            g.time_read(buf, reps=reps)
+    x3, i3 = g.solve(bt)
+    assert torch.equal(x1, x3) and i1.outer_iters == i3.outer_iters
     g.close()
 
 
