@@ -194,7 +194,10 @@ typedef struct {
                              made 4 times in a row between one event pair) */
   int64_t padded_nnz;    /* stored entries of the device format incl. padding */
   int32_t rows_per_lane[3]; /* shapes in use: W sweep, G sweep, Richardson residual */
-  int32_t entry_chunk[3];   /* entries per load chunk of the same three sweeps */
+  int32_t entry_chunk[3];   /* entries per load chunk of the same three sweeps
+                               (the residual's rule also picks 7, one chunk
+                               over rows of seven entries, for narrow vectors
+                               in the slice-offset layout) */
   double tune_ms;        /* set-up time spent timing the candidate shapes */
   int32_t layout;        /* F3R_LAYOUT_SELL, _DIAG or _SLICE: format in use */
   int32_t ilu_sweep;     /* F3R_M_ILU: forms of the triangular sweeps launched

@@ -612,8 +612,10 @@ void autotune(f3r_handle* h) {
     // longer than the side reads values it does not sum, so chunks of three
     // serve three entries in every precision there; with its short per-entry
     // code, narrow vectors there take four rows per lane, one round of waves
-    // over the chip, and the residual chunks of four: measured on the 128^3
-    // Poisson matrix, 12.8 against 13.2 ms a solve)
+    // over the chip, and the residual chunks of four, or one chunk of seven
+    // over rows of seven entries: measured on the 128^3 Poisson matrix, 12.8
+    // against 13.2 ms a solve, then 12.15 against 12.3 ms for the chunk of
+    // seven)
     const bool slice = h->A.idx16 == 2;
     const bool four = slice && narrow;
     auto pick = [&](int side) {
@@ -622,7 +624,7 @@ void autotune(f3r_handle* h) {
     };
     h->kr[0] = pick(lower);
     h->kr[1] = pick(upper);
-    h->kr[2] = four && h->A.dell_w <= 8 ? 44 : 18;
+    h->kr[2] = !four ? 18 : h->A.dell_w == 7 ? 47 : h->A.dell_w <= 8 ? 44 : 18;
     return;
   }
   const double t0 = now_ms();

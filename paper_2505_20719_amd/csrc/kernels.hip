@@ -25,18 +25,24 @@ static_assert(kRowsPerBlock == kSysAlign, "systems are aligned to reduction bloc
 // do not depend on it), coded as 10 KR + U: KR rows per lane, entries in
 // chunks of U.  Chunks of 3 (7-point stencils have 3 entries on each side of
 // the diagonal) exist for narrow vectors, and for every vector type in the
-// slice-offset format, whose chunks read whole positions unclamped.
-template <class F> static hipError_t with_kr(int code, F&& f) {
+// slice-offset format, whose chunks read whole positions unclamped.  With
+// WHOLE (the residual, which sums whole rows): also chunks of 7, one pass
+// over the rows of a 7-point stencil, for narrow vectors in that format.
+template <bool WHOLE = false, class F> static hipError_t with_kr(int code, F&& f) {
   switch (code) {
     case 18: return f(std::integral_constant<int, 1>{}, std::integral_constant<int, 8>{});
     case 24: return f(std::integral_constant<int, 2>{}, std::integral_constant<int, 4>{});
     case 44: return f(std::integral_constant<int, 4>{}, std::integral_constant<int, 4>{});
     case 23: return f(std::integral_constant<int, 2>{}, std::integral_constant<int, 3>{});
     case 43: return f(std::integral_constant<int, 4>{}, std::integral_constant<int, 3>{});
+    case 47:
+      if constexpr (WHOLE) return f(std::integral_constant<int, 4>{}, std::integral_constant<int, 7>{});
+      break;
   }
   return hipErrorInvalidValue;
 }
 template <int U, class TT, class TI> constexpr bool shape_ok() {
+  if (U == 7) return sizeof(TT) == 2 && std::is_same<TI, SOff>::value;
   return U != 3 || sizeof(TT) == 2 || std::is_same<TI, SOff>::value;
 }
 
@@ -1208,7 +1214,7 @@ __global__ __launch_bounds__(kBlock) void k_rres(SellDesc A, const TA* __restric
 
 hipError_t rich_residual(hipStream_t st, const SellDesc& A, const void* av, int ta,
                          const Basis& in, const void* z, void* r, int tr, const int* stop, int kr) {
-  return with_kr(kr, [&](auto KRc, auto Uc) {
+  return with_kr<true>(kr, [&](auto KRc, auto Uc) {
   constexpr int KR = decltype(KRc)::value, U = decltype(Uc)::value;
   const int64_t nb = n_blocks_kr(A.n, KR);
   const dim3 grid((unsigned)physical_grid(nb));

@@ -481,7 +481,7 @@ def test_autotuned_shapes_change_time_not_results():
         assert info.layout == (lay if lay else PP.LAYOUT_SLICE)
         shapes = list(info.rows_per_lane)
         assert all(v in (1, 2, 4) for v in shapes)
-        assert all(c in (3, 4, 8) for c in info.entry_chunk)
+        assert all(c in (3, 4, 7, 8) for c in info.entry_chunk)
         if kr > 0:
             assert shapes == [kr] * 3 and info.tune_ms == 0.0
             if ch:
@@ -489,10 +489,11 @@ def test_autotuned_shapes_change_time_not_results():
         elif kr == 0:
             # 7-point stencil: three entries on each side of the diagonal
             # (at most, in the SELL format's mean): two rows per lane, four
-            # in the slice-offset format with its narrow vectors
+            # in the slice-offset format with its narrow vectors, where the
+            # residual reads its rows of seven in one chunk
             assert info.tune_ms == 0.0
             if info.layout == PP.LAYOUT_SLICE:
-                assert shapes == [4, 4, 4] and list(info.entry_chunk) == [3, 3, 4], shapes
+                assert shapes == [4, 4, 4] and list(info.entry_chunk) == [3, 3, 7], shapes
             else:
                 assert shapes == [2, 2, 1], shapes
         else:
