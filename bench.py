@@ -70,7 +70,7 @@ def measured_traffic(kernel: str, workload: str):
     return int(m.group(1))
 
 
-def survey_bytes(A):
+def csr_model_bytes(A):
     """Algorithmic bytes per launch by the per-unit figures of the hot-path
     scope table (CSR with 4-byte column indices and row pointers; fp16
     values and Richardson vectors, fp32 level-2 vectors; each vector read
@@ -569,7 +569,7 @@ def main():
     # on the solve's stream, direct launches)
     width = int(round(info16.padded_nnz / (((A.n + 63) // 64) * 64)))
     ab = algorithmic_bytes(A, info16.idx_bits, info16.layout, width)
-    sb = survey_bytes(A)
+    sb = csr_model_bytes(A)
     probes = {"m_lower": P.PROBE_M_LOWER, "m_upper": P.PROBE_M_UPPER,
               "r_residual": P.PROBE_R_RESIDUAL, "spmv_l2": P.PROBE_SPMV_L2}
     kern = {}
