@@ -669,13 +669,18 @@ void autotune(f3r_handle* h) {
       else
         HIPCHK(rich_residual(h->st, At, h->ah[R.pa], R.pa, basis, R.rz[0], R.rt, tr, nullptr, kr));
     };
+    // the residual also tries one chunk over rows of seven entries (narrow
+    // vectors in the slice-offset format)
+    int cf[6], nf = 0;
+    for (int c = 0; c < ncand; c++) cf[nf++] = cand[c];
+    if (f == 2 && tsz(tr) == 2 && h->A.idx16 == 2 && h->A.dell_w == 7) cf[nf++] = 47;
     // three interleaved rounds; each candidate keeps its best round
-    float best[5] = {0.f, 0.f, 0.f, 0.f, 0.f};
-    for (int c = 0; c < ncand; c++) launch(cand[c]);
+    float best[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+    for (int c = 0; c < nf; c++) launch(cf[c]);
     for (int round = 0; round < 3; round++) {
-      for (int c = 0; c < ncand; c++) {
+      for (int c = 0; c < nf; c++) {
         HIPCHK(hipEventRecord(e0, h->st));
-        for (int i = 0; i < 4; i++) launch(cand[c]);
+        for (int i = 0; i < 4; i++) launch(cf[c]);
         HIPCHK(hipEventRecord(e1, h->st));
         HIPCHK(hipEventSynchronize(e1));
         float ms = 0.f;
@@ -684,9 +689,9 @@ void autotune(f3r_handle* h) {
       }
     }
     int bc = 0;
-    for (int c = 1; c < ncand; c++)
+    for (int c = 1; c < nf; c++)
       if (best[c] < best[bc]) bc = c;
-    h->kr[f] = cand[bc];
+    h->kr[f] = cf[bc];
   }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
